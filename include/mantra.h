@@ -1,0 +1,180 @@
+/*
+ * mantra.h -- C ABI of the MI355X temporal-betweenness hot path.
+ *
+ * The library estimates the temporal betweenness centrality of nodes and
+ * temporal edges of a directed temporal graph by sampling ordered node pairs
+ * (the "ob" estimator of Section 4.1 of the MANTRA paper, arXiv 2304.08356),
+ * and stops the sampling with the c-MCERA supremum-deviation bound of
+ * Theorem 1 inside the progressive schedule of Algorithm 1.
+ *
+ * Conventions
+ *  - Every call returns a mantra_status (0 = OK, < 0 = error); nothing is
+ *    thrown across the ABI.  mantra_last_error() gives a thread-local text.
+ *  - Pointers in these signatures are HOST pointers unless stated otherwise.
+ *    The library allocates and owns all device memory; the caller owns every
+ *    buffer it passes in, and the library copies what it needs before the call
+ *    returns (mantra_submit: buffers named in the request must stay valid until
+ *    mantra_poll reports the ticket finished).
+ *  - Node ids are 0..n-1; a temporal edge is (src, dst, t) with src != dst and
+ *    t >= 0.  The edge set is a set (Preliminaries: duplicates are merged).
+ *  - Optimalities (Definition 1; fm is an extension, see mantra_opt) are
+ *    counted over strict temporal walks: consecutive edges have strictly
+ *    increasing times, and the source starts before every edge.
+ *  - Path counts are exact uint64; a count that reaches 2^64-1 is saturated and
+ *    reported (MANTRA_REC_OVERFLOW / MANTRA_E_OVERFLOW), never rounded.
+ *  - Time windows [t0, t1] are inclusive; the node set and the n(n-1)
+ *    normalisation are those of the whole graph.
+ */
+#ifndef MANTRA_H
+#define MANTRA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Temporal path optimality (Definition 1).
+ *  SH  : fewest hops.
+ *  SFM : earliest arrival first, then fewest hops among those.
+ *  PFM : every prefix ending at v_i arrives at the earliest arrival at v_i.
+ *  FM  : every walk arriving at the earliest arrival (walks, visits counted
+ *        with multiplicity: counting foremost simple paths is #P-hard, see the
+ *        Preliminaries).  f(v) may exceed 1, so Theorems 1 and 3 do not cover
+ *        it: results carry MANTRA_RES_NO_GUARANTEE. */
+typedef enum { MANTRA_SH = 0, MANTRA_FM = 1, MANTRA_SFM = 2, MANTRA_PFM = 3 } mantra_opt;
+
+typedef enum {
+    MANTRA_OK = 0,
+    MANTRA_PENDING = 1,       /* mantra_poll: not finished yet */
+    MANTRA_E_INVALID = -1,    /* bad argument (message says which) */
+    MANTRA_E_NODEV = -2,      /* no usable gfx950 device */
+    MANTRA_E_OOM = -3,        /* device allocation failed */
+    MANTRA_E_OVERFLOW = -4,   /* a sampled pair's count saturated at 2^64-1 */
+    MANTRA_E_TOO_LARGE = -5,  /* the request can never fit the memory budget */
+    MANTRA_E_INTERNAL = -6,   /* HIP runtime error or broken invariant */
+    MANTRA_E_LIMIT = -7       /* a hop count above 65534 */
+} mantra_status;
+
+typedef struct mantra_graph mantra_graph; /* opaque, device resident */
+
+/* Per-pair record (bit-exact against the oracle). */
+typedef struct {
+    int32_t reachable; /* 1 if an optimal walk s -> z exists in the window */
+    int32_t t_arr;     /* earliest arrival time among the optimal walks, -1 */
+    int32_t hops;      /* fewest hops among the optimal walks, -1 */
+    int32_t flags;     /* MANTRA_REC_* */
+    uint64_t sigma;    /* number of optimal walks (saturated at 2^64-1) */
+} mantra_pair_record;
+
+#define MANTRA_REC_OVERFLOW 1u   /* sigma (or an fm visit count) saturated */
+#define MANTRA_REC_HOPS_LIMIT 4u /* a hop count would exceed 65534 */
+
+/* Build a device-resident graph from m edges (src[i], dst[i], t[i]).
+ * Rejects ids outside [0, n), self-loops and negative times
+ * (MANTRA_E_INVALID); merges exact duplicate triples (counted in
+ * mantra_graph_info).  The arrays are copied; the caller keeps them. */
+int mantra_graph_create(const int32_t *src, const int32_t *dst, const int32_t *t, int64_t m,
+                        int32_t n, uint32_t flags, mantra_graph **out);
+
+/* G independent graphs in one device graph (packed CSR segments).  Graph g
+ * has node_count[g] nodes and edges [edge_off[g], edge_off[g+1]) of the
+ * arrays, with node ids local to the graph.  Pairs of graph g are sampled
+ * among its own nodes; sums are kept per graph. */
+int mantra_graph_create_packed(int32_t G, const int32_t *node_count, const int64_t *edge_off,
+                               const int32_t *src, const int32_t *dst, const int32_t *t,
+                               uint32_t flags, mantra_graph **out);
+
+void mantra_graph_destroy(mantra_graph *g);
+
+/* n, unique edge count, merged duplicates, time span, number of packed graphs */
+int mantra_graph_info(const mantra_graph *g, int32_t *n, int64_t *m_unique, int64_t *n_duplicates,
+                      int32_t *t_min, int32_t *t_max, int32_t *n_graphs);
+
+/* Test / measurement entry point: exact counts for r explicit pairs
+ * (s[q], z[q]) in window [t0, t1].  out[r] receives the records.  Optional
+ * dense outputs (NULL to skip): node_f[r*n] gets f(v|s,z) = N(v)/sigma and
+ * edge_f[r*m] gets f(e|s,z) per input edge index (duplicates share their
+ * merged edge's value), for pairs whose counts did not saturate.  For packed
+ * graphs, graph[q] names the pair's graph (NULL for a single graph) and node
+ * ids are local. */
+int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r,
+                       const int32_t *graph, const int32_t *s, const int32_t *z,
+                       mantra_pair_record *out, double *node_f, double *edge_f);
+
+/* One estimation request. */
+typedef struct {
+    mantra_opt opt;
+    int32_t t0, t1;        /* inclusive window; t1 < t0 means the whole span */
+    double eps, delta;     /* accuracy and failure probability, in (0, 1) */
+    uint64_t seed;         /* pairs and Rademacher signs are functions of it */
+    int32_t c;             /* Monte Carlo trials of the c-MCERA, 1..64 (0: 25) */
+    int64_t s1;            /* first sample size override (0: from the bound) */
+    int64_t max_samples;   /* cap on the sample size (0: none) */
+    int64_t fixed_r;       /* > 0: exactly this many pairs, no progressive loop */
+    uint32_t flags;        /* MANTRA_F_* */
+    double *node_bc;       /* out [n] (packed: [sum of n_g]), caller owned */
+    double *edge_bc;       /* out [m] input edge order, or NULL */
+} mantra_request;
+
+#define MANTRA_F_EDGE_BC 1u /* also estimate temporal-edge betweenness */
+
+typedef struct {
+    int32_t status;        /* mantra_status of the request */
+    uint32_t flags;        /* MANTRA_RES_* */
+    int64_t samples;       /* |S| at the stop */
+    int64_t rounds;        /* progressive rounds run */
+    int64_t omega;         /* Theorem 3 sample size bound */
+    int64_t s_boot;        /* bootstrap pairs s' */
+    int64_t s1;            /* first sample size */
+    int64_t n_overflow;    /* sampled pairs whose counts saturated */
+    int64_t n_reachable;   /* sampled pairs with sigma > 0 */
+    int64_t window_edges;  /* temporal edges swept, summed over pairs */
+    int64_t arcs;          /* appearance-DAG arcs recorded, summed over pairs */
+    double xi;             /* supremum-deviation bound at the stop */
+    double rho_hat, v_hat; /* bootstrap estimates */
+    double wimpy, mcera;   /* last round's W and R^c */
+    double gpu_ms;         /* device time of the sweep kernels */
+    double latency_ms;     /* submit -> finish (serving) or call duration */
+} mantra_result;
+
+#define MANTRA_RES_NO_GUARANTEE 1u /* fm: Theorems 1 and 3 do not apply */
+#define MANTRA_RES_STOP_XI 2u      /* stopped because xi <= eps */
+#define MANTRA_RES_STOP_OMEGA 4u   /* stopped because |S| >= omega */
+
+/* Algorithm 1 on the whole span with the paper's defaults (c = 25): blocking.
+ * node_bc[n] receives the estimates. */
+int mantra_estimate(mantra_graph *g, mantra_opt opt, double eps, double delta, uint64_t seed,
+                    double *node_bc, mantra_result *out);
+
+/* Blocking run of one request (window, c, fixed sample, edge estimates). */
+int mantra_run(mantra_graph *g, const mantra_request *req, mantra_result *out);
+
+/* Serving: non-blocking submission to the graph's scheduler, which batches the
+ * rounds of all admitted requests into shared launches.  Admission is by the
+ * device memory a request's sums need; a request that can never fit returns
+ * MANTRA_E_TOO_LARGE.  mantra_poll waits up to timeout_ms (0: no wait, < 0:
+ * forever) and returns MANTRA_OK (result filled, ticket consumed),
+ * MANTRA_PENDING, or an error (ticket consumed). */
+int mantra_submit(mantra_graph *g, const mantra_request *req, uint64_t *ticket);
+int mantra_poll(uint64_t ticket, mantra_result *out, int32_t timeout_ms);
+
+/* Serving configuration: device bytes the scheduler may use for per-request
+ * sums (0: a default share of free memory), maximum concurrent requests. */
+int mantra_serve_config(mantra_graph *g, uint64_t mem_budget_bytes, int32_t max_active);
+
+/* Launch configuration: number of persistent workgroups (0: automatic) and
+ * per-slab arc capacity (0: automatic).  Measurement knob. */
+int mantra_set_launch(mantra_graph *g, int32_t n_slabs, int64_t arc_cap);
+
+/* Timing of the last blocking call: device time of the sweep kernel, its
+ * launch count, and the swept-window and arc totals. */
+int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launches,
+                       int64_t *window_edges, int64_t *arcs);
+
+const char *mantra_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MANTRA_H */

@@ -1,0 +1,172 @@
+"""MI355X-native temporal betweenness estimation (MANTRA hot path).
+
+A thin Python binding over the C ABI of ``libmantra.so`` (include/mantra.h):
+every computation runs in the library's HIP kernels; this module only
+marshals numpy arrays and results.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (OPT, F_EDGE_BC, MantraError, PairRecord, Request, Result,  # noqa: F401
+                   REC_OVERFLOW, REC_HOPS_LIMIT, RES_NO_GUARANTEE, RES_STOP_OMEGA, RES_STOP_XI)
+
+REC_DTYPE = np.dtype([("reachable", np.int32), ("t_arr", np.int32), ("hops", np.int32),
+                      ("flags", np.int32), ("sigma", np.uint64)])
+T_MAX = 2**31 - 1
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _opt(o):
+    return OPT[o] if isinstance(o, str) else int(o)
+
+
+class Graph:
+    """A device-resident temporal graph (mantra_graph)."""
+
+    def __init__(self, n, src, dst, t, _packed=None):
+        L = _lib.load()
+        self._h = ctypes.c_void_p()
+        if _packed is None:
+            src = np.ascontiguousarray(src, dtype=np.int32)
+            dst = np.ascontiguousarray(dst, dtype=np.int32)
+            t = np.ascontiguousarray(t, dtype=np.int32)
+            _lib.check(L.mantra_graph_create(_p(src), _p(dst), _p(t), int(src.shape[0]), int(n), 0,
+                                             ctypes.byref(self._h)))
+            self.m_input = int(src.shape[0])
+        else:
+            nc, eo = _packed
+            _lib.check(L.mantra_graph_create_packed(int(nc.shape[0]), _p(nc), _p(eo), _p(src), _p(dst),
+                                                    _p(t), 0, ctypes.byref(self._h)))
+            self.m_input = int(src.shape[0])
+        info = self.info()
+        self.n = info["n"]
+        self.m = info["m_unique"]
+        self.n_graphs = info["n_graphs"]
+
+    @classmethod
+    def of(cls, g):
+        return cls(g.n, g.src, g.dst, g.t)
+
+    @classmethod
+    def packed(cls, graphs):
+        """One device graph holding independent graphs (local node ids)."""
+        nc = np.array([g.n for g in graphs], dtype=np.int32)
+        eo = np.zeros(len(graphs) + 1, dtype=np.int64)
+        eo[1:] = np.cumsum([g.m for g in graphs])
+        src = np.ascontiguousarray(np.concatenate([g.src for g in graphs]), dtype=np.int32)
+        dst = np.ascontiguousarray(np.concatenate([g.dst for g in graphs]), dtype=np.int32)
+        t = np.ascontiguousarray(np.concatenate([g.t for g in graphs]), dtype=np.int32)
+        obj = cls(None, src, dst, t, _packed=(nc, eo))
+        obj.node_counts = nc
+        obj.edge_offsets = eo
+        return obj
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib._lib.mantra_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n = ctypes.c_int32(); mu = ctypes.c_int64(); nd = ctypes.c_int64()
+        t0 = ctypes.c_int32(); t1 = ctypes.c_int32(); G = ctypes.c_int32()
+        _lib.check(_lib._lib.mantra_graph_info(self._h, ctypes.byref(n), ctypes.byref(mu), ctypes.byref(nd),
+                                               ctypes.byref(t0), ctypes.byref(t1), ctypes.byref(G)))
+        return {"n": n.value, "m_unique": mu.value, "n_duplicates": nd.value, "t_min": t0.value,
+                "t_max": t1.value, "n_graphs": G.value}
+
+    def set_launch(self, n_slabs=0, arc_cap=0):
+        _lib.check(_lib._lib.mantra_set_launch(self._h, int(n_slabs), int(arc_cap)))
+
+    def last_timing(self):
+        ms = ctypes.c_double(); nl = ctypes.c_int64(); w = ctypes.c_int64(); a = ctypes.c_int64()
+        _lib.check(_lib._lib.mantra_last_timing(self._h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(w),
+                                                ctypes.byref(a)))
+        return {"sweep_ms": ms.value, "launches": nl.value, "window_edges": w.value, "arcs": a.value}
+
+    def count_pairs(self, opt, s, z, t0=0, t1=T_MAX, graph=None, node_f=False, edge_f=False):
+        """Records (and optionally dense per-pair f over nodes / input edges)
+        for explicit pairs."""
+        s = np.ascontiguousarray(s, dtype=np.int32)
+        z = np.ascontiguousarray(z, dtype=np.int32)
+        r = int(s.shape[0])
+        g = None if graph is None else np.ascontiguousarray(graph, dtype=np.int32)
+        rec = np.zeros(r, dtype=REC_DTYPE)
+        nf = np.zeros((r, self.n), dtype=np.float64) if node_f else None
+        ef = np.zeros((r, self.m_input), dtype=np.float64) if edge_f else None
+        _lib.check(_lib._lib.mantra_count_pairs(self._h, _opt(opt), int(t0), int(t1), r, _p(g), _p(s), _p(z),
+                                                _p(rec), _p(nf), _p(ef)))
+        return rec, nf, ef
+
+    def _request(self, opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges):
+        node_bc = np.zeros(self.n, dtype=np.float64)
+        edge_bc = np.zeros(self.m_input, dtype=np.float64) if edges else None
+        rq = Request(opt=_opt(opt), t0=int(t0), t1=int(t1), eps=float(eps), delta=float(delta),
+                     seed=int(seed), c=int(c), s1=int(s1), max_samples=int(max_samples), fixed_r=int(fixed_r),
+                     flags=F_EDGE_BC if edges else 0, node_bc=_p(node_bc), edge_bc=_p(edge_bc))
+        return rq, node_bc, edge_bc
+
+    def run(self, opt, eps=0.01, delta=0.1, seed=0, c=25, t0=0, t1=T_MAX, s1=0, max_samples=0, fixed_r=0,
+            edges=False, raise_on_error=True):
+        """Algorithm 1 (or a fixed sample of ``fixed_r`` pairs): returns
+        (node_bc, edge_bc or None, result dict)."""
+        rq, node_bc, edge_bc = self._request(opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges)
+        res = Result()
+        rc = _lib._lib.mantra_run(self._h, ctypes.byref(rq), ctypes.byref(res))
+        if raise_on_error:
+            _lib.check(rc)
+        out = res.to_dict()
+        out["rc"] = rc
+        return node_bc, edge_bc, out
+
+    def estimate(self, opt, eps, delta, seed):
+        node_bc = np.zeros(self.n, dtype=np.float64)
+        res = Result()
+        _lib.check(_lib._lib.mantra_estimate(self._h, _opt(opt), float(eps), float(delta), int(seed),
+                                             _p(node_bc), ctypes.byref(res)))
+        return node_bc, res.to_dict()
+
+    # serving
+    def serve_config(self, mem_budget_bytes=0, max_active=0):
+        _lib.check(_lib._lib.mantra_serve_config(self._h, int(mem_budget_bytes), int(max_active)))
+
+    def submit(self, opt, eps=0.01, delta=0.1, seed=0, c=25, t0=0, t1=T_MAX, s1=0, max_samples=0, fixed_r=0,
+               edges=False):
+        rq, node_bc, edge_bc = self._request(opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges)
+        tk = ctypes.c_uint64()
+        _lib.check(_lib._lib.mantra_submit(self._h, ctypes.byref(rq), ctypes.byref(tk)))
+        return Ticket(tk.value, node_bc, edge_bc)
+
+
+class Ticket:
+    def __init__(self, tk, node_bc, edge_bc):
+        self.id = tk
+        self.node_bc = node_bc  # filled by the library when the ticket finishes
+        self.edge_bc = edge_bc
+        self.result = None
+
+    def poll(self, timeout_ms=0):
+        res = Result()
+        rc = _lib._lib.mantra_poll(self.id, ctypes.byref(res), int(timeout_ms))
+        if rc == _lib.PENDING:
+            return None
+        _lib.check(rc)
+        self.result = res.to_dict()
+        return self.result
+
+
+def symbols():
+    """Names of the exported C entry points (for checks without a GPU)."""
+    return sorted(_lib.SIGNATURES)

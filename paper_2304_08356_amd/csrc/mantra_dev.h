@@ -1,0 +1,93 @@
+// Shared device/host structures of the sweep kernels (library internal).
+#pragma once
+#include <stdint.h>
+
+namespace mantra {
+
+typedef unsigned long long u64;
+typedef unsigned int u32;
+
+constexpr int kWave = 64;
+constexpr int kE = 4;                // edges per lane per batch
+constexpr int kC = kWave * kE;       // batch capacity (edges or arcs)
+constexpr int kFwN = 2 * kC;         // LDS forwarding / tail table slots
+constexpr u32 kHInf = 0xFFFFu;       // "unreached" hop count
+constexpr u64 kUMax = ~0ull;
+
+enum { OPT_SH = 0, OPT_FM = 1, OPT_SFM = 2, OPT_PFM = 3 };
+enum { STREAM_PAIR = 0, STREAM_BOOT = 1, STREAM_RADE = 2, STREAMS_PER_GRAPH = 4 };
+
+// record flags (public ones mirror mantra.h)
+enum : u32 {
+    REC_OVERFLOW = 1u,
+    REC_SELFCHECK = 2u,   // flow conservation at the origin failed (internal error)
+    REC_HOPS_LIMIT = 4u,
+    REC_ARCS_LIMIT = 8u,  // arc buffer too small: pair re-run with a larger one
+};
+
+struct DevGraph {
+    const int32_t *U, *V, *T;           // [m] sorted by (graph, t, dst, src); local node ids
+    const int64_t *out_off;             // [n_total+1] global node -> out-edge times
+    const int32_t *out_t;               // [m] ascending per node
+    const int64_t *in_off;
+    const int32_t *in_t;
+    const int64_t *seg_eoff;            // [G+1]
+    const int32_t *seg_noff;            // [G+1]
+    int32_t n_total;
+    int32_t G;
+    int64_t m;
+};
+
+// one request's slice of a launch
+struct DevReq {
+    int32_t opt, t0, t1, c;
+    u64 seed;
+    int32_t stream;      // STREAM_PAIR or STREAM_BOOT (RNG mode)
+    int32_t graph;       // -1: pairs spread over all graphs (packed RNG mode), else graph id
+    int64_t base;        // pair index of the first pair of this slice within its stream
+    int64_t qoff;        // first launch-pair slot of this request
+    int64_t count;       // pairs of this request in the launch
+    int64_t per_graph;   // packed RNG mode: pairs per graph
+    double *Bsum, *Wsum, *Rsum, *Esum; // accumulators (device), may be null
+};
+
+struct DevSlabs {
+    u64 *F;           // [ns][nmax][2]  {tag | h<<32, S}
+    u64 *R;           // [ns][nmax][2]  {tag | lvl<<32, acc}
+    u64 *N;           // [ns][nmax]     zero between pairs
+    u64 *AG;          // [ns][nmax][2]  big-tick aggregation {~stamp<<32 | dmin, sum}
+    u32 *AGF;         // [ns][nmax]
+    int32_t *touched; // [ns][nmax]
+    u64 *arcs;        // [ns][cap][2]   {k | tl<<32 | hl<<48, tail count}
+    u64 *XS;          // [ns][gmax][2]  big-tick scratch
+    u32 *hdr;         // [ns][4]        pair serial, tick stamp
+    int64_t nmax, cap, gmax;
+};
+
+struct LaunchArgs {
+    DevGraph g;
+    DevSlabs sl;
+    const DevReq *reqs;
+    int32_t nreq;
+    int32_t lds_bitmap;      // 1: reached-bitmap of nmax bits in LDS
+    int64_t npairs;
+    const int32_t *pg, *ps, *pz; // explicit pairs (or null: RNG mode)
+    const int32_t *pq;           // explicit launch slot -> original pair number (retries), or null
+    void *rec;                   // mantra_pair_record[npairs] or null
+    double *node_f;              // dense per-pair node output [npairs][n_total] or null
+    double *edge_f;              // dense per-pair edge output [npairs][m] or null
+    u32 *work;                   // work counter, zero at launch
+    u64 *stats;                  // [8] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck
+    int32_t *retry;              // [1 + npairs] pairs whose arcs did not fit
+};
+
+struct ReduceArgs {
+    const double *W;      // [n]
+    const double *R;      // [n][c]
+    const double *B;      // [n]
+    int64_t n;
+    int32_t c;
+    double *part;         // [blocks][2 + c]: max W, sum B, max R_j
+};
+
+}  // namespace mantra

@@ -1,0 +1,248 @@
+"""GPU parity: the HIP library (through its C ABI) against the oracle.
+
+Bit-exact: sigma, arrival, hops, flags and every per-pair f(v|s,z) and
+f(e|s,z) (the same IEEE division of the same exact integers).  Sums: the
+spec tolerance, 1e-12 relative (the Rademacher-weighted sums, which
+cancel, are compared with an absolute floor of 1e-12 times sum f).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mantra as omantra
+from parity_util import OPTS, compare_pairs, rel_close
+from synthgen import chung_lu_graph, uniform_graph, workload
+from test_oracle_brute import tiny_graph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+    import paper_2304_08356_amd as pk
+    return pk
+
+
+def both(pk, G):
+    return pk.Graph.of(G), oracle.Graph.of(G)
+
+
+def all_pairs(n):
+    S, Z = zip(*[(s, z) for s in range(n) for z in range(n) if s != z])
+    return np.array(S, dtype=np.int32), np.array(Z, dtype=np.int32)
+
+
+def test_tiny_random_graphs_all_pairs(lib):
+    from synthgen.graphs import TemporalGraph
+    for seed in range(40):
+        rng = np.random.default_rng(seed)
+        n, src, dst, t = tiny_graph(rng)
+        gg, og = both(lib, TemporalGraph(n, src, dst, t))
+        S, Z = all_pairs(n)
+        for opt in OPTS:
+            compare_pairs(gg, og, opt, S, Z, ctx="tiny%d" % seed)
+
+
+def test_tiny_windows(lib):
+    from synthgen.graphs import TemporalGraph
+    for seed in range(15):
+        rng = np.random.default_rng(500 + seed)
+        n, src, dst, t = tiny_graph(rng, T_hi=7)
+        t0 = int(rng.integers(1, 4))
+        t1 = int(rng.integers(t0, 8))
+        gg, og = both(lib, TemporalGraph(n, src, dst, t))
+        S, Z = all_pairs(n)
+        for opt in OPTS:
+            compare_pairs(gg, og, opt, S, Z, t0, t1, ctx="win%d" % seed)
+
+
+@pytest.fixture(scope="module")
+def tiny_workload(lib):
+    G = workload("tiny-uniform-n100")
+    return G, lib.Graph.of(G), oracle.Graph.of(G)
+
+
+def test_tiny_workload_all_pairs_sh(tiny_workload):
+    """n = 100, |E| = 2000, t in [1, 100]: all 9,900 ordered pairs, sh."""
+    G, gg, og = tiny_workload
+    S, Z = all_pairs(G.n)
+    compare_pairs(gg, og, "sh", S, Z, edges=False, ctx="C1-all")
+    compare_pairs(gg, og, "sh", S[::19], Z[::19], edges=True, ctx="C1-edges")
+
+
+@pytest.mark.parametrize("opt", ["fm", "sfm", "pfm"])
+def test_tiny_workload_sampled(tiny_workload, opt):
+    G, gg, og = tiny_workload
+    S, Z = oracle.draw_pairs(2001, oracle.STREAM_PAIR, G.n, 0, 500)
+    compare_pairs(gg, og, opt, S, Z, ctx="C1-" + opt)
+
+
+@pytest.mark.parametrize("opt", OPTS)
+def test_big_ticks(lib, opt):
+    """Ticks far larger than one 256-edge batch: the global-scratch path."""
+    G = uniform_graph(80, 4000, 6, seed=77)
+    gg, og = both(lib, G)
+    S, Z = oracle.draw_pairs(5, 0, G.n, 0, 300)
+    compare_pairs(gg, og, opt, S, Z, ctx="bigtick")
+
+
+@pytest.mark.parametrize("opt", OPTS)
+def test_hub_star_tick(lib, opt):
+    """One head with 600 in-edges at one time (a run longer than a batch)."""
+    rng = np.random.default_rng(3)
+    n = 700
+    src = list(range(1, 601)) + list(rng.integers(0, n, 400))
+    dst = [0] * 600 + list(rng.integers(0, n, 400))
+    t = [5] * 600 + list(rng.integers(1, 10, 400))
+    tr = {}
+    for u, v, tt in zip(src, dst, t):
+        if u != v:
+            tr[(int(u), int(v), int(tt))] = 1
+    a = np.array(list(tr.keys()), dtype=np.int32)
+    from synthgen.graphs import TemporalGraph
+    G = TemporalGraph(n, a[:, 0].copy(), a[:, 1].copy(), a[:, 2].copy())
+    gg, og = both(lib, G)
+    S, Z = oracle.draw_pairs(9, 0, n, 0, 400)
+    compare_pairs(gg, og, opt, S, Z, ctx="star")
+
+
+def test_saturation(lib):
+    """16 hops x 16 parallel edges: 2^64 shortest paths saturate (flagged,
+    no contributions); 15 hops give exactly 2^60."""
+    edges = [(i, i + 1, 16 * i + j + 1) for i in range(16) for j in range(16)]
+    a = np.array(edges, dtype=np.int32)
+    from synthgen.graphs import TemporalGraph
+    G = TemporalGraph(17, a[:, 0].copy(), a[:, 1].copy(), a[:, 2].copy())
+    gg, og = both(lib, G)
+    rec = compare_pairs(gg, og, "sh", [0, 0, 3], [16, 15, 12], ctx="sat")
+    assert int(rec["sigma"][0]) == 2**64 - 1 and int(rec["flags"][0]) & 1
+    assert int(rec["sigma"][1]) == 2**60
+    for opt in ("fm", "sfm", "pfm"):
+        compare_pairs(gg, og, opt, [0, 0, 3], [16, 15, 12], ctx="sat-" + opt)
+
+
+def test_duplicates_and_validation(lib):
+    src = np.array([0, 0, 1, 1], dtype=np.int32)
+    dst = np.array([1, 1, 2, 2], dtype=np.int32)
+    t = np.array([1, 1, 2, 2], dtype=np.int32)
+    g = lib.Graph(3, src, dst, t)
+    info = g.info()
+    assert info["m_unique"] == 2 and info["n_duplicates"] == 2
+    rec, nf, ef = g.count_pairs("sh", [0], [2], node_f=True, edge_f=True)
+    assert int(rec["sigma"][0]) == 1 and nf[0, 1] == 1.0
+    assert list(ef[0]) == [1.0, 1.0, 1.0, 1.0]  # duplicates share their merged edge's value
+    with pytest.raises(lib.MantraError):
+        lib.Graph(3, np.array([0]), np.array([0]), np.array([1]))  # self-loop
+    with pytest.raises(lib.MantraError):
+        lib.Graph(3, np.array([0]), np.array([3]), np.array([1]))  # id out of range
+    with pytest.raises(lib.MantraError):
+        lib.Graph(3, np.array([0]), np.array([1]), np.array([-1]))  # negative time
+    with pytest.raises(lib.MantraError):
+        g.count_pairs("sh", [1], [1])  # s == z
+
+
+def test_arc_capacity_retry(tiny_workload):
+    """Pairs whose DAG arcs exceed the slab buffer are re-run with a full
+    window buffer; results are unchanged."""
+    G, gg, og = tiny_workload
+    S, Z = oracle.draw_pairs(11, 0, G.n, 0, 300)
+    gg.set_launch(n_slabs=32, arc_cap=1024)
+    try:
+        compare_pairs(gg, og, "sh", S, Z, ctx="retry")
+        compare_pairs(gg, og, "fm", S, Z, ctx="retry-fm")
+    finally:
+        gg.set_launch(0, 0)
+
+
+@pytest.fixture(scope="module")
+def mid_workload(lib):
+    G = workload("mid-chunglu-n50k")
+    return G, lib.Graph.of(G), oracle.Graph.of(G)
+
+
+def test_mid_workload_sampled_pairs_sfm(mid_workload):
+    """Full size (n = 50,000, |E| = 2,000,000, bursty ticks), in the launch
+    configuration of the benchmark: pairs 0..15 of the benchmark's pair
+    stream, records and per-pair f over nodes and edges."""
+    G, gg, og = mid_workload
+    S, Z = oracle.draw_pairs(2002, oracle.STREAM_PAIR, G.n, 0, 16)
+    compare_pairs(gg, og, "sfm", S, Z, mode=1, ctx="C2-sfm")
+
+
+@pytest.mark.parametrize("opt", ["sh", "fm", "pfm"])
+def test_mid_workload_other_optimalities(mid_workload, opt):
+    G, gg, og = mid_workload
+    S, Z = oracle.draw_pairs(2002, oracle.STREAM_PAIR, G.n, 100, 4)
+    compare_pairs(gg, og, opt, S, Z, mode=1, edges=False, ctx="C2-" + opt)
+
+
+def check_sums(gpu_node, gpu_edge, osums, r, c_floor=True):
+    ok, worst = rel_close(gpu_node, osums.B / r, rel=1e-12, abs_floor=1e-300)
+    assert ok, worst
+    if gpu_edge is not None:
+        ok, worst = rel_close(gpu_edge, osums.E / r, rel=1e-12, abs_floor=1e-300)
+        assert ok, worst
+
+
+def test_fixed_sample_sums_tiny(tiny_workload):
+    """r = 500 sampled pairs (sh), node and temporal-edge estimates, and the
+    MCERA statistics of the sample (W, R^c)."""
+    G, gg, og = tiny_workload
+    nb, eb, res = gg.run("sh", fixed_r=500, seed=2001, c=16, edges=True)
+    ref = omantra.fixed(og, "sh", 500, seed=2001, c=16, edges=True, mode=0)
+    check_sums(nb, eb, ref["sums"], 500)
+    assert abs(res["wimpy"] - ref["W"]) <= 1e-12 * abs(ref["W"])
+    scale = float(np.max(ref["sums"].B)) / 500
+    assert abs(res["mcera"] - ref["Rc"]) <= 1e-12 * max(scale, 1e-300)
+
+
+@pytest.mark.parametrize("opt", OPTS)
+def test_progressive_tiny(tiny_workload, opt):
+    """Algorithm 1 end to end against the oracle's loop: same bootstrap
+    statistics, sample-size bound, schedule, stop and estimates."""
+    G, gg, og = tiny_workload
+    nb, _, res = gg.run(opt, eps=0.03, delta=0.1, seed=7, c=16)
+    ref = omantra.estimate(og, opt, 0.03, 0.1, 7, c=16, mode=0)
+    assert res["s_boot"] == ref["s_boot"]
+    assert abs(res["rho_hat"] - ref["rho_hat"]) <= 1e-12 * max(ref["rho_hat"], 1e-300)
+    assert abs(res["v_hat"] - ref["v_hat"]) <= 1e-12 * max(ref["v_hat"], 1e-300)
+    assert res["omega"] == ref["omega"] and res["s1"] == ref["s1"]
+    assert res["samples"] == ref["samples"] and res["rounds"] == len(ref["rounds"])
+    assert abs(res["xi"] - ref["xi"]) <= 1e-9 * ref["xi"]
+    ok, worst = rel_close(nb, ref["node_bc"], rel=1e-12, abs_floor=1e-300)
+    assert ok, worst
+    if opt == "fm":
+        assert res["flags"] & 1
+
+
+def test_packed_graphs(lib):
+    """Independent graphs in one device graph: per-graph pairs and sums."""
+    from synthgen import packed_uniform_graphs
+    gs = packed_uniform_graphs(6, seed=41, n_lo=30, n_hi=300, edges_per_node=10, T=50)
+    pg = lib.Graph.packed(gs)
+    r = 40
+    nb, _, res = pg.run("sh", fixed_r=r, seed=9, c=4)
+    off = 0
+    for gi, G in enumerate(gs):
+        og = oracle.Graph.of(G)
+        # graph gi's pairs use the stream 4 gi (pair) / 4 gi + 2 (signs)
+        S, Z = oracle.draw_pairs(9, 4 * gi, G.n, 0, r)
+        sums, _ = oracle.accumulate(og, "sh", S, Z)
+        ok, worst = rel_close(nb[off:off + G.n], sums.B / r, rel=1e-12, abs_floor=1e-300)
+        assert ok, (gi, worst)
+        rec, nf, _ = pg.count_pairs("sh", S[:10], Z[:10], graph=np.full(10, gi))
+        for q in range(10):
+            want, _, _ = oracle.pair(og, "sh", int(S[q]), int(Z[q]), nodes=False, edges=False)
+            assert int(rec["sigma"][q]) == want["sigma"] and int(rec["hops"][q]) == want["hops"]
+        off += G.n
+
+
+def test_repeat_calls_identical(tiny_workload):
+    """Slab state (tags, counters, N) is clean between pairs and calls."""
+    G, gg, og = tiny_workload
+    a, _, _ = gg.run("sfm", fixed_r=300, seed=3, c=8)
+    b, _, _ = gg.run("sfm", fixed_r=300, seed=3, c=8)
+    ok, worst = rel_close(a, b, rel=1e-12, abs_floor=1e-300)
+    assert ok, worst
