@@ -92,9 +92,11 @@ class Graph:
 
     def last_timing(self):
         ms = ctypes.c_double(); nl = ctypes.c_int64(); w = ctypes.c_int64(); a = ctypes.c_int64()
+        tn = ctypes.c_int64(); te = ctypes.c_int64()
         _lib.check(_lib._lib.mantra_last_timing(self._h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(w),
-                                                ctypes.byref(a)))
-        return {"sweep_ms": ms.value, "launches": nl.value, "window_edges": w.value, "arcs": a.value}
+                                                ctypes.byref(a), ctypes.byref(tn), ctypes.byref(te)))
+        return {"sweep_ms": ms.value, "launches": nl.value, "window_edges": w.value, "arcs": a.value,
+                "touched_nodes": tn.value, "touched_edges": te.value}
 
     def count_pairs(self, opt, s, z, t0=0, t1=T_MAX, graph=None, node_f=False, edge_f=False):
         """Records (and optionally dense per-pair f over nodes / input edges)

@@ -62,7 +62,7 @@ SIGNATURES = {
     "mantra_poll": (I32, [U64, P, I32]),
     "mantra_serve_config": (I32, [P, U64, I32]),
     "mantra_set_launch": (I32, [P, I32, I64]),
-    "mantra_last_timing": (I32, [P, P, P, P, P]),
+    "mantra_last_timing": (I32, [P, P, P, P, P, P, P]),
     "mantra_last_error": (ctypes.c_char_p, []),
 }
 

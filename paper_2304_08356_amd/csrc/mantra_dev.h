@@ -8,9 +8,15 @@ typedef unsigned long long u64;
 typedef unsigned int u32;
 
 constexpr int kWave = 64;
-constexpr int kE = 4;                // edges per lane per batch
+#ifndef MANTRA_KE
+#define MANTRA_KE 1
+#endif
+constexpr int kE = MANTRA_KE;        // edges per lane per batch
 constexpr int kC = kWave * kE;       // batch capacity (edges or arcs)
 constexpr int kFwN = 2 * kC;         // LDS forwarding / tail table slots
+constexpr int kFwBits = kFwN == 128 ? 7 : (kFwN == 256 ? 8 : (kFwN == 512 ? 9 : 10));
+static_assert((1 << kFwBits) == kFwN, "table size must be a power of two");
+constexpr int kAliveN = 512;         // alive-set hash slots of the reverse sweep (no LDS bitmap)
 constexpr u32 kHInf = 0xFFFFu;       // "unreached" hop count
 constexpr u64 kUMax = ~0ull;
 
@@ -33,6 +39,7 @@ struct DevGraph {
     const int32_t *in_t;
     const int64_t *seg_eoff;            // [G+1]
     const int32_t *seg_noff;            // [G+1]
+    const int32_t *perm;                // [n_total] input node id -> internal id (hubs first)
     int32_t n_total;
     int32_t G;
     int64_t m;
@@ -58,7 +65,7 @@ struct DevSlabs {
     u64 *AG;          // [ns][nmax][2]  big-tick aggregation {~stamp<<32 | dmin, sum}
     u32 *AGF;         // [ns][nmax]
     int32_t *touched; // [ns][nmax]
-    u64 *arcs;        // [ns][cap][2]   {k | tl<<32 | hl<<48, tail count}
+    u64 *arcs;        // [ns][cap][4]   per slab: cap x {head | t<<32}, then cap x {k | u<<32, tail count, tl | hl<<16}
     u64 *XS;          // [ns][gmax][2]  big-tick scratch
     u32 *hdr;         // [ns][4]        pair serial, tick stamp
     int64_t nmax, cap, gmax;
@@ -77,7 +84,7 @@ struct LaunchArgs {
     double *node_f;              // dense per-pair node output [npairs][n_total] or null
     double *edge_f;              // dense per-pair edge output [npairs][m] or null
     u32 *work;                   // work counter, zero at launch
-    u64 *stats;                  // [8] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck
+    u64 *stats;                  // [16] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck, touched nodes, touched edges
     int32_t *retry;              // [1 + npairs] pairs whose arcs did not fit
 };
 

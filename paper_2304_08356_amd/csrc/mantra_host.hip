@@ -30,6 +30,7 @@ hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t l
 hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st);
 hipError_t mantra_launch_fill(mantra::u64 *p, mantra::u64 val, int64_t n, hipStream_t st);
 size_t mantra_tab_lds_bytes(void);
+int mantra_sweep_occupancy(size_t lds_bytes);
 }
 
 // ------------------------------------------------------------------ errors
@@ -137,8 +138,10 @@ struct mantra_graph {
     std::vector<int32_t> seg_noff;
     std::vector<int64_t> seg_eoff;
     std::vector<int64_t> in2k;  // input edge index -> internal edge id
+    std::vector<int32_t> perm;  // input node id (global) -> internal id, hubs first
+    std::vector<int32_t> iperm; // internal id -> input id
     int32_t *dU = nullptr, *dV = nullptr, *dT = nullptr, *dout_t = nullptr, *din_t = nullptr,
-            *dseg_noff = nullptr;
+            *dseg_noff = nullptr, *dperm = nullptr;
     int64_t *dout_off = nullptr, *din_off = nullptr, *dseg_eoff = nullptr;
     hipStream_t st = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -157,13 +160,13 @@ struct mantra_graph {
     std::mutex mu;  // one blocking call at a time per graph
     // timing of the last blocking call
     double last_ms = 0;
-    int64_t last_launches = 0, last_W = 0, last_arcs = 0;
+    int64_t last_launches = 0, last_W = 0, last_arcs = 0, last_tn = 0, last_te = 0;
     ServeState *serve = nullptr;
     DevGraph dev() const {
         DevGraph d;
         d.U = dU; d.V = dV; d.T = dT; d.out_off = dout_off; d.out_t = dout_t; d.in_off = din_off;
         d.in_t = din_t; d.seg_eoff = dseg_eoff; d.seg_noff = dseg_noff; d.n_total = n_total;
-        d.G = G; d.m = m;
+        d.G = G; d.m = m; d.perm = dperm;
         return d;
     }
 };
@@ -212,6 +215,33 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
     g->seg_noff[G] = (int32_t)ntot;
     g->n_total = (int32_t)ntot;
     g->nmax = nmax;
+    // internal node ids: each graph's nodes ordered by total degree, highest
+    // first, so that the per-pair state of the hubs (which most edges touch
+    // in skewed graphs) shares a few cache lines
+    {
+        std::vector<int64_t> deg((size_t)ntot, 0);
+        for (int gi = 0; gi < G; ++gi) {
+            int32_t ng = node_count[gi];
+            for (int64_t i = edge_off[gi]; i < edge_off[gi + 1]; ++i) {
+                int32_t u = src[i], v = dst[i];
+                if (u >= 0 && u < ng) deg[(size_t)(g->seg_noff[gi] + u)]++;
+                if (v >= 0 && v < ng) deg[(size_t)(g->seg_noff[gi] + v)]++;
+            }
+        }
+        g->perm.assign((size_t)ntot, 0);
+        g->iperm.assign((size_t)ntot, 0);
+        std::vector<int32_t> ord;
+        for (int gi = 0; gi < G; ++gi) {
+            int32_t b = g->seg_noff[gi], ng = node_count[gi];
+            ord.resize((size_t)ng);
+            for (int32_t i = 0; i < ng; ++i) ord[(size_t)i] = b + i;
+            std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return deg[(size_t)x] > deg[(size_t)y]; });
+            for (int32_t i = 0; i < ng; ++i) {
+                g->perm[(size_t)ord[(size_t)i]] = b + i;
+                g->iperm[(size_t)(b + i)] = ord[(size_t)i];
+            }
+        }
+    }
     std::vector<EdgeRec> E((size_t)m);
     for (int gi = 0; gi < G; ++gi) {
         int32_t ng = node_count[gi];
@@ -222,7 +252,8 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
             if (u == v) return fail(MANTRA_E_INVALID, "edge %lld: self-loop on %d", (long long)i, u);
             if (tt < 0 || tt == INT32_MAX)
                 return fail(MANTRA_E_INVALID, "edge %lld: time %d outside [0, 2^31-2]", (long long)i, tt);
-            E[(size_t)i] = EdgeRec{gi, tt, v, u, i};
+            int32_t b = g->seg_noff[gi];
+            E[(size_t)i] = EdgeRec{gi, tt, g->perm[(size_t)(b + v)] - b, g->perm[(size_t)(b + u)] - b, i};
         }
     }
     std::sort(E.begin(), E.end(), [](const EdgeRec &a, const EdgeRec &b) {
@@ -297,6 +328,8 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
     HIPCHK(dalloc(&g->din_off, ntot + 1));
     HIPCHK(dalloc(&g->dseg_eoff, G + 1));
     HIPCHK(dalloc(&g->dseg_noff, G + 1));
+    HIPCHK(dalloc(&g->dperm, ntot));
+    HIPCHK(hipMemcpy(g->dperm, g->perm.data(), sizeof(int32_t) * ntot, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->dU, U.data(), sizeof(int32_t) * mu, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->dV, V.data(), sizeof(int32_t) * mu, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->dT, T.data(), sizeof(int32_t) * mu, hipMemcpyHostToDevice));
@@ -310,17 +343,21 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
     HIPCHK(hipEventCreate(&g->ev0));
     HIPCHK(hipEventCreate(&g->ev1));
     HIPCHK(dalloc(&g->dwork, 1));
-    HIPCHK(dalloc(&g->dstats, 8));
+    HIPCHK(dalloc(&g->dstats, 16));
     *out = g.release();
     return MANTRA_OK;
 }
 
 // ------------------------------------------------------------------ slabs
 
-static int lds_bitmap_ok(int64_t nmax) { return ((nmax + 31) / 32) * 4 <= 48 * 1024; }
+// A reached-bitmap in LDS lets a batch skip the state loads of unreached
+// tails; beyond 8 KB it costs more occupancy than it saves, and the reached
+// test reads the gathered per-node state (its pair tag) instead.
+static int lds_bitmap_ok(int64_t nmax) { return ((nmax + 31) / 32) * 4 <= 8 * 1024; }
 static size_t lds_bytes(int64_t nmax) {
     size_t b = mantra_tab_lds_bytes();
     if (lds_bitmap_ok(nmax)) b += (size_t)((nmax + 31) / 32) * 4;
+    else b += (size_t)kAliveN * 4;  // alive-set hash of the reverse sweep
     return b;
 }
 
@@ -329,10 +366,13 @@ static int auto_slabs(const mantra_graph *g) {
     hipDeviceProp_t pr;
     hipGetDeviceProperties(&pr, g->device);
     int cus = pr.multiProcessorCount > 0 ? pr.multiProcessorCount : 256;
-    // occupancy bound: two waves per SIMD (register use), LDS per CU
+    // resident workgroups per CU (registers and LDS), as the runtime reports
     size_t lb = lds_bytes(g->nmax);
-    int by_lds = (int)((160 * 1024) / (lb ? lb : 1));
-    int per_cu = std::min(8, std::max(1, by_lds));
+    int per_cu = mantra_sweep_occupancy(lb);
+    if (per_cu <= 0) {
+        int by_lds = (int)((160 * 1024) / (lb ? lb : 1));
+        per_cu = std::min(8, std::max(1, by_lds));
+    }
     return cus * per_cu;
 }
 
@@ -345,7 +385,7 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
     size_t ns = (size_t)nslabs;
     if (dalloc(&p.F, ns * nmax * 2) || dalloc(&p.R, ns * nmax * 2) || dalloc(&p.N, ns * nmax) ||
         dalloc(&p.AG, ns * nmax * 2) || dalloc(&p.AGF, ns * nmax) || dalloc(&p.touched, ns * nmax) ||
-        dalloc(&p.arcs, ns * (size_t)cap * 2) || dalloc(&p.XS, ns * (size_t)gmax * 2) ||
+        dalloc(&p.arcs, ns * (size_t)cap * 4) || dalloc(&p.XS, ns * (size_t)gmax * 2) ||
         dalloc(&p.hdr, ns * 4)) {
         p.release();
         (void)hipGetLastError();
@@ -386,8 +426,8 @@ struct LaunchSpec {
 // launch the sweep over all pairs of spec; re-run pairs whose arcs did not
 // fit with a pool of few slabs and the largest capacity.  Adds the device
 // time of the sweep launches to g->last_ms.
-static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[8]) {
-    if (sp.npairs <= 0) { memset(stats_out, 0, sizeof(u64) * 8); return MANTRA_OK; }
+static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[16]) {
+    if (sp.npairs <= 0) { memset(stats_out, 0, sizeof(u64) * 16); return MANTRA_OK; }
     hipSetDevice(g->device);
     int ns = auto_slabs(g);
     if ((int64_t)ns > sp.npairs) ns = (int)sp.npairs;
@@ -407,7 +447,7 @@ static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[8]) {
     }
     HIPCHK(hipMemcpyAsync(g->dreqs, sp.reqs.data(), sizeof(DevReq) * sp.reqs.size(), hipMemcpyHostToDevice, g->st));
     HIPCHK(hipMemsetAsync(g->dwork, 0, sizeof(u32), g->st));
-    HIPCHK(hipMemsetAsync(g->dstats, 0, sizeof(u64) * 8, g->st));
+    HIPCHK(hipMemsetAsync(g->dstats, 0, sizeof(u64) * 16, g->st));
     HIPCHK(hipMemsetAsync(g->dretry, 0, sizeof(int32_t), g->st));
     LaunchArgs a;
     memset(&a, 0, sizeof a);
@@ -435,8 +475,8 @@ static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[8]) {
     HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
     g->last_ms += ms;
     g->last_launches += 1;
-    u64 st1[8];
-    HIPCHK(hipMemcpy(st1, g->dstats, sizeof(u64) * 8, hipMemcpyDeviceToHost));
+    u64 st1[16];
+    HIPCHK(hipMemcpy(st1, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
     if (nretry > 0) {
         // pairs whose appearance-DAG arcs exceeded the slab capacity
         int ns2 = std::min<int>(nretry, 64);
@@ -449,7 +489,7 @@ static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[8]) {
         HIPCHK(dalloc(&dq, (size_t)nretry));
         HIPCHK(hipMemcpy(dq, q.data() + 1, sizeof(int32_t) * nretry, hipMemcpyHostToDevice));
         HIPCHK(hipMemsetAsync(g->dwork, 0, sizeof(u32), g->st));
-        HIPCHK(hipMemsetAsync(g->dstats, 0, sizeof(u64) * 8, g->st));
+        HIPCHK(hipMemsetAsync(g->dstats, 0, sizeof(u64) * 16, g->st));
         HIPCHK(hipMemsetAsync(g->dretry, 0, sizeof(int32_t), g->st));
         a.sl = g->pool_big.view();
         a.npairs = nretry;
@@ -461,18 +501,20 @@ static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[8]) {
         HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
         g->last_ms += ms;
         g->last_launches += 1;
-        u64 st2[8];
-        HIPCHK(hipMemcpy(st2, g->dstats, sizeof(u64) * 8, hipMemcpyDeviceToHost));
+        u64 st2[16];
+        HIPCHK(hipMemcpy(st2, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
         hipFree(dq);
         int32_t n2 = 0;
         HIPCHK(hipMemcpy(&n2, g->dretry, sizeof(int32_t), hipMemcpyDeviceToHost));
         if (n2 > 0) return fail(MANTRA_E_INTERNAL, "arc buffer of a full window overflowed");
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 16; ++i)
             if (i != 5) st1[i] += st2[i];
     }
     memcpy(stats_out, st1, sizeof(st1));
     g->last_W += (int64_t)st1[0];
     g->last_arcs += (int64_t)st1[1];
+    g->last_tn += (int64_t)st1[7];
+    g->last_te += (int64_t)st1[8];
     if (st1[6]) return fail(MANTRA_E_INTERNAL, "%llu pairs failed flow conservation", (unsigned long long)st1[6]);
     return MANTRA_OK;
 }
@@ -583,7 +625,7 @@ static int finish_outputs(mantra_graph *g, const mantra_request &rq, Acc &acc, i
     }
     HIPCHK(hipStreamSynchronize(g->st));
     double rr = (double)r;
-    for (int64_t v = 0; v < g->n_total; ++v) rq.node_bc[v] = r ? hb[(size_t)v] / rr : 0.0;
+    for (int64_t v = 0; v < g->n_total; ++v) rq.node_bc[g->iperm[(size_t)v]] = r ? hb[(size_t)v] / rr : 0.0;
     if (rq.edge_bc && acc.E)
         for (int64_t i = 0; i < g->m_in; ++i) rq.edge_bc[i] = r ? he[(size_t)g->in2k[(size_t)i]] / rr : 0.0;
     return MANTRA_OK;
@@ -600,12 +642,12 @@ static int run_request(mantra_graph *g, mantra_request rq, mantra_result *res) {
     mantra_result R;
     memset(&R, 0, sizeof R);
     if (rq.opt == MANTRA_FM) R.flags |= MANTRA_RES_NO_GUARANTEE;
-    g->last_ms = 0; g->last_launches = 0; g->last_W = 0; g->last_arcs = 0;
+    g->last_ms = 0; g->last_launches = 0; g->last_W = 0; g->last_arcs = 0; g->last_tn = 0; g->last_te = 0;
     Acc acc;
     rc = acc_alloc(g, acc, c, edges);
     if (rc) { acc.release(); return rc; }
     rc = acc_zero(g, acc);
-    u64 st[8];
+    u64 st[16];
     int64_t r = 0;
     if (!rc && rq.fixed_r > 0) {
         LaunchSpec sp;
@@ -742,7 +784,7 @@ void mantra_graph_destroy(mantra_graph *g) {
     g->pool.release();
     g->pool_big.release();
     hipFree(g->dU); hipFree(g->dV); hipFree(g->dT); hipFree(g->dout_t); hipFree(g->din_t);
-    hipFree(g->dout_off); hipFree(g->din_off); hipFree(g->dseg_eoff); hipFree(g->dseg_noff);
+    hipFree(g->dout_off); hipFree(g->din_off); hipFree(g->dseg_eoff); hipFree(g->dseg_noff); hipFree(g->dperm);
     hipFree(g->dwork); hipFree(g->dstats); hipFree(g->dretry); hipFree(g->dpart); hipFree(g->dreqs);
     if (g->ev0) hipEventDestroy(g->ev0);
     if (g->ev1) hipEventDestroy(g->ev1);
@@ -773,12 +815,15 @@ int mantra_set_launch(mantra_graph *g, int32_t n_slabs, int64_t arc_cap) {
 }
 
 int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launches, int64_t *window_edges,
-                       int64_t *arcs) {
+                       int64_t *arcs, int64_t *touched_nodes, int64_t *touched_edges) {
     if (!g) return fail(MANTRA_E_INVALID, "graph is NULL");
+    g_err.clear();
     if (sweep_ms) *sweep_ms = g->last_ms;
     if (launches) *launches = g->last_launches;
     if (window_edges) *window_edges = g->last_W;
     if (arcs) *arcs = g->last_arcs;
+    if (touched_nodes) *touched_nodes = g->last_tn;
+    if (touched_edges) *touched_edges = g->last_te;
     return MANTRA_OK;
 }
 
@@ -802,7 +847,7 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
     if (edge_f && (double)r * (double)g->m > 4e9) return fail(MANTRA_E_INVALID, "edge_f too large");
     std::lock_guard<std::mutex> lk(g->mu);
     hipSetDevice(g->device);
-    g->last_ms = 0; g->last_launches = 0; g->last_W = 0; g->last_arcs = 0;
+    g->last_ms = 0; g->last_launches = 0; g->last_W = 0; g->last_arcs = 0; g->last_tn = 0; g->last_te = 0;
     int32_t *dpg = nullptr, *dps = nullptr, *dpz = nullptr;
     void *drec = nullptr;
     double *dnf = nullptr, *def = nullptr;
@@ -815,8 +860,16 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
         (void)hipGetLastError();
         return fail(MANTRA_E_OOM, "count_pairs buffers");
     }
-    hipMemcpy(dps, s, sizeof(int32_t) * r, hipMemcpyHostToDevice);
-    hipMemcpy(dpz, z, sizeof(int32_t) * r, hipMemcpyHostToDevice);
+    {
+        std::vector<int32_t> si((size_t)r), zi((size_t)r);
+        for (int64_t q = 0; q < r; ++q) {
+            int32_t b = g->seg_noff[graph ? graph[q] : 0];
+            si[(size_t)q] = g->perm[(size_t)(b + s[q])] - b;
+            zi[(size_t)q] = g->perm[(size_t)(b + z[q])] - b;
+        }
+        hipMemcpy(dps, si.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice);
+        hipMemcpy(dpz, zi.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice);
+    }
     if (graph) hipMemcpy(dpg, graph, sizeof(int32_t) * r, hipMemcpyHostToDevice);
     if (dnf) hipMemsetAsync(dnf, 0, sizeof(double) * r * g->n_total, g->st);
     if (def) hipMemsetAsync(def, 0, sizeof(double) * r * g->m, g->st);
@@ -831,12 +884,19 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
     sp.reqs.push_back(d);
     sp.npairs = r;
     sp.dpg = dpg; sp.dps = dps; sp.dpz = dpz; sp.drec = drec; sp.dnode_f = dnf; sp.dedge_f = def;
-    u64 st[8];
+    u64 st[16];
     rc = run_sweep(g, sp, st);
     if (!rc) {
         if (hipMemcpy(out, drec, (size_t)r * 24, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(MANTRA_E_INTERNAL, "copy records");
-        if (!rc && node_f && hipMemcpy(node_f, dnf, sizeof(double) * r * g->n_total, hipMemcpyDeviceToHost) != hipSuccess)
-            rc = fail(MANTRA_E_INTERNAL, "copy node_f");
+        if (!rc && node_f) {
+            std::vector<double> tmp((size_t)(r * g->n_total));
+            if (hipMemcpy(tmp.data(), dnf, sizeof(double) * r * g->n_total, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = fail(MANTRA_E_INTERNAL, "copy node_f");
+            else
+                for (int64_t q = 0; q < r; ++q)
+                    for (int64_t v = 0; v < g->n_total; ++v)
+                        node_f[q * g->n_total + g->iperm[(size_t)v]] = tmp[(size_t)(q * g->n_total + v)];
+        }
         if (!rc && edge_f) {
             std::vector<double> tmp((size_t)(r * g->m));
             if (hipMemcpy(tmp.data(), def, sizeof(double) * r * g->m, hipMemcpyDeviceToHost) != hipSuccess)

@@ -96,26 +96,30 @@ __device__ __forceinline__ int64_t wave_upper_bound(const int32_t *arr, int64_t 
 
 // ------------------------------------------------------------ LDS layout
 
-struct FwdLds {               // forward tables (per batch)
-    u64 fw_key[kFwN];         // stamp<<32 | node
-    u32 fw_run[kFwN];         // run slot holding the node's committed state
-    u32 rt_d[kC];             // per run: min hop candidate
-    u32 rt_nh[kC];            // per run: committed h
-    u32 rt_ok[kC];            // per run: committed (useful)
-    u64 rt_c[kC];             // per run: count sum
-    u64 rt_nS[kC];            // per run: committed S
+enum : u32 { FM_NEEDED = 1u, FM_COMMITTED = 2u };
+
+struct FwdLds {
+    u32 fk[kFwN];         // forwarding table: node + 1 (0 = empty)
+    u32 fm[kFwN];         // FM_NEEDED | FM_COMMITTED
+    u64 ftm[kFwN];        // bit tau: the node is a run head at tick tau of the batch
+    u32 fh[kFwN];         // last committed h
+    u64 fS[kFwN];         // last committed S
+    u32 rmin[kWave];      // per run (by run-start lane): min hop candidate
+    u64 rlo[kWave];       // per run: count sum, low 32-bit halves
+    u64 rhi[kWave];       //                      high 32-bit halves
+    int32_t dtick[kWave]; // per tick: latest earlier tick one of its edges reads
 };
-struct RevLds {               // reverse table (per batch): tail state by node
+struct RevLds {           // reverse: tail state by node, per batch
     u64 tb_key[kFwN];
     u64 tb_acc[kFwN];
-    u32 tb_lvl[kFwN];         // bit 31: valid
+    u32 tb_lvl[kFwN];     // bit 31: valid
 };
 union TabLds { FwdLds f; RevLds r; };
 
-__device__ __forceinline__ u32 hslot(u32 node) { return (node * 2654435761u) >> (32 - 9); }
-static_assert(kFwN == 512, "hslot assumes 512 slots");
 
-// lookup node in a stamped open-addressing table; -1 if absent
+__device__ __forceinline__ u32 hslot(u32 node) { return (node * 2654435761u) >> (32 - kFwBits); }
+
+// stamped open-addressing table (reverse): lookup, -1 if absent
 __device__ __forceinline__ int tab_find(const u64 *keys, u32 stamp, u32 node) {
     u32 sl = hslot(node);
     for (int it = 0; it < kFwN; ++it) {
@@ -138,10 +142,33 @@ __device__ __forceinline__ int tab_insert(u64 *keys, u32 stamp, u32 node, int *f
             sl = (sl + 1) & (kFwN - 1);
             continue;
         }
-        u64 old = atomicCAS((unsigned long long *)&keys[sl], (unsigned long long)k,
-                            (unsigned long long)want);
+        u64 old = atomicCAS((unsigned long long *)&keys[sl], (unsigned long long)k, (unsigned long long)want);
         if (old == k) { *fresh = 1; return (int)sl; }
-        // someone claimed it: re-examine the same slot
+    }
+    return -1;
+}
+// forwarding table (forward, cleared per batch): find / insert
+__device__ __forceinline__ int fw_find(const u32 *fk, u32 node) {
+    u32 sl = hslot(node);
+    for (int it = 0; it < kFwN; ++it) {
+        u32 k = fk[sl];
+        if (k == 0) return -1;
+        if (k == node + 1) return (int)sl;
+        sl = (sl + 1) & (kFwN - 1);
+    }
+    return -1;
+}
+__device__ __forceinline__ int fw_insert(u32 *fk, u32 node) {
+    u32 sl = hslot(node);
+    for (int it = 0; it < kFwN; ++it) {
+        u32 k = fk[sl];
+        if (k == node + 1) return (int)sl;
+        if (k == 0) {
+            u32 old = atomicCAS(&fk[sl], 0u, node + 1);
+            if (old == 0u || old == node + 1) return (int)sl;
+            continue;  // claimed by another node: look again at this slot
+        }
+        sl = (sl + 1) & (kFwN - 1);
     }
     return -1;
 }
@@ -181,7 +208,9 @@ struct Pair {
 };
 
 struct Slab {
-    u64 *F, *R, *N, *AG, *arcs, *XS;
+    u64 *F, *R, *N, *AG, *XS;
+    u64 *arcm;             // [cap] head | time << 32
+    u64 *arcx;             // [cap][3] edge | tail << 32, tail count, tl | hl << 16
     u32 *AGF, *hdr;
     int32_t *touched;
 };
@@ -197,6 +226,16 @@ struct FwdOut {
 };
 
 __device__ __forceinline__ bool bm_test(const u32 *bm, int32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
+
+__device__ __forceinline__ void put_arc(const Slab &S, int64_t cap, int64_t pos, int32_t v, int32_t t, u32 k,
+                                        int32_t u, u64 tc, u32 tl, u32 hl) {
+    if (pos < cap) {
+        S.arcm[pos] = (u64)(u32)v | ((u64)(u32)t << 32);
+        S.arcx[3 * pos] = (u64)k | ((u64)(u32)u << 32);
+        S.arcx[3 * pos + 1] = tc;
+        S.arcx[3 * pos + 2] = (u64)tl | ((u64)hl << 16);
+    }
+}
 
 // decide the commit of head v at time t given its run's (d, c) and its
 // current state (reached, hv, Sv); returns useful, sets the new state
@@ -227,13 +266,14 @@ __device__ __forceinline__ bool head_commit(int opt, bool rv, u32 hv, u64 Sv, u3
     return true;
 }
 
-// ------------------------------------------------------------ forward: big tick
-// A tick with more edges than one batch: aggregation by head through the
+// ------------------------------------------------------------ forward: long tick
+// A tick with more edges than one row (64): aggregation by head through the
 // slab's global per-node scratch (AG), four passes, commits after all reads.
+// Such a tick always forms a batch of its own.
 
-__device__ void fwd_big_tick(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm,
-                             int64_t g0, int64_t g1, int32_t t, u32 &agstamp, FwdOut &o,
-                             u32 &zh, u64 &zS, bool &zhit) {
+__device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm,
+                              int64_t g0, int64_t g1, int32_t t, u32 &agstamp, FwdOut &o,
+                              u32 &zh, u64 &zS, bool &zhit) {
     const int l = lane_id();
     const int32_t *U = a.g.U, *V = a.g.V;
     agstamp += 1;
@@ -338,26 +378,27 @@ __device__ void fwd_big_tick(const LaunchArgs &a, const Pair &P, const Slab &S, 
     for (int64_t sb = g0; sb < g1; sb += kWave) {
         int64_t idx = sb + l;
         bool rec = false;
-        u64 w0 = 0, w1 = 0;
+        u32 hu = 0, d = 0;
+        int32_t v = 0, u = 0;
+        u64 su = 0;
         if (idx < g1) {
             u64 x0 = S.XS[2 * (idx - g0)];
             if (x0 >> 32) {
-                int32_t v = V[idx];
+                v = V[idx];
                 if (S.AGF[v] == agstamp) {
-                    u32 hu = (u32)x0;
-                    u32 d = (u32)ld_agent(&S.AG[2 * (int64_t)v]);
+                    hu = (u32)x0;
+                    d = (u32)ld_agent(&S.AG[2 * (int64_t)v]);
                     if (!P.level || hu + 1 == d) {
                         rec = true;
-                        w0 = (u64)(u32)idx | ((u64)hu << 32) | ((u64)d << 48);
-                        w1 = S.XS[2 * (idx - g0) + 1];
+                        u = U[idx];
+                        su = S.XS[2 * (idx - g0) + 1];
                     }
                 }
             }
         }
         u64 m = ballot(rec);
         if (m) {
-            int64_t pos = o.arcs + mbcnt(m);
-            if (rec && pos < a.sl.cap) { S.arcs[2 * pos] = w0; S.arcs[2 * pos + 1] = w1; }
+            if (rec) put_arc(S, a.sl.cap, o.arcs + mbcnt(m), v, t, (u32)idx, u, su, hu, d);
             o.arcs += __popcll(m);
         }
     }
@@ -366,11 +407,40 @@ __device__ void fwd_big_tick(const LaunchArgs &a, const Pair &P, const Slab &S, 
 
 // ------------------------------------------------------------ forward sweep
 
+// element j of a per-slice register array (j is wave-uniform)
+__device__ __forceinline__ u64 pick4(const u64 *m, int j) {
+    u64 r = m[0];
+#pragma unroll
+    for (int i = 1; i < kE; ++i) if (j == i) r = m[i];
+    return r;
+}
+
+__device__ __forceinline__ int32_t pick4i(const int32_t *m, int j) {
+    int32_t r = m[0];
+#pragma unroll
+    for (int i = 1; i < kE; ++i) if (j == i) r = m[i];
+    return r;
+}
+
+// first set bit at offset >= pos over the batch masks, or `none`
+__device__ __forceinline__ int next_bit(const u64 *m, int pos, int none) {
+    for (int j = pos >> 6; j < kE; ++j) {
+        u64 x = pick4(m, j);
+        int b = (j == (pos >> 6)) ? (pos & 63) : 0;
+        x &= kUMax << b;
+        if (x) return j * kWave + (__ffsll((long long)x) - 1);
+    }
+    return none;
+}
+
 __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, FwdLds &L,
-                        u32 &fstamp, u32 &agstamp, FwdOut &o) {  // fstamp: shared table stamp
+                        u32 &agstamp, FwdOut &o) {
+    static_assert(kE == 1, "the forward sweep is written for one edge per lane");
     const int l = lane_id();
     const int32_t *U = a.g.U, *V = a.g.V, *T = a.g.T;
     const int opt = P.opt;
+    const u64 le = (l == kWave - 1) ? kUMax : ((2ull << l) - 1ull);  // lanes <= l
+    const u32 kBig = 0xFFFFFFFFu;
     u32 zh = kHInf;
     u64 zS = 0;
     bool zhit = false;
@@ -380,37 +450,33 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
     o.flags = 0;
     o.t_arr = -1;
     while (b0 < P.hi && !done) {
+        // ---- batch: up to 64 edges, whole ticks
         const int64_t avail = P.hi - b0;
-        const int nb = avail < kC ? (int)avail : kC;
-        int32_t tt[kE];
-#pragma unroll
-        for (int j = 0; j < kE; ++j) {
-            int off = j * kWave + l;
-            tt[j] = off < nb ? T[b0 + off] : INT32_MAX;
-        }
+        const int nb = avail < kWave ? (int)avail : kWave;
+        const bool ld = l < nb;
+        const int32_t t = ld ? T[b0 + l] : INT32_MAX;
+        const int32_t u = ld ? U[b0 + l] : 0;
+        const int32_t v = ld ? V[b0 + l] : -1;
+        for (int i = l; i < kFwN; i += kWave) { L.fk[i] = 0u; L.fm[i] = 0u; L.ftm[i] = 0ull; }
         int nbat = nb;
-        if (nb == kC && b0 + kC < P.hi) {
-            int32_t tnext = T[b0 + kC];
-            int32_t tlast = rl32(tt[kE - 1], kWave - 1);
+        if (nb == kWave && b0 + kWave < P.hi) {
+            const int32_t tnext = T[b0 + kWave];
+            const int32_t tlast = rl32(t, kWave - 1);
             if (tnext == tlast) {
-                int first = -1;
-#pragma unroll
-                for (int j = 0; j < kE; ++j) {
-                    u64 m = ballot(tt[j] == tlast);
-                    if (first < 0 && m) first = j * kWave + (__ffsll((long long)m) - 1);
-                }
+                const int first = __ffsll((long long)ballot(t == tlast)) - 1;
                 if (first == 0) {
                     // one tick longer than a batch
                     int64_t g1 = P.hi;
-                    for (int64_t i = b0 + kC; i < P.hi; i += kWave) {
+                    for (int64_t i = b0 + kWave; i < P.hi; i += kWave) {
                         int64_t idx = i + l;
                         u64 m = ballot(idx < P.hi && T[idx] != tlast);
                         if (m) { g1 = i + (__ffsll((long long)m) - 1); break; }
                     }
-                    fwd_big_tick(a, P, S, bm, b0, g1, tlast, agstamp, o, zh, zS, zhit);
+                    __syncthreads();
+                    fwd_long_tick(a, P, S, bm, b0, g1, tlast, agstamp, o, zh, zS, zhit);
                     o.swept = g1 - P.lo;
                     b0 = g1;
-                    if (o.flags & (REC_HOPS_LIMIT)) return;
+                    if (o.flags & REC_HOPS_LIMIT) return;
                     if (o.arcs > a.sl.cap) { o.flags |= REC_ARCS_LIMIT; return; }
                     if (zhit && opt != OPT_SH) done = true;
                     continue;
@@ -418,198 +484,167 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                 nbat = first;
             }
         }
-        // ---- load the batch, boundaries, runs
-        int32_t uu[kE], vv[kE];
-        bool in[kE], gst[kE], rst[kE];
-        u64 gm[kE], rm[kE];
-#pragma unroll
-        for (int j = 0; j < kE; ++j) {
-            int off = j * kWave + l;
-            in[j] = off < nbat;
-            uu[j] = in[j] ? U[b0 + off] : 0;
-            vv[j] = in[j] ? V[b0 + off] : -1;
+        const bool in = l < nbat;
+        int32_t tp = __shfl_up(t, 1);
+        int32_t vp = __shfl_up(v, 1);
+        if (l == 0) { tp = INT32_MIN; vp = -2; }
+        const bool gst = in && t != tp;
+        const bool rs = in && (gst || v != vp);
+        const u64 gm = ballot(gst);
+        const u64 rsall = ballot(rs);
+        const int tid = __popcll(gm & le) - 1;
+        const int ntick = __popcll(gm);
+        const int rsl = 63 - __clzll((long long)((rsall & le) | 1ull));  // lane of my run's start
+        // ---- state at batch start: reached bitmap, then the per-node state
+        bool rt = false, hr = false;
+        u32 hu = 0, hv = 0;
+        u64 su = 0, sv = 0;
+        if (in && (a.lds_bitmap ? bm_test(bm, u) : true)) {
+            const u64 th = S.F[2 * (int64_t)u], x = S.F[2 * (int64_t)u + 1];
+            if ((u32)th == P.tag) { rt = true; hu = (u32)(th >> 32) & 0xFFFFu; su = x; }
         }
-#pragma unroll
-        for (int j = 0; j < kE; ++j) {
-            int32_t tp = __shfl_up(tt[j], 1);
-            int32_t vp = __shfl_up(vv[j], 1);
-            if (l == 0) {
-                tp = j > 0 ? rl32(tt[j - 1], kWave - 1) : INT32_MIN;
-                vp = j > 0 ? rl32(vv[j - 1], kWave - 1) : -2;
-            }
-            gst[j] = in[j] && (tt[j] != tp);
-            rst[j] = in[j] && (gst[j] || vv[j] != vp);
-            gm[j] = ballot(gst[j]);
-            rm[j] = ballot(rst[j]);
+        if (rs && (a.lds_bitmap ? bm_test(bm, v) : true)) {
+            const u64 th = S.F[2 * (int64_t)v], x = S.F[2 * (int64_t)v + 1];
+            if ((u32)th == P.tag) { hr = true; hv = (u32)(th >> 32) & 0xFFFFu; sv = x; }
         }
-        int roff[kE];
-        {
-            int last = 0;
-#pragma unroll
-            for (int j = 0; j < kE; ++j) {
-                u64 low = (l == kWave - 1) ? kUMax : ((2ull << l) - 1ull);
-                u64 mm = rm[j] & low;
-                roff[j] = mm ? (j * kWave + 63 - __clzll((long long)mm)) : last;
-                if (rm[j]) last = j * kWave + 63 - __clzll((long long)rm[j]);
-            }
+        // no tail reached at batch start: no tick of the batch can commit
+        if (!ballot(rt)) {
+            b0 += nbat;
+            o.swept = b0 - P.lo;
+            continue;
         }
-        // ---- gathers: tails (reached at batch start) and run heads
-        bool rt[kE], hvr[kE];
-        u32 hu[kE], hv0[kE];
-        u64 su[kE], sv0[kE];
-#pragma unroll
-        for (int j = 0; j < kE; ++j) {
-            rt[j] = false; hu[j] = 0; su[j] = 0;
-            hvr[j] = false; hv0[j] = kHInf; sv0[j] = 0;
-            if (in[j] && (a.lds_bitmap ? bm_test(bm, uu[j]) : true)) {
-                u64 th = S.F[2 * (int64_t)uu[j]], sv = S.F[2 * (int64_t)uu[j] + 1];
-                if ((u32)th == P.tag) { rt[j] = true; hu[j] = (u32)(th >> 32) & 0xFFFFu; su[j] = sv; }
-            }
-            if (rst[j] && (a.lds_bitmap ? bm_test(bm, vv[j]) : true)) {
-                u64 th = S.F[2 * (int64_t)vv[j]], sv = S.F[2 * (int64_t)vv[j] + 1];
-                if ((u32)th == P.tag) { hvr[j] = true; hv0[j] = (u32)(th >> 32) & 0xFFFFu; sv0[j] = sv; }
-            }
-            if (rst[j]) {
-                int off = j * kWave + l;
-                L.rt_d[off] = kHInf;
-                L.rt_c[off] = 0;
-                L.rt_ok[off] = 0;
-            }
-        }
-        fstamp += 1;
-        bool fw_used = false;
+        if (rs) { L.rmin[l] = kBig; L.rlo[l] = 0ull; L.rhi[l] = 0ull; }
+        L.dtick[l] = -1;
         __syncthreads();
-        // ---- ticks of the batch in time order
-        int gs = 0;
-        while (gs < nbat && !done) {
-            // next tick start after gs
-            int ge = nbat;
-            {
-                int pos = gs + 1;
-                for (int j = pos >> 6; j < kE; ++j) {
-                    u64 m = (j == 0) ? gm[0] : (j == 1 ? gm[1] : (j == 2 ? gm[2] : gm[3]));
-                    int b = (j == (pos >> 6)) ? (pos & 63) : 0;
-                    m = (b >= 64) ? 0 : (m & (kUMax << b));
-                    if (m) { ge = j * kWave + (__ffsll((long long)m) - 1); break; }
-                }
-                if (ge > nbat) ge = nbat;
+        // ---- in-batch dependencies: at which ticks is each head node a run head
+        int slv = -1, slu = -1;
+        if (rs) {
+            slv = fw_insert(L.fk, (u32)v);
+            if (slv >= 0) atomicOr((unsigned long long *)&L.ftm[slv], 1ull << tid);
+        }
+        __syncthreads();
+        const u64 before = (tid > 0) ? ((1ull << tid) - 1ull) : 0ull;
+        int dep = -1;
+        bool nt = false, nh = false;
+        if (in) {
+            slu = fw_find(L.fk, (u32)u);
+            if (slu >= 0) {
+                const u64 m = L.ftm[slu] & before;
+                if (m) { nt = true; dep = 63 - __clzll((long long)m); atomicOr(&L.fm[slu], FM_NEEDED); }
             }
-            const int jlo = gs >> 6, jhi = (ge - 1) >> 6;
-            const int32_t t = rl32(jlo == 0 ? tt[0] : (jlo == 1 ? tt[1] : (jlo == 2 ? tt[2] : tt[3])), gs & 63);
-            // step 1: forwarded tail state, candidate minima
-#pragma unroll
-            for (int j = 0; j < kE; ++j) {
-                if (j < jlo || j > jhi) continue;
-                int off = j * kWave + l;
-                bool act = off >= gs && off < ge;
-                if (act && fw_used) {
-                    int sl = tab_find(L.fw_key, fstamp, (u32)uu[j]);
-                    if (sl >= 0) {
-                        u32 r = L.fw_run[sl];
-                        rt[j] = true; hu[j] = L.rt_nh[r]; su[j] = L.rt_nS[r];
-                    }
-                }
-                bool hl = act && rt[j] && hu[j] + 1 >= kHInf;
-                if (act && rt[j] && !hl) atomicMin(&L.rt_d[roff[j]], hu[j] + 1);
-                if (ballot(hl)) o.flags |= REC_HOPS_LIMIT;
+        }
+        if (rs && slv >= 0) {
+            const u64 m = L.ftm[slv] & before;
+            if (m) {
+                nh = true;
+                const int d2 = 63 - __clzll((long long)m);
+                dep = d2 > dep ? d2 : dep;
+                atomicOr(&L.fm[slv], FM_NEEDED);
             }
-            __syncthreads();
-            // step 2: count sums
-#pragma unroll
-            for (int j = 0; j < kE; ++j) {
-                if (j < jlo || j > jhi) continue;
-                int off = j * kWave + l;
-                bool act = off >= gs && off < ge;
-                if (act && rt[j]) {
-                    bool tight = P.level ? (hu[j] + 1 == L.rt_d[roff[j]]) : true;
-                    if (tight) lds_sat_add(&L.rt_c[roff[j]], su[j]);
+        }
+        if (dep >= 0) atomicMax(&L.dtick[tid], dep);
+        __syncthreads();
+        const bool nd = rs && slv >= 0 && (L.fm[slv] & FM_NEEDED);
+        const int32_t dt = L.dtick[l];  // lane tau: D(tau)
+        // ---- segments: maximal runs of ticks that read nothing committed inside them
+        int ta = 0;
+        while (ta < ntick && !done) {
+            int tb = ta + 1;
+            while (tb < ntick && rl32(dt, tb) < ta) ++tb;
+            const bool act = in && tid >= ta && tid < tb;
+            bool reached = act && rt;
+            u32 h_u = hu;
+            u64 s_u = su;
+            if (act && nt && (L.fm[slu] & FM_COMMITTED)) { reached = true; h_u = L.fh[slu]; s_u = L.fS[slu]; }
+            if (!ballot(reached)) { ta = tb; continue; }
+            if (ballot(reached && h_u + 1 >= kHInf)) { o.flags |= REC_HOPS_LIMIT; return; }
+            const u32 cand = reached ? h_u + 1 : kBig;
+            const u64 am = ballot(act);
+            const u64 rsm = ballot(act && rs);
+            u32 d;
+            u64 c = 0;
+            bool tight, lead;
+            const bool single = (rsm == am);
+            if (single) {
+                d = cand;
+                tight = reached;
+                c = s_u;
+                lead = reached;
+            } else {
+                if (reached) atomicMin(&L.rmin[rsl], cand);
+                __syncthreads();
+                d = act ? L.rmin[rsl] : kBig;
+                tight = reached && (P.level ? cand == d : true);
+                if (tight) {
+                    atomicAdd((unsigned long long *)&L.rlo[rsl], (unsigned long long)(s_u & 0xFFFFFFFFull));
+                    atomicAdd((unsigned long long *)&L.rhi[rsl], (unsigned long long)(s_u >> 32));
                 }
-            }
-            __syncthreads();
-            // step 3: run heads decide and commit
-            bool zl_any = false;
-            u32 zh_new = zh;
-            u64 zS_new = zS;
-            bool any_commit = false;
-#pragma unroll
-            for (int j = 0; j < kE; ++j) {
-                if (j < jlo || j > jhi) continue;
-                int off = j * kWave + l;
-                bool act = off >= gs && off < ge;
-                bool lead = act && rst[j] && L.rt_d[off] != kHInf;
-                bool zl = false;
-                u32 nh = 0;
-                u64 nS = 0;
-                bool ok = false;
+                __syncthreads();
+                lead = act && rs && d != kBig;
                 if (lead) {
-                    int32_t v = vv[j];
-                    bool rv = hvr[j];
-                    u32 hv = hv0[j];
-                    u64 Sv = sv0[j];
-                    if (fw_used) {
-                        int sl = tab_find(L.fw_key, fstamp, (u32)v);
-                        if (sl >= 0) { u32 r = L.fw_run[sl]; rv = true; hv = L.rt_nh[r]; Sv = L.rt_nS[r]; }
-                    }
-                    ok = head_commit(opt, rv, hv, Sv, L.rt_d[off], L.rt_c[off], v, P.z, zh, &nh, &nS);
-                    if (ok) {
-                        S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh << 32);
-                        S.F[2 * (int64_t)v + 1] = nS;
-                        if (a.lds_bitmap) atomicOr(&bm[v >> 5], 1u << (v & 31));
-                        int fresh;
-                        int sl = tab_insert(L.fw_key, fstamp, (u32)v, &fresh);
-                        if (sl >= 0) L.fw_run[sl] = (u32)off;
-                        L.rt_nh[off] = nh;
-                        L.rt_nS[off] = nS;
-                        L.rt_ok[off] = 1;
-                        zl = (v == P.z);
-                    }
-                }
-                if (ballot(ok)) any_commit = true;
-                u64 zm = ballot(zl);
-                if (zm) {
-                    int zlane = __ffsll((long long)zm) - 1;
-                    zh_new = (u32)rl32((int)nh, zlane);
-                    zS_new = rl64(nS, zlane);
-                    zl_any = true;
+                    const u64 lo = L.rlo[rsl], hi = L.rhi[rsl];
+                    if (hi >> 32) c = kUMax;
+                    else { const u64 x = hi << 32; c = x + lo; if (c < x) c = kUMax; }
                 }
             }
-            if (zl_any) {
-                if (opt == OPT_SH) { if (zh_new < zh) o.t_arr = t; }
-                else o.t_arr = t;
+            // run heads decide
+            bool ok = false;
+            u32 nh2 = 0;
+            u64 nS = 0;
+            if (lead) {
+                bool rv = hr;
+                u32 h_v = hv;
+                u64 S_v = sv;
+                if (nh && (L.fm[slv] & FM_COMMITTED)) { rv = true; h_v = L.fh[slv]; S_v = L.fS[slv]; }
+                ok = head_commit(opt, rv, h_v, S_v, d, c, v, P.z, zh, &nh2, &nS);
+            }
+            // fm/sfm/pfm stop at the tick where z is first reached: later ticks
+            // of the segment are dropped
+            int cut = tb;
+            if (opt != OPT_SH) {
+                const u64 zm = ballot(ok && v == P.z);
+                if (zm) cut = rl32(tid, __ffsll((long long)zm) - 1) + 1;
+            }
+            const bool keep = tid < cut;
+            ok = ok && keep;
+            if (ok) {
+                S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh2 << 32);
+                S.F[2 * (int64_t)v + 1] = nS;
+                if (a.lds_bitmap) atomicOr(&bm[v >> 5], 1u << (v & 31));
+                if (nd) {
+                    L.fh[slv] = nh2;
+                    L.fS[slv] = nS;
+                    atomicOr(&L.fm[slv], FM_COMMITTED);
+                }
+            }
+            const u64 zm = ballot(ok && v == P.z);
+            if (zm) {
+                const int zl = __ffsll((long long)zm) - 1;
+                const u32 zh_new = (u32)rl32((int)nh2, zl);
+                const int32_t zt = rl32(t, zl);
+                if (opt == OPT_SH) { if (zh_new < zh) o.t_arr = zt; }
+                else o.t_arr = zt;
                 zh = zh_new;
-                zS = zS_new;
+                zS = rl64(nS, zl);
                 zhit = true;
             }
-            if (any_commit) fw_used = true;
-            __syncthreads();
-            // step 4: arcs of this tick
-#pragma unroll
-            for (int j = 0; j < kE; ++j) {
-                if (j < jlo || j > jhi) continue;
-                int off = j * kWave + l;
-                bool act = off >= gs && off < ge;
-                bool rec = false;
-                u64 w0 = 0;
-                if (act && rt[j] && L.rt_ok[roff[j]]) {
-                    u32 d = L.rt_d[roff[j]];
-                    if (!P.level || hu[j] + 1 == d) {
-                        rec = true;
-                        w0 = (u64)(u32)(b0 + off) | ((u64)hu[j] << 32) | ((u64)d << 48);
-                    }
-                }
-                u64 m = ballot(rec);
-                if (m) {
-                    int64_t pos = o.arcs + mbcnt(m);
-                    if (rec && pos < a.sl.cap) { S.arcs[2 * pos] = w0; S.arcs[2 * pos + 1] = su[j]; }
-                    o.arcs += __popcll(m);
-                }
+            // arcs of the segment
+            const bool okr = single ? ok : (__shfl((int)ok, rsl) != 0);
+            const bool rec = tight && okr && keep;
+            const u64 m = ballot(rec);
+            if (m) {
+                if (rec) put_arc(S, a.sl.cap, o.arcs + mbcnt(m), v, t, (u32)(b0 + l), u, s_u, h_u, d);
+                o.arcs += __popcll(m);
             }
-            o.swept = (b0 + ge) - P.lo;
-            if (o.flags & REC_HOPS_LIMIT) return;
             if (o.arcs > a.sl.cap) { o.flags |= REC_ARCS_LIMIT; return; }
-            if (zhit && opt != OPT_SH) done = true;
-            gs = ge;
+            if (zhit && opt != OPT_SH) {
+                done = true;
+                const u64 after = ballot(in && tid >= cut);
+                o.swept = b0 + (after ? (__ffsll((long long)after) - 1) : nbat) - P.lo;
+            }
+            ta = tb;
         }
+        if (!done) o.swept = (b0 + nbat) - P.lo;
         __syncthreads();
         b0 += nbat;
     }
@@ -624,8 +659,39 @@ struct RevCtx {
     u64 sigma;
     u32 dsh;
     int64_t touched_n;
+    int64_t edges_n;   // arcs with a non-zero dependency (touched temporal edges)
     bool ovf;
+    bool alive_all;    // alive hash overflowed: treat every node as alive
 };
+
+// alive set: nodes with a non-zero dependency accumulator for this pair
+__device__ __forceinline__ bool alive_test(const LaunchArgs &a, const u32 *bm, const RevCtx &X, int32_t v) {
+    if (a.lds_bitmap) return bm_test(bm, v);
+    if (X.alive_all) return true;
+    u32 sl = (((u32)v) * 2654435761u) >> (32 - 9);
+    for (int it = 0; it < kAliveN; ++it) {
+        u32 k = bm[sl];
+        if (k == 0) return false;
+        if (k == (u32)v + 1) return true;
+        sl = (sl + 1) & (kAliveN - 1);
+    }
+    return false;
+}
+__device__ __forceinline__ bool alive_set(const LaunchArgs &a, u32 *bm, int32_t v) {
+    if (a.lds_bitmap) { atomicOr(&bm[v >> 5], 1u << (v & 31)); return true; }
+    u32 sl = (((u32)v) * 2654435761u) >> (32 - 9);
+    for (int it = 0; it < kAliveN / 2; ++it) {
+        u32 k = bm[sl];
+        if (k == (u32)v + 1) return true;
+        if (k == 0) {
+            u32 old = atomicCAS(&bm[sl], 0u, (u32)v + 1);
+            if (old == 0u || old == (u32)v + 1) return true;
+            continue;
+        }
+        sl = (sl + 1) & (kAliveN - 1);
+    }
+    return false;  // too full: the caller switches to "everything alive"
+}
 
 __device__ __forceinline__ void rev_contrib(const LaunchArgs &a, const Pair &P, const Slab &S,
                                             RevCtx &X, bool act, u64 B, u64 tc, int32_t v, u32 k) {
@@ -645,6 +711,7 @@ __device__ __forceinline__ void rev_contrib(const LaunchArgs &a, const Pair &P, 
         if (a.edge_f) a.edge_f[P.qout * a.g.m + k] = (double)na / (double)X.sigma;
     }
     if (ballot(wrap)) X.ovf = true;
+    X.edges_n += __popcll(ballot(act && B != 0));
     u64 m = ballot(first);
     if (m) {
         int64_t pos = X.touched_n + mbcnt(m);
@@ -661,18 +728,24 @@ __device__ __forceinline__ u64 head_B(const Pair &P, const RevCtx &X, int32_t v,
     return acc;
 }
 
-__device__ void rev_big_tick(const LaunchArgs &a, const Pair &P, const Slab &S, RevCtx &X,
-                             int64_t a0, int64_t a1) {
+// a tick with more arcs than one batch: heads first (all read state older
+// than the tick), then level resets and additions at the tails
+__device__ void rev_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, RevCtx &X,
+                              int64_t a0, int64_t a1) {
     const int l = lane_id();
-    // pass A: heads read state older than this tick
     for (int64_t sb = a0; sb < a1; sb += kWave) {
         int64_t i = sb + l;
-        bool act = i < a1;
-        u64 w0 = act ? S.arcs[2 * i] : 0, tc = act ? S.arcs[2 * i + 1] : 0;
-        u32 k = (u32)w0, hl = (u32)(w0 >> 48);
-        int32_t v = act ? a.g.V[k] : 0;
-        u64 B = 0;
+        bool inr = i < a1;
+        u64 mm = inr ? S.arcm[i] : 0;
+        int32_t v = (int32_t)(u32)mm;
+        bool act = inr && (v == P.z || alive_test(a, bm, X, v));
+        u64 B = 0, tc = 0;
+        u32 k = 0;
         if (act) {
+            u64 x0 = S.arcx[3 * i];
+            tc = S.arcx[3 * i + 1];
+            u32 hl = (u32)(S.arcx[3 * i + 2] >> 16) & 0xFFFFu;
+            k = (u32)x0;
             bool valid = false;
             u32 lvl = 0;
             u64 acc = 0;
@@ -681,20 +754,18 @@ __device__ void rev_big_tick(const LaunchArgs &a, const Pair &P, const Slab &S, 
                 if ((u32)th == P.tag) { valid = true; lvl = (u32)(th >> 32) & 0xFFFFu; acc = ld_agent(&S.R[2 * (int64_t)v + 1]); }
             }
             B = head_B(P, X, v, hl, valid, lvl, acc);
-            S.XS[i - a0] = B;
         }
+        if (inr) S.XS[i - a0] = B;
         rev_contrib(a, P, S, X, act, B, tc, v, k);
     }
     __syncthreads();
-    // pass R: reset stale tail entries
     for (int64_t sb = a0; sb < a1; sb += kWave) {
         int64_t i = sb + l;
         if (i >= a1) continue;
         u64 B = S.XS[i - a0];
         if (!B) continue;
-        u64 w0 = S.arcs[2 * i];
-        u32 k = (u32)w0, tl = (u32)(w0 >> 32) & 0xFFFFu;
-        int32_t u = a.g.U[k];
+        int32_t u = (int32_t)(S.arcx[3 * i] >> 32);
+        u32 tl = (u32)S.arcx[3 * i + 2] & 0xFFFFu;
         u32 want = P.level ? tl : 0u;
         u64 th = ld_agent(&S.R[2 * (int64_t)u]);
         if ((u32)th != P.tag || ((u32)(th >> 32) & 0xFFFFu) != want) {
@@ -703,47 +774,53 @@ __device__ void rev_big_tick(const LaunchArgs &a, const Pair &P, const Slab &S, 
         }
     }
     __syncthreads();
-    // pass C: add
+    bool full = false;
     for (int64_t sb = a0; sb < a1; sb += kWave) {
         int64_t i = sb + l;
         if (i >= a1) continue;
         u64 B = S.XS[i - a0];
         if (!B) continue;
-        int32_t u = a.g.U[(u32)S.arcs[2 * i]];
+        int32_t u = (int32_t)(S.arcx[3 * i] >> 32);
         atomicAdd((unsigned long long *)&S.R[2 * (int64_t)u + 1], (unsigned long long)B);
+        if (!alive_set(a, bm, u)) full = true;
     }
+    if (ballot(full)) X.alive_all = true;
     __syncthreads();
 }
 
-__device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, RevLds &L, u32 &rstamp,
-                        int64_t narcs, RevCtx &X) {
+__device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t bmw, RevLds &L,
+                        u32 &stamp, int64_t narcs, RevCtx &X) {
     const int l = lane_id();
-    const int32_t *U = a.g.U, *V = a.g.V, *T = a.g.T;
+    // the alive set starts empty
+    const int64_t words = a.lds_bitmap ? bmw : kAliveN;
+    for (int64_t w = l; w < words; w += kWave) bm[w] = 0;
+    X.alive_all = false;
+    __syncthreads();
     int64_t ac = narcs;
     while (ac > 0) {
-        int nb = ac < kC ? (int)ac : kC;
-        int64_t blo = ac - nb;
-        u64 w0[kE], tc[kE];
-        int32_t uu[kE], vv[kE], tt[kE];
-        bool in[kE];
+        const int nb = ac < kC ? (int)ac : kC;
+        const int64_t blo = ac - nb;
+        int32_t vv[kE], tt[kE];
+        bool in[kE], al[kE];
+        bool any = false;
 #pragma unroll
         for (int j = 0; j < kE; ++j) {
             int off = j * kWave + l;
             in[j] = off < nb;
-            w0[j] = in[j] ? S.arcs[2 * (blo + off)] : 0;
-            tc[j] = in[j] ? S.arcs[2 * (blo + off) + 1] : 0;
-            u32 k = (u32)w0[j];
-            uu[j] = in[j] ? U[k] : 0;
-            vv[j] = in[j] ? V[k] : 0;
-            tt[j] = in[j] ? T[k] : INT32_MIN;
+            u64 mm = in[j] ? S.arcm[blo + off] : 0;
+            vv[j] = (int32_t)(u32)mm;
+            tt[j] = in[j] ? (int32_t)(mm >> 32) : INT32_MIN;
+            al[j] = in[j] && (vv[j] == P.z || alive_test(a, bm, X, vv[j]));
+            if (ballot(al[j])) any = true;
         }
+        // no arc of this batch can carry a dependency: nothing to do
+        if (!any) { ac = blo; continue; }
         // cut at a tick boundary at the low end
         int cut = 0;
         if (blo > 0) {
             int32_t t_first = rl32(tt[0], 0);
-            int32_t t_before = T[(u32)S.arcs[2 * (blo - 1)]];
+            int32_t t_before = (int32_t)(S.arcm[blo - 1] >> 32);
             if (t_before == t_first) {
-                // first offset whose time differs from t_first
                 int firstdiff = -1;
 #pragma unroll
                 for (int j = 0; j < kE; ++j) {
@@ -751,67 +828,66 @@ __device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, RevLd
                     if (firstdiff < 0 && m) firstdiff = j * kWave + (__ffsll((long long)m) - 1);
                 }
                 if (firstdiff < 0) {
-                    // the whole batch is one tick that continues below: big tick
                     int64_t a0 = 0;
                     for (int64_t i = blo - kWave; ; i -= kWave) {
                         int64_t idx = i + l;
-                        bool ok = idx >= 0 && idx < blo;
-                        bool diff = ok && T[(u32)S.arcs[2 * idx]] != t_first;
+                        bool okk = idx >= 0 && idx < blo;
+                        bool diff = okk && (int32_t)(S.arcm[idx] >> 32) != t_first;
                         u64 m = ballot(diff);
                         if (m) { a0 = i + (63 - __clzll((long long)m)) + 1; break; }
                         if (i <= 0) { a0 = 0; break; }
                     }
-                    rev_big_tick(a, P, S, X, a0, ac);
+                    rev_long_tick(a, P, S, bm, X, a0, ac);
                     ac = a0;
                     continue;
                 }
                 cut = firstdiff;
             }
         }
-        // active: offsets [cut, nb)
-#pragma unroll
-        for (int j = 0; j < kE; ++j) {
-            int off = j * kWave + l;
-            in[j] = in[j] && off >= cut;
-        }
-        // tick starts (ascending offsets) within [cut, nb)
+        // arcs of the batch: tails and counts
+        u64 tc[kE];
+        u32 kk[kE], tl[kE], hl[kE];
+        int32_t uu[kE];
         u64 gm[kE];
-#pragma unroll
-        for (int j = 0; j < kE; ++j) {
-            int32_t tp = __shfl_up(tt[j], 1);
-            int off = j * kWave + l;
-            if (l == 0) tp = j > 0 ? rl32(tt[j - 1], kWave - 1) : INT32_MIN;
-            gm[j] = ballot(in[j] && (off == cut || tt[j] != tp));
-        }
-        // pre-gather head and tail reverse state
         bool hval[kE], tval[kE];
         u32 hlvl[kE], tlvl[kE];
         u64 hacc[kE], tacc[kE];
 #pragma unroll
         for (int j = 0; j < kE; ++j) {
+            int off = j * kWave + l;
+            in[j] = in[j] && off >= cut;
+            al[j] = al[j] && in[j];
+            int32_t tp = __shfl_up(tt[j], 1);
+            if (l == 0) tp = j > 0 ? rl32(tt[j - 1], kWave - 1) : INT32_MIN;
+            gm[j] = ballot(in[j] && (off == cut || tt[j] != tp));
+            u64 x0 = in[j] ? S.arcx[3 * (blo + off)] : 0;
+            tc[j] = in[j] ? S.arcx[3 * (blo + off) + 1] : 0;
+            u64 x2 = in[j] ? S.arcx[3 * (blo + off) + 2] : 0;
+            kk[j] = (u32)x0;
+            uu[j] = (int32_t)(x0 >> 32);
+            tl[j] = (u32)x2 & 0xFFFFu;
+            hl[j] = (u32)(x2 >> 16) & 0xFFFFu;
             hval[j] = false; hlvl[j] = 0; hacc[j] = 0;
             tval[j] = false; tlvl[j] = 0; tacc[j] = 0;
-            if (in[j] && vv[j] != P.z) {
+            if (al[j] && vv[j] != P.z) {
                 u64 th = ld_agent(&S.R[2 * (int64_t)vv[j]]);
                 if ((u32)th == P.tag) { hval[j] = true; hlvl[j] = (u32)(th >> 32) & 0xFFFFu; hacc[j] = ld_agent(&S.R[2 * (int64_t)vv[j] + 1]); }
             }
-            if (in[j]) {
+            if (in[j] && alive_test(a, bm, X, uu[j])) {
                 u64 th = ld_agent(&S.R[2 * (int64_t)uu[j]]);
                 if ((u32)th == P.tag) { tval[j] = true; tlvl[j] = (u32)(th >> 32) & 0xFFFFu; tacc[j] = ld_agent(&S.R[2 * (int64_t)uu[j] + 1]); }
             }
         }
-        rstamp += 1;
+        stamp += 1;
         bool used = false;
         __syncthreads();
-        // ticks in descending time: walk tick starts from the top
         int ge = nb;
         while (ge > cut) {
-            // start of the tick that ends at ge: highest tick start < ge
             int gs = cut;
             {
                 int pos = ge - 1;
                 for (int j = pos >> 6; j >= 0; --j) {
-                    u64 m = (j == 0) ? gm[0] : (j == 1 ? gm[1] : (j == 2 ? gm[2] : gm[3]));
+                    u64 m = pick4(gm, j);
                     int b = (j == (pos >> 6)) ? (pos & 63) : 63;
                     m &= (b == 63) ? kUMax : ((2ull << b) - 1ull);
                     if (m) { gs = j * kWave + 63 - __clzll((long long)m); break; }
@@ -819,50 +895,49 @@ __device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, RevLd
             }
             const int jlo = gs >> 6, jhi = (ge - 1) >> 6;
             u64 Bv[kE];
-            // step A: heads
+            bool anyB = false;
 #pragma unroll
             for (int j = 0; j < kE; ++j) {
                 Bv[j] = 0;
                 if (j < jlo || j > jhi) continue;
                 int off = j * kWave + l;
-                bool act = off >= gs && off < ge;
-                if (act) {
+                bool inr = off >= gs && off < ge;
+                bool act = false;
+                if (inr) {
                     bool valid = hval[j];
                     u32 lvl = hlvl[j];
                     u64 acc = hacc[j];
+                    act = al[j];
                     if (used && vv[j] != P.z) {
-                        int sl = tab_find(L.tb_key, rstamp, (u32)vv[j]);
-                        if (sl >= 0) { u32 x = L.tb_lvl[sl]; valid = (x >> 31) != 0; lvl = x & 0xFFFFu; acc = L.tb_acc[sl]; }
+                        int sl = tab_find(L.tb_key, stamp, (u32)vv[j]);
+                        if (sl >= 0) { u32 x = L.tb_lvl[sl]; valid = (x >> 31) != 0; lvl = x & 0xFFFFu; acc = L.tb_acc[sl]; act = true; }
                     }
-                    Bv[j] = head_B(P, X, vv[j], (u32)(w0[j] >> 48), valid, lvl, acc);
+                    if (act) Bv[j] = head_B(P, X, vv[j], hl[j], valid, lvl, acc);
                 }
-                rev_contrib(a, P, S, X, act, Bv[j], tc[j], vv[j], (u32)w0[j]);
-            }
-            // step T1: tail entries
-            bool anyB = false;
-            int tsl[kE];
-#pragma unroll
-            for (int j = 0; j < kE; ++j) {
-                tsl[j] = -1;
-                if (j < jlo || j > jhi) continue;
-                if (Bv[j]) {
-                    int fresh;
-                    tsl[j] = tab_insert(L.tb_key, rstamp, (u32)uu[j], &fresh);
-                    if (fresh) {
-                        L.tb_lvl[tsl[j]] = tval[j] ? ((tlvl[j] & 0xFFFFu) | 0x80000000u) : 0u;
-                        L.tb_acc[tsl[j]] = tval[j] ? tacc[j] : 0ull;
-                    }
-                }
+                if (ballot(act)) rev_contrib(a, P, S, X, act, Bv[j], tc[j], vv[j], kk[j]);
                 if (ballot(Bv[j] != 0)) anyB = true;
             }
             if (anyB) {
                 used = true;
+                int tsl[kE];
+#pragma unroll
+                for (int j = 0; j < kE; ++j) {
+                    tsl[j] = -1;
+                    if (j < jlo || j > jhi) continue;
+                    if (Bv[j]) {
+                        int fresh;
+                        tsl[j] = tab_insert(L.tb_key, stamp, (u32)uu[j], &fresh);
+                        if (fresh) {
+                            L.tb_lvl[tsl[j]] = tval[j] ? ((tlvl[j] & 0xFFFFu) | 0x80000000u) : 0u;
+                            L.tb_acc[tsl[j]] = tval[j] ? tacc[j] : 0ull;
+                        }
+                    }
+                }
                 __syncthreads();
-                // step T2: level resets (identical writes for one node)
 #pragma unroll
                 for (int j = 0; j < kE; ++j) {
                     if (tsl[j] < 0) continue;
-                    u32 want = P.level ? ((u32)(w0[j] >> 32) & 0xFFFFu) : 0u;
+                    u32 want = P.level ? tl[j] : 0u;
                     u32 x = L.tb_lvl[tsl[j]];
                     if (!(x >> 31) || (x & 0xFFFFu) != want) {
                         L.tb_lvl[tsl[j]] = want | 0x80000000u;
@@ -870,20 +945,22 @@ __device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, RevLd
                     }
                 }
                 __syncthreads();
+                bool full = false;
 #pragma unroll
                 for (int j = 0; j < kE; ++j) {
                     if (tsl[j] < 0) continue;
                     atomicAdd((unsigned long long *)&L.tb_acc[tsl[j]], (unsigned long long)Bv[j]);
+                    if (!alive_set(a, bm, uu[j])) full = true;
                 }
+                if (ballot(full)) X.alive_all = true;
                 __syncthreads();
             }
             ge = gs;
         }
-        // write back the tail table
         if (used) {
             for (int sl = l; sl < kFwN; sl += kWave) {
                 u64 key = L.tb_key[sl];
-                if ((u32)(key >> 32) != rstamp) continue;
+                if ((u32)(key >> 32) != stamp) continue;
                 u32 node = (u32)key;
                 u32 x = L.tb_lvl[sl];
                 S.R[2 * (int64_t)node] = (u64)P.tag | ((u64)(x & 0xFFFFu) << 32);
@@ -922,8 +999,9 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
         u64 st = (u64)R.stream + (u64)STREAMS_PER_GRAPH * (u64)P.g;
         u64 s = __umul64hi(rng_word(R.seed, st, (u64)idx, 0), (u64)ng);
         u64 zp = __umul64hi(rng_word(R.seed, st, (u64)idx, 1), (u64)(ng - 1));
-        P.s = (int32_t)s;
-        P.z = (int32_t)(zp + (zp >= s ? 1 : 0));
+        // pairs are drawn over input ids, then mapped to internal ids
+        P.s = a.g.perm[noff + (int32_t)s] - noff;
+        P.z = a.g.perm[noff + (int32_t)(zp + (zp >= s ? 1 : 0))] - noff;
         if (R.c > 0) P.lam = rng_word(R.seed, (u64)STREAM_RADE + (u64)STREAMS_PER_GRAPH * (u64)P.g, (u64)idx, 0);
     }
     P.noff = a.g.seg_noff[P.g];
@@ -933,7 +1011,7 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
     P.level = (P.opt == OPT_SH || P.opt == OPT_SFM);
 }
 
-__global__ void __launch_bounds__(64) k_sweep(LaunchArgs a) {
+__global__ void __launch_bounds__(64, 5) k_sweep(LaunchArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int l = lane_id();
     const int64_t slab = blockIdx.x;
@@ -944,17 +1022,17 @@ __global__ void __launch_bounds__(64) k_sweep(LaunchArgs a) {
     S.AG = a.sl.AG + slab * a.sl.nmax * 2;
     S.AGF = a.sl.AGF + slab * a.sl.nmax;
     S.touched = a.sl.touched + slab * a.sl.nmax;
-    S.arcs = a.sl.arcs + slab * a.sl.cap * 2;
+    S.arcm = a.sl.arcs + slab * a.sl.cap * 4;
+    S.arcx = S.arcm + a.sl.cap;
     S.XS = a.sl.XS + slab * a.sl.gmax * 2;
     S.hdr = a.sl.hdr + slab * 4;
     TabLds &tab = *reinterpret_cast<TabLds *>(lds_raw);
     u32 *bm = reinterpret_cast<u32 *>(lds_raw + sizeof(TabLds));
     const int64_t bmw = a.lds_bitmap ? (a.sl.nmax + 31) / 32 : 0;
-    // stamped tables start empty
-    for (int i = l; i < kFwN; i += kWave) { tab.f.fw_key[i] = 0; }
+    for (int i = l; i < kFwN; i += kWave) { tab.r.tb_key[i] = 0; }
     u32 serial = S.hdr[0];
     u32 agstamp = S.hdr[1];
-    u32 stamp = 1;  // one counter for both table uses (they share LDS)
+    u32 stamp = 1;  // reverse table stamps (0 = empty)
     __syncthreads();
     for (;;) {
         u32 qq = 0;
@@ -989,7 +1067,11 @@ __global__ void __launch_bounds__(64) k_sweep(LaunchArgs a) {
                 if (a.lds_bitmap) bm[P.s >> 5] |= 1u << (P.s & 31);
             }
             __syncthreads();
-            forward(a, P, S, bm, tab.f, stamp, agstamp, fo);
+            forward(a, P, S, bm, tab.f, agstamp, fo);
+            __syncthreads();
+            // the reverse table reuses the forward's LDS: empty it
+            for (int i = l; i < kFwN; i += kWave) { tab.r.tb_key[i] = 0; }
+            stamp = 1;
             __syncthreads();
         }
         u32 flags = fo.flags;
@@ -998,9 +1080,9 @@ __global__ void __launch_bounds__(64) k_sweep(LaunchArgs a) {
         if (reach && sigma == kUMax) flags |= REC_OVERFLOW;
         bool do_rev = reach && !(flags & REC_OVERFLOW);
         RevCtx X;
-        X.sigma = sigma; X.dsh = fo.zh; X.touched_n = 0; X.ovf = false;
+        X.sigma = sigma; X.dsh = fo.zh; X.touched_n = 0; X.edges_n = 0; X.ovf = false; X.alive_all = false;
         if (do_rev) {
-            reverse(a, P, S, tab.r, stamp, fo.arcs, X);
+            reverse(a, P, S, bm, bmw, tab.r, stamp, fo.arcs, X);
             __syncthreads();
             // flow conservation at the origin: B(origin) must equal sigma
             u64 th = ld_agent(&S.R[2 * (int64_t)P.s]);
@@ -1046,6 +1128,8 @@ __global__ void __launch_bounds__(64) k_sweep(LaunchArgs a) {
             if (reach) atomicAdd((unsigned long long *)&a.stats[3], 1ull);
             if (flags & REC_HOPS_LIMIT) atomicAdd((unsigned long long *)&a.stats[4], 1ull);
             if (flags & REC_SELFCHECK) atomicAdd((unsigned long long *)&a.stats[6], 1ull);
+            atomicAdd((unsigned long long *)&a.stats[7], (unsigned long long)X.touched_n);
+            atomicAdd((unsigned long long *)&a.stats[8], (unsigned long long)X.edges_n);
             if (flags & REC_ARCS_LIMIT) {
                 atomicAdd((unsigned long long *)&a.stats[5], 1ull);
                 int pos = atomicAdd(&a.retry[0], 1);
@@ -1122,4 +1206,10 @@ hipError_t mantra_launch_fill(mantra::u64 *p, mantra::u64 val, int64_t n, hipStr
     return hipGetLastError();
 }
 size_t mantra_tab_lds_bytes(void) { return sizeof(mantra::TabLds); }
+// resident sweep workgroups per CU for a given dynamic LDS size
+int mantra_sweep_occupancy(size_t lds_bytes) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mantra::k_sweep, 64, lds_bytes) != hipSuccess) return 0;
+    return nb;
+}
 }
