@@ -168,13 +168,15 @@ int mantra_serve_config(mantra_graph *g, uint64_t mem_budget_bytes, int32_t max_
 int mantra_set_launch(mantra_graph *g, int32_t n_slabs, int64_t arc_cap);
 
 /* Work and timing of the last blocking call on g: device time of the sweep
- * kernel launches (HIP events on the graph's stream), their count, and the
+ * kernel launches (HIP events on the graph's stream), their count, the
  * totals over its pairs of swept window edges, recorded appearance-DAG arcs,
- * touched nodes (N(v) > 0) and touched temporal edges (N(e) > 0).  Any
- * pointer may be NULL. */
+ * touched nodes (N(v) > 0) and touched temporal edges (N(e) > 0), and the
+ * load balance of the persistent grid (busy time of its workgroups over
+ * workgroups x launch span, averaged over launch time).  Any pointer may be
+ * NULL. */
 int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launches,
                        int64_t *window_edges, int64_t *arcs, int64_t *touched_nodes,
-                       int64_t *touched_edges);
+                       int64_t *touched_edges, double *balance);
 
 const char *mantra_last_error(void);
 

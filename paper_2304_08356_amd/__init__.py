@@ -92,11 +92,12 @@ class Graph:
 
     def last_timing(self):
         ms = ctypes.c_double(); nl = ctypes.c_int64(); w = ctypes.c_int64(); a = ctypes.c_int64()
-        tn = ctypes.c_int64(); te = ctypes.c_int64()
+        tn = ctypes.c_int64(); te = ctypes.c_int64(); bal = ctypes.c_double()
         _lib.check(_lib._lib.mantra_last_timing(self._h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(w),
-                                                ctypes.byref(a), ctypes.byref(tn), ctypes.byref(te)))
+                                                ctypes.byref(a), ctypes.byref(tn), ctypes.byref(te),
+                                                ctypes.byref(bal)))
         return {"sweep_ms": ms.value, "launches": nl.value, "window_edges": w.value, "arcs": a.value,
-                "touched_nodes": tn.value, "touched_edges": te.value}
+                "touched_nodes": tn.value, "touched_edges": te.value, "balance": bal.value}
 
     def count_pairs(self, opt, s, z, t0=0, t1=T_MAX, graph=None, node_f=False, edge_f=False):
         """Records (and optionally dense per-pair f over nodes / input edges)
@@ -164,8 +165,10 @@ class Ticket:
         rc = _lib._lib.mantra_poll(self.id, ctypes.byref(res), int(timeout_ms))
         if rc == _lib.PENDING:
             return None
+        if rc != _lib.E_INVALID:  # the ticket finished (and is consumed)
+            self.result = res.to_dict()
+            self.result["rc"] = rc
         _lib.check(rc)
-        self.result = res.to_dict()
         return self.result
 
 

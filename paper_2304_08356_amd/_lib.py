@@ -18,6 +18,7 @@ SH, FM, SFM, PFM = 0, 1, 2, 3
 OPT = {"sh": SH, "fm": FM, "sfm": SFM, "pfm": PFM}
 
 OK, PENDING = 0, 1
+E_INVALID = -1
 STATUS = {0: "OK", 1: "PENDING", -1: "E_INVALID", -2: "E_NODEV", -3: "E_OOM", -4: "E_OVERFLOW",
           -5: "E_TOO_LARGE", -6: "E_INTERNAL", -7: "E_LIMIT"}
 
@@ -62,7 +63,7 @@ SIGNATURES = {
     "mantra_poll": (I32, [U64, P, I32]),
     "mantra_serve_config": (I32, [P, U64, I32]),
     "mantra_set_launch": (I32, [P, I32, I64]),
-    "mantra_last_timing": (I32, [P, P, P, P, P, P, P]),
+    "mantra_last_timing": (I32, [P, P, P, P, P, P, P, P]),
     "mantra_last_error": (ctypes.c_char_p, []),
 }
 

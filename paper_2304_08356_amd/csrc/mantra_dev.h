@@ -12,6 +12,9 @@ constexpr int kWave = 64;
 #define MANTRA_KE 1
 #endif
 constexpr int kE = MANTRA_KE;        // edges per lane per batch
+#ifndef MANTRA_SWEEP_WPS
+#define MANTRA_SWEEP_WPS 5               // sweep waves per SIMD the register budget is cut for
+#endif
 constexpr int kC = kWave * kE;       // batch capacity (edges or arcs)
 constexpr int kFwN = 2 * kC;         // LDS forwarding / tail table slots
 constexpr int kFwBits = kFwN == 128 ? 7 : (kFwN == 256 ? 8 : (kFwN == 512 ? 9 : 10));
@@ -51,11 +54,12 @@ struct DevReq {
     u64 seed;
     int32_t stream;      // STREAM_PAIR or STREAM_BOOT (RNG mode)
     int32_t graph;       // -1: pairs spread over all graphs (packed RNG mode), else graph id
-    int64_t base;        // pair index of the first pair of this slice within its stream
+    int64_t base;        // stream index of the slice's first pair (see per_graph)
     int64_t qoff;        // first launch-pair slot of this request
     int64_t count;       // pairs of this request in the launch
-    int64_t per_graph;   // packed RNG mode: pairs per graph
+    int64_t per_graph;   // graph = -1: index i is pair i % per_graph of graph i / per_graph
     double *Bsum, *Wsum, *Rsum, *Esum; // accumulators (device), may be null
+    u64 *rstat;          // per-request counters: overflow, reachable, hops limit, window edges, arcs; may be null
 };
 
 struct DevSlabs {
@@ -84,7 +88,7 @@ struct LaunchArgs {
     double *node_f;              // dense per-pair node output [npairs][n_total] or null
     double *edge_f;              // dense per-pair edge output [npairs][m] or null
     u32 *work;                   // work counter, zero at launch
-    u64 *stats;                  // [16] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck, touched nodes, touched edges
+    u64 *stats;                  // [16] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck, touched nodes, touched edges, slab busy ticks, last end, ~first start
     int32_t *retry;              // [1 + npairs] pairs whose arcs did not fit
 };
 

@@ -1,43 +1,15 @@
 // Host runtime of the temporal-betweenness library: graph residency, the
-// per-slab device state, launches of the sweep kernel, the progressive
-// sampling driver of Algorithm 1, and the serving scheduler.
+// per-slab device state, launches of the sweep kernel and the progressive
+// sampling driver of Algorithm 1 (blocking calls and the serving scheduler
+// share the per-request state machine defined here).
 
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-#include <string.h>
-#include <math.h>
-#include <stdio.h>
-#include <stdarg.h>
-#include <algorithm>
-#include <atomic>
-#include <chrono>
-#include <condition_variable>
-#include <deque>
-#include <map>
-#include <memory>
-#include <mutex>
-#include <string>
-#include <thread>
-#include <vector>
+#include "mantra_int.h"
 
-#include "mantra_dev.h"
-#include "../../include/mantra.h"
+namespace mantra {
 
-using namespace mantra;
+thread_local std::string g_err;
 
-extern "C" {
-hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
-hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st);
-hipError_t mantra_launch_fill(mantra::u64 *p, mantra::u64 val, int64_t n, hipStream_t st);
-size_t mantra_tab_lds_bytes(void);
-int mantra_sweep_occupancy(size_t lds_bytes);
-}
-
-// ------------------------------------------------------------------ errors
-
-static thread_local std::string g_err;
-
-static int fail(int code, const char *fmt, ...) {
+int fail(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -45,21 +17,6 @@ static int fail(int code, const char *fmt, ...) {
     va_end(ap);
     g_err = buf;
     return code;
-}
-
-#define HIPCHK(expr)                                                                      \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess) {                                                           \
-            if (e_ == hipErrorOutOfMemory) return fail(MANTRA_E_OOM, "%s: %s", #expr,     \
-                                                       hipGetErrorString(e_));            \
-            return fail(MANTRA_E_INTERNAL, "%s: %s", #expr, hipGetErrorString(e_));       \
-        }                                                                                 \
-    } while (0)
-
-template <class T>
-static hipError_t dalloc(T **p, size_t count) {
-    return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
 }
 
 // ------------------------------------------------------------------ bounds
@@ -103,73 +60,6 @@ static int64_t next(int64_t prev) {
     return x > prev ? x : prev + 1;
 }
 }  // namespace bnd
-
-// ------------------------------------------------------------------ graph
-
-struct SlabPool {
-    int nslabs = 0;
-    int64_t nmax = 0, cap = 0, gmax = 0;
-    u64 *F = nullptr, *R = nullptr, *N = nullptr, *AG = nullptr, *arcs = nullptr, *XS = nullptr;
-    u32 *AGF = nullptr, *hdr = nullptr;
-    int32_t *touched = nullptr;
-    void release() {
-        hipFree(F); hipFree(R); hipFree(N); hipFree(AG); hipFree(arcs); hipFree(XS);
-        hipFree(AGF); hipFree(hdr); hipFree(touched);
-        F = R = N = AG = arcs = XS = nullptr;
-        AGF = hdr = nullptr;
-        touched = nullptr;
-        nslabs = 0;
-    }
-    DevSlabs view() const {
-        DevSlabs s;
-        s.F = F; s.R = R; s.N = N; s.AG = AG; s.AGF = AGF; s.touched = touched; s.arcs = arcs;
-        s.XS = XS; s.hdr = hdr; s.nmax = nmax; s.cap = cap; s.gmax = gmax;
-        return s;
-    }
-};
-
-struct ServeState;
-
-struct mantra_graph {
-    int device = 0;
-    int32_t n_total = 0, G = 1, nmax = 0;
-    int64_t m_in = 0, m = 0, ndup = 0, gmax = 1;
-    int32_t tmin = 0, tmax = 0;
-    std::vector<int32_t> seg_noff;
-    std::vector<int64_t> seg_eoff;
-    std::vector<int64_t> in2k;  // input edge index -> internal edge id
-    std::vector<int32_t> perm;  // input node id (global) -> internal id, hubs first
-    std::vector<int32_t> iperm; // internal id -> input id
-    int32_t *dU = nullptr, *dV = nullptr, *dT = nullptr, *dout_t = nullptr, *din_t = nullptr,
-            *dseg_noff = nullptr, *dperm = nullptr;
-    int64_t *dout_off = nullptr, *din_off = nullptr, *dseg_eoff = nullptr;
-    hipStream_t st = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    SlabPool pool, pool_big;
-    int user_slabs = 0;
-    int64_t user_cap = 0;
-    // misc device buffers
-    u32 *dwork = nullptr;
-    u64 *dstats = nullptr;
-    int32_t *dretry = nullptr;
-    int64_t retry_cap = 0;
-    double *dpart = nullptr;
-    int part_blocks = 0, part_c = -1;
-    DevReq *dreqs = nullptr;
-    int dreq_cap = 0;
-    std::mutex mu;  // one blocking call at a time per graph
-    // timing of the last blocking call
-    double last_ms = 0;
-    int64_t last_launches = 0, last_W = 0, last_arcs = 0, last_tn = 0, last_te = 0;
-    ServeState *serve = nullptr;
-    DevGraph dev() const {
-        DevGraph d;
-        d.U = dU; d.V = dV; d.T = dT; d.out_off = dout_off; d.out_t = dout_t; d.in_off = din_off;
-        d.in_t = din_t; d.seg_eoff = dseg_eoff; d.seg_noff = dseg_noff; d.n_total = n_total;
-        d.G = G; d.m = m; d.perm = dperm;
-        return d;
-    }
-};
 
 static int pick_device(int *dev) {
     int cnt = 0;
@@ -361,7 +251,23 @@ static size_t lds_bytes(int64_t nmax) {
     return b;
 }
 
-static int auto_slabs(const mantra_graph *g) {
+// device bytes of one slab's per-node state (F, R, AG: 16 B; N: 8 B; AGF,
+// touched: 4 B) and its big-tick scratch
+static size_t slab_state_bytes(const mantra_graph *g) {
+    return (size_t)g->nmax * 64 + (size_t)g->gmax * 16 + 16;
+}
+
+// device memory and the share of it the slab pool (state and arc buffers)
+// may take
+static size_t device_bytes(const mantra_graph *g) {
+    size_t fr = 0, tot = 0;
+    hipSetDevice(g->device);
+    hipMemGetInfo(&fr, &tot);
+    return tot;
+}
+static size_t pool_budget(const mantra_graph *g) { return (size_t)(0.45 * (double)device_bytes(g)); }
+
+int auto_slabs(const mantra_graph *g) {
     if (g->user_slabs > 0) return g->user_slabs;
     hipDeviceProp_t pr;
     hipGetDeviceProperties(&pr, g->device);
@@ -373,7 +279,10 @@ static int auto_slabs(const mantra_graph *g) {
         int by_lds = (int)((160 * 1024) / (lb ? lb : 1));
         per_cu = std::min(8, std::max(1, by_lds));
     }
-    return cus * per_cu;
+    // large graphs: the per-node state in half the pool budget bounds the
+    // number of pairs in flight
+    int64_t by_mem = (int64_t)(pool_budget(g) / 2 / slab_state_bytes(g));
+    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, by_mem));
 }
 
 static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
@@ -403,31 +312,25 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
     return MANTRA_OK;
 }
 
+// arc records (32 B each) per slab: the rest of the pool budget, at most
+// one per edge of the graph
 static int64_t auto_cap(const mantra_graph *g, int nslabs) {
     if (g->user_cap > 0) return g->user_cap;
-    size_t fr = 0, tot = 0;
-    hipMemGetInfo(&fr, &tot);
-    // arcs take at most a quarter of free memory; 16 bytes each
-    int64_t per = (int64_t)(fr / 4 / 16 / (size_t)std::max(1, nslabs));
+    size_t state = slab_state_bytes(g) * (size_t)std::max(1, nslabs);
+    size_t bud = pool_budget(g);
+    size_t left = bud > state ? bud - state : 0;
+    int64_t per = (int64_t)(left / 32 / (size_t)std::max(1, nslabs));
     int64_t cap = std::min<int64_t>(g->m + 1, std::max<int64_t>(per, 1 << 16));
     return std::max<int64_t>(cap, 1024);
 }
 
-// ------------------------------------------------------------------ launches
-
-struct LaunchSpec {
-    std::vector<DevReq> reqs;
-    int64_t npairs = 0;
-    const int32_t *dpg = nullptr, *dps = nullptr, *dpz = nullptr;
-    void *drec = nullptr;
-    double *dnode_f = nullptr, *dedge_f = nullptr;
-};
-
 // launch the sweep over all pairs of spec; re-run pairs whose arcs did not
-// fit with a pool of few slabs and the largest capacity.  Adds the device
-// time of the sweep launches to g->last_ms.
-static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[16]) {
-    if (sp.npairs <= 0) { memset(stats_out, 0, sizeof(u64) * 16); return MANTRA_OK; }
+// fit with a pool of few slabs and the largest capacity
+int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o) {
+    memset(o.st, 0, sizeof o.st);
+    o.ms = 0;
+    o.launches = 0;
+    if (sp.npairs <= 0) return MANTRA_OK;
     hipSetDevice(g->device);
     int ns = auto_slabs(g);
     if ((int64_t)ns > sp.npairs) ns = (int)sp.npairs;
@@ -473,14 +376,17 @@ static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[16]) {
     HIPCHK(hipStreamSynchronize(g->st));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
-    g->last_ms += ms;
-    g->last_launches += 1;
+    o.ms += ms;
+    o.launches += 1;
     u64 st1[16];
     HIPCHK(hipMemcpy(st1, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
     if (nretry > 0) {
         // pairs whose appearance-DAG arcs exceeded the slab capacity
-        int ns2 = std::min<int>(nretry, 64);
+        // pairs whose arcs overflowed get slabs that hold every edge of the
+        // graph, as many as a fifth of device memory allows
         int64_t cap2 = g->m + 1;
+        int64_t fit = (int64_t)(device_bytes(g) / 5 / (slab_state_bytes(g) + (size_t)cap2 * 32));
+        int ns2 = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int>(nretry, 64), fit));
         rc = pool_ensure(g, g->pool_big, ns2, cap2);
         if (rc) return rc;
         std::vector<int32_t> q((size_t)nretry + 1);
@@ -499,8 +405,8 @@ static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[16]) {
         HIPCHK(hipEventRecord(g->ev1, g->st));
         HIPCHK(hipStreamSynchronize(g->st));
         HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
-        g->last_ms += ms;
-        g->last_launches += 1;
+        o.ms += ms;
+        o.launches += 1;
         u64 st2[16];
         HIPCHK(hipMemcpy(st2, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
         hipFree(dq);
@@ -508,15 +414,29 @@ static int run_sweep(mantra_graph *g, const LaunchSpec &sp, u64 stats_out[16]) {
         HIPCHK(hipMemcpy(&n2, g->dretry, sizeof(int32_t), hipMemcpyDeviceToHost));
         if (n2 > 0) return fail(MANTRA_E_INTERNAL, "arc buffer of a full window overflowed");
         for (int i = 0; i < 16; ++i)
-            if (i != 5) st1[i] += st2[i];
+            if (i != 5 && i < 9) st1[i] += st2[i];
     }
-    memcpy(stats_out, st1, sizeof(st1));
-    g->last_W += (int64_t)st1[0];
-    g->last_arcs += (int64_t)st1[1];
-    g->last_tn += (int64_t)st1[7];
-    g->last_te += (int64_t)st1[8];
+    memcpy(o.st, st1, sizeof(st1));
+    // busy share of the first launch's persistent grid
+    const u64 span = st1[10] - ~st1[11];
+    o.balance = span ? (double)st1[9] / ((double)ns * (double)span) : 1.0;
     if (st1[6]) return fail(MANTRA_E_INTERNAL, "%llu pairs failed flow conservation", (unsigned long long)st1[6]);
     return MANTRA_OK;
+}
+
+// blocking calls report their work through mantra_last_timing
+static void timing_reset(mantra_graph *g) {
+    g->last_ms = 0; g->last_launches = 0; g->last_W = 0; g->last_arcs = 0; g->last_tn = 0; g->last_te = 0;
+    g->last_busy_ms = 0;
+}
+static void timing_add(mantra_graph *g, const SweepOut &o) {
+    g->last_busy_ms += o.balance * o.ms;
+    g->last_ms += o.ms;
+    g->last_launches += o.launches;
+    g->last_W += (int64_t)o.st[0];
+    g->last_arcs += (int64_t)o.st[1];
+    g->last_tn += (int64_t)o.st[7];
+    g->last_te += (int64_t)o.st[8];
 }
 
 // per-block partials of max W, sum B, max R_j
@@ -551,13 +471,6 @@ static int reduce(mantra_graph *g, const double *W, const double *B, const doubl
 
 // ------------------------------------------------------------------ requests
 
-struct Acc {
-    double *B = nullptr, *W = nullptr, *R = nullptr, *E = nullptr;
-    int64_t n = 0, m = 0;
-    int c = 0;
-    void release() { hipFree(B); hipFree(W); hipFree(R); hipFree(E); B = W = R = E = nullptr; }
-};
-
 static int acc_alloc(mantra_graph *g, Acc &a, int c, bool edges) {
     a.n = g->n_total; a.m = g->m; a.c = c;
     HIPCHK(dalloc(&a.B, (size_t)a.n));
@@ -574,8 +487,12 @@ static int acc_zero(mantra_graph *g, Acc &a) {
     return MANTRA_OK;
 }
 
+// a slice of count pairs of one request's stream.  Launch slot q of the slice
+// takes stream index base + (q - qoff); for graph = -1 (fixed samples over
+// packed graphs) that index i names graph i / per_graph and its pair
+// i % per_graph.
 static DevReq make_req(const mantra_request &rq, int stream, int64_t base, int64_t qoff, int64_t count,
-                       const Acc &acc, int c) {
+                       const Acc *acc, int c) {
     DevReq d;
     memset(&d, 0, sizeof d);
     d.opt = rq.opt;
@@ -589,14 +506,16 @@ static DevReq make_req(const mantra_request &rq, int stream, int64_t base, int64
     d.qoff = qoff;
     d.count = count;
     d.per_graph = count;
-    d.Bsum = acc.B;
-    d.Wsum = acc.W;
-    d.Rsum = c > 0 ? acc.R : nullptr;
-    d.Esum = acc.E;
+    if (acc) {
+        d.Bsum = acc->B;
+        d.Wsum = acc->W;
+        d.Rsum = c > 0 ? acc->R : nullptr;
+        d.Esum = acc->E;
+    }
     return d;
 }
 
-static int check_request(const mantra_graph *g, const mantra_request &rq) {
+int check_request(const mantra_graph *g, const mantra_request &rq) {
     if (rq.opt < MANTRA_SH || rq.opt > MANTRA_PFM) return fail(MANTRA_E_INVALID, "unknown optimality %d", (int)rq.opt);
     if (!rq.node_bc) return fail(MANTRA_E_INVALID, "node_bc is NULL");
     int c = rq.c ? rq.c : 25;
@@ -631,128 +550,191 @@ static int finish_outputs(mantra_graph *g, const mantra_request &rq, Acc &acc, i
     return MANTRA_OK;
 }
 
-// Algorithm 1 (or a fixed sample) for one request, blocking
-static int run_request(mantra_graph *g, mantra_request rq, mantra_result *res) {
-    auto t_start = std::chrono::steady_clock::now();
-    int rc = check_request(g, rq);
-    if (rc) return rc;
-    norm_window(rq);
+size_t req_mem_bytes(const mantra_graph *g, const mantra_request &rq) {
     const int c = rq.c ? rq.c : 25;
     const bool edges = (rq.flags & MANTRA_F_EDGE_BC) && rq.edge_bc;
-    mantra_result R;
-    memset(&R, 0, sizeof R);
-    if (rq.opt == MANTRA_FM) R.flags |= MANTRA_RES_NO_GUARANTEE;
-    g->last_ms = 0; g->last_launches = 0; g->last_W = 0; g->last_arcs = 0; g->last_tn = 0; g->last_te = 0;
-    Acc acc;
-    rc = acc_alloc(g, acc, c, edges);
-    if (rc) { acc.release(); return rc; }
-    rc = acc_zero(g, acc);
-    u64 st[16];
-    int64_t r = 0;
-    if (!rc && rq.fixed_r > 0) {
-        LaunchSpec sp;
-        int64_t npairs = rq.fixed_r * g->G;
-        DevReq d = make_req(rq, STREAM_PAIR, 0, 0, npairs, acc, c);
-        d.graph = g->G == 1 ? 0 : -1;
-        d.per_graph = rq.fixed_r;
-        sp.reqs.push_back(d);
-        sp.npairs = npairs;
-        rc = run_sweep(g, sp, st);
-        if (!rc) {
-            r = rq.fixed_r;
-            R.samples = r;
-            R.rounds = 1;
-            R.n_overflow = (int64_t)st[2];
-            R.n_reachable = (int64_t)st[3];
-            if (st[4]) rc = fail(MANTRA_E_LIMIT, "a hop count exceeded 65534");
-        }
-        if (!rc && g->G == 1) {
-            double mw, sb;
-            std::vector<double> mr;
-            rc = reduce(g, acc.W, acc.B, acc.R, g->n_total, c, &mw, &sb, mr);
-            if (!rc) {
-                double W = std::max(mw, 0.0) / (double)r, Rc = 0;
-                for (int j = 0; j < c; ++j) Rc += mr[(size_t)j] / (double)r;
-                Rc /= c;
-                R.wimpy = W;
-                R.mcera = Rc;
-                R.xi = bnd::xi(Rc, W, std::min(0.25, W), c, (double)r, rq.delta > 0 && rq.delta < 1 ? rq.delta : 0.1);
-            }
-        }
-    } else if (!rc) {
-        // bootstrap: s' pairs of the BOOT stream (delta/2 of the budget)
-        const int64_t sb = bnd::boot(rq.eps, rq.delta);
-        R.s_boot = sb;
-        Acc boot;
-        rc = acc_alloc(g, boot, 0, false);
-        if (!rc) rc = acc_zero(g, boot);
-        if (!rc) {
-            LaunchSpec sp;
-            sp.reqs.push_back(make_req(rq, STREAM_BOOT, 0, 0, sb, boot, 0));
-            sp.npairs = sb;
-            rc = run_sweep(g, sp, st);
-            if (!rc && st[4]) rc = fail(MANTRA_E_LIMIT, "a hop count exceeded 65534");
-            if (!rc && st[2]) { R.n_overflow += (int64_t)st[2]; }
-        }
-        double mw = 0, sumb = 0;
-        std::vector<double> mr;
-        if (!rc) rc = reduce(g, boot.W, boot.B, boot.R, g->n_total, 0, &mw, &sumb, mr);
-        boot.release();
-        int64_t om = 0, s1 = 0;
-        if (!rc) {
-            R.rho_hat = sumb / (double)sb;
-            double wb = std::max(mw, 0.0) / (double)sb;
-            R.v_hat = std::min(0.25, wb);
-            om = std::max<int64_t>(sb, bnd::omega(R.v_hat, R.rho_hat, rq.eps, rq.delta / 2.0, g->n_total));
-            if (rq.max_samples > 0) om = std::min(om, rq.max_samples);
-            s1 = rq.s1 > 0 ? rq.s1 : bnd::first(sb, om, R.v_hat, rq.eps, rq.delta / 4.0);
-            s1 = std::min(s1, om);
-            R.omega = om;
-            R.s1 = s1;
-        }
-        int64_t prev = 0;
-        int i = 0;
-        while (!rc) {
-            ++i;
-            int64_t si = (i == 1) ? s1 : std::min(bnd::next(prev), om);
-            LaunchSpec sp;
-            sp.reqs.push_back(make_req(rq, STREAM_PAIR, prev, 0, si - prev, acc, c));
-            sp.npairs = si - prev;
-            rc = run_sweep(g, sp, st);
-            if (rc) break;
-            R.n_overflow += (int64_t)st[2];
-            R.n_reachable += (int64_t)st[3];
-            if (st[4]) { rc = fail(MANTRA_E_LIMIT, "a hop count exceeded 65534"); break; }
-            double sumB;
-            rc = reduce(g, acc.W, acc.B, acc.R, g->n_total, c, &mw, &sumB, mr);
-            if (rc) break;
-            r = si;
-            double W = std::max(mw, 0.0) / (double)r, Rc = 0;
-            for (int j = 0; j < c; ++j) Rc += mr[(size_t)j] / (double)r;
-            Rc /= c;
-            double di = rq.delta / pow(2.0, (double)(i + 1));
-            double xi = bnd::xi(Rc, W, std::min(0.25, W), c, (double)r, di);
-            R.xi = xi; R.wimpy = W; R.mcera = Rc; R.rounds = i; R.samples = r;
-            if (r >= om) { R.flags |= MANTRA_RES_STOP_OMEGA; break; }
-            if (xi <= rq.eps) { R.flags |= MANTRA_RES_STOP_XI; break; }
-            prev = si;
+    size_t b = sizeof(double) * (size_t)g->n_total * (size_t)(2 + c);
+    if (edges) b += sizeof(double) * (size_t)g->m;
+    if (rq.fixed_r <= 0) b += sizeof(double) * (size_t)g->n_total * 3;  // bootstrap sums
+    return b + sizeof(u64) * RS_N;
+}
+
+void req_release(ReqRun &q) {
+    q.acc.release();
+    q.boot.release();
+    hipFree(q.rstat);
+    q.rstat = nullptr;
+}
+
+static int rstat_zero(mantra_graph *g, ReqRun &q) {
+    HIPCHK(hipMemsetAsync(q.rstat, 0, sizeof(u64) * RS_N, g->st));
+    return MANTRA_OK;
+}
+
+int req_begin(mantra_graph *g, ReqRun &q) {
+    if (q.t_start == std::chrono::steady_clock::time_point()) q.t_start = std::chrono::steady_clock::now();
+    memset(&q.R, 0, sizeof q.R);
+    int rc = check_request(g, q.rq);
+    if (rc) return rc;
+    norm_window(q.rq);
+    q.c = q.rq.c ? q.rq.c : 25;
+    q.edges = (q.rq.flags & MANTRA_F_EDGE_BC) && q.rq.edge_bc;
+    if (q.rq.opt == MANTRA_FM) q.R.flags |= MANTRA_RES_NO_GUARANTEE;
+    q.mem_bytes = req_mem_bytes(g, q.rq);
+    hipSetDevice(g->device);
+    HIPCHK(dalloc(&q.rstat, RS_N));
+    if ((rc = rstat_zero(g, q))) return rc;
+    if ((rc = acc_alloc(g, q.acc, q.c, q.edges))) return rc;
+    if ((rc = acc_zero(g, q.acc))) return rc;
+    q.prev = 0;
+    q.issued = 0;
+    q.round = 0;
+    if (q.rq.fixed_r > 0) {
+        q.phase = ReqRun::ROUND;
+        q.target = q.rq.fixed_r * g->G;
+        return MANTRA_OK;
+    }
+    // bootstrap: s' pairs of their own stream, at delta/2 of the budget
+    q.phase = ReqRun::BOOT;
+    q.R.s_boot = bnd::boot(q.rq.eps, q.rq.delta);
+    q.target = q.R.s_boot;
+    if ((rc = acc_alloc(g, q.boot, 0, false))) return rc;
+    return acc_zero(g, q.boot);
+}
+
+DevReq req_slice(ReqRun &q, int64_t count, int64_t qoff) {
+    DevReq d;
+    const int64_t base = q.prev + q.issued;
+    if (q.phase == ReqRun::BOOT) {
+        d = make_req(q.rq, STREAM_BOOT, base, qoff, count, &q.boot, 0);
+    } else {
+        d = make_req(q.rq, STREAM_PAIR, base, qoff, count, &q.acc, q.c);
+        if (q.rq.fixed_r > 0) {
+            // fixed samples: fixed_r pairs of each graph, graph-major
+            d.graph = -1;
+            d.per_graph = q.rq.fixed_r;
         }
     }
-    if (!rc) rc = finish_outputs(g, rq, acc, r);
-    acc.release();
-    if (!rc && R.n_overflow > 0) rc = fail(MANTRA_E_OVERFLOW, "%lld sampled pairs saturated", (long long)R.n_overflow);
-    R.window_edges = g->last_W;
-    R.arcs = g->last_arcs;
-    R.gpu_ms = g->last_ms;
-    R.latency_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    R.status = rc;
-    if (rc == MANTRA_E_OVERFLOW)
-        for (int64_t v = 0; v < g->n_total; ++v) rq.node_bc[v] = NAN;
-    if (res) *res = R;
+    d.rstat = q.rstat;
+    q.issued += count;
+    return d;
+}
+
+// counters of the finished phase
+static int phase_stats(mantra_graph *g, ReqRun &q, u64 rs[RS_N]) {
+    HIPCHK(hipMemcpyAsync(rs, q.rstat, sizeof(u64) * RS_N, hipMemcpyDeviceToHost, g->st));
+    HIPCHK(hipStreamSynchronize(g->st));
+    int rc = rstat_zero(g, q);
+    if (rc) return rc;
+    q.R.window_edges += (int64_t)rs[RS_WINDOW];
+    q.R.arcs += (int64_t)rs[RS_ARCS];
+    if (rs[RS_HOPS]) return fail(MANTRA_E_LIMIT, "a hop count exceeded 65534");
+    return MANTRA_OK;
+}
+
+int req_advance(mantra_graph *g, ReqRun &q) {
+    if (q.phase == ReqRun::DONE || q.issued < q.target - q.prev) return MANTRA_OK;
+    u64 rs[RS_N];
+    int rc = phase_stats(g, q, rs);
+    if (rc) return rc;
+    const int c = q.c;
+    if (q.phase == ReqRun::BOOT) {
+        q.R.n_overflow += (int64_t)rs[RS_OVERFLOW];
+        double mw = 0, sumb = 0;
+        std::vector<double> mr;
+        if ((rc = reduce(g, q.boot.W, q.boot.B, q.boot.R, g->n_total, 0, &mw, &sumb, mr))) return rc;
+        q.boot.release();
+        const int64_t sb = q.R.s_boot;
+        q.R.rho_hat = sumb / (double)sb;
+        q.R.v_hat = std::min(0.25, std::max(mw, 0.0) / (double)sb);
+        int64_t om = std::max<int64_t>(sb, bnd::omega(q.R.v_hat, q.R.rho_hat, q.rq.eps, q.rq.delta / 2.0, g->n_total));
+        if (q.rq.max_samples > 0) om = std::min(om, q.rq.max_samples);
+        int64_t s1 = q.rq.s1 > 0 ? q.rq.s1 : bnd::first(sb, om, q.R.v_hat, q.rq.eps, q.rq.delta / 4.0);
+        s1 = std::min(s1, om);
+        q.om = om;
+        q.R.omega = om;
+        q.R.s1 = s1;
+        q.phase = ReqRun::ROUND;
+        q.prev = 0;
+        q.issued = 0;
+        q.target = s1;
+        return MANTRA_OK;
+    }
+    // a round (or the fixed sample) is complete
+    q.R.n_overflow += (int64_t)rs[RS_OVERFLOW];
+    q.R.n_reachable += (int64_t)rs[RS_REACHABLE];
+    q.round += 1;
+    const int64_t r = q.rq.fixed_r > 0 ? q.rq.fixed_r : q.target;
+    q.R.rounds = q.round;
+    q.R.samples = r;
+    if (g->G == 1) {
+        double mw, sumB;
+        std::vector<double> mr;
+        if ((rc = reduce(g, q.acc.W, q.acc.B, q.acc.R, g->n_total, c, &mw, &sumB, mr))) return rc;
+        const double W = std::max(mw, 0.0) / (double)r;
+        double Rc = 0;
+        for (int j = 0; j < c; ++j) Rc += mr[(size_t)j] / (double)r;
+        Rc /= c;
+        q.R.wimpy = W;
+        q.R.mcera = Rc;
+        // round i runs at delta_i = delta / 2^(i+1); a fixed sample uses delta
+        const double dd = q.rq.delta > 0 && q.rq.delta < 1 ? q.rq.delta : 0.1;
+        const double di = q.rq.fixed_r > 0 ? dd : q.rq.delta / pow(2.0, (double)(q.round + 1));
+        q.R.xi = bnd::xi(Rc, W, std::min(0.25, W), c, (double)r, di);
+    }
+    if (q.rq.fixed_r > 0) { q.phase = ReqRun::DONE; return MANTRA_OK; }
+    if (r >= q.om) { q.R.flags |= MANTRA_RES_STOP_OMEGA; q.phase = ReqRun::DONE; return MANTRA_OK; }
+    if (q.R.xi <= q.rq.eps) { q.R.flags |= MANTRA_RES_STOP_XI; q.phase = ReqRun::DONE; return MANTRA_OK; }
+    q.prev = q.target;
+    q.issued = 0;
+    q.target = std::min(bnd::next(q.target), q.om);
+    return MANTRA_OK;
+}
+
+int req_finish(mantra_graph *g, ReqRun &q, mantra_result *out) {
+    int rc = q.rc;
+    if (rc < 0 && q.err.empty()) q.err = g_err;
+    if (!rc) rc = finish_outputs(g, q.rq, q.acc, q.R.samples);
+    req_release(q);
+    if (!rc && q.R.n_overflow > 0)
+        rc = fail(MANTRA_E_OVERFLOW, "%lld sampled pairs saturated", (long long)q.R.n_overflow);
+    if (rc == MANTRA_E_OVERFLOW && q.rq.node_bc)
+        for (int64_t v = 0; v < g->n_total; ++v) q.rq.node_bc[v] = NAN;
+    q.R.latency_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q.t_start).count();
+    q.R.status = rc;
+    if (rc < 0 && q.rc == MANTRA_OK) q.err = g_err;
+    q.rc = rc;
+    if (out) *out = q.R;
     return rc;
 }
 
+// Algorithm 1 (or a fixed sample) for one request, blocking: each phase is
+// one launch
+static int run_request(mantra_graph *g, const mantra_request &rq, mantra_result *res) {
+    ReqRun q;
+    q.rq = rq;
+    timing_reset(g);
+    int rc = req_begin(g, q);
+    while (!rc && q.phase != ReqRun::DONE) {
+        LaunchSpec sp;
+        const int64_t cnt = req_pending(q);
+        sp.reqs.push_back(req_slice(q, cnt, 0));
+        sp.npairs = cnt;
+        SweepOut o;
+        rc = run_sweep(g, sp, o);
+        timing_add(g, o);
+        q.R.gpu_ms += o.ms;
+        if (!rc) rc = req_advance(g, q);
+    }
+    q.rc = rc;
+    return req_finish(g, q, res);
+}
+
+}  // namespace mantra
+
 // ------------------------------------------------------------------ C ABI
+
+using namespace mantra;
 
 extern "C" {
 
@@ -774,11 +756,9 @@ int mantra_graph_create_packed(int32_t G, const int32_t *node_count, const int64
     return build_graph(G, node_count, edge_off, src, dst, t, out);
 }
 
-int mantra_serve_stop(mantra_graph *g);
-
 void mantra_graph_destroy(mantra_graph *g) {
     if (!g) return;
-    mantra_serve_stop(g);
+    serve_stop(g);
     hipSetDevice(g->device);
     if (g->st) hipStreamSynchronize(g->st);
     g->pool.release();
@@ -815,7 +795,7 @@ int mantra_set_launch(mantra_graph *g, int32_t n_slabs, int64_t arc_cap) {
 }
 
 int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launches, int64_t *window_edges,
-                       int64_t *arcs, int64_t *touched_nodes, int64_t *touched_edges) {
+                       int64_t *arcs, int64_t *touched_nodes, int64_t *touched_edges, double *balance) {
     if (!g) return fail(MANTRA_E_INVALID, "graph is NULL");
     g_err.clear();
     if (sweep_ms) *sweep_ms = g->last_ms;
@@ -824,6 +804,7 @@ int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launche
     if (arcs) *arcs = g->last_arcs;
     if (touched_nodes) *touched_nodes = g->last_tn;
     if (touched_edges) *touched_edges = g->last_te;
+    if (balance) *balance = g->last_ms > 0 ? g->last_busy_ms / g->last_ms : 1.0;
     return MANTRA_OK;
 }
 
@@ -847,7 +828,7 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
     if (edge_f && (double)r * (double)g->m > 4e9) return fail(MANTRA_E_INVALID, "edge_f too large");
     std::lock_guard<std::mutex> lk(g->mu);
     hipSetDevice(g->device);
-    g->last_ms = 0; g->last_launches = 0; g->last_W = 0; g->last_arcs = 0; g->last_tn = 0; g->last_te = 0;
+    timing_reset(g);
     int32_t *dpg = nullptr, *dps = nullptr, *dpz = nullptr;
     void *drec = nullptr;
     double *dnf = nullptr, *def = nullptr;
@@ -878,14 +859,12 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
     memset(&rq, 0, sizeof rq);
     rq.opt = opt; rq.t0 = t0; rq.t1 = t1;
     norm_window(rq);
-    Acc none;
-    DevReq d = make_req(rq, STREAM_PAIR, 0, 0, r, none, 0);
-    d.Bsum = d.Wsum = d.Rsum = d.Esum = nullptr;
-    sp.reqs.push_back(d);
+    sp.reqs.push_back(make_req(rq, STREAM_PAIR, 0, 0, r, nullptr, 0));
     sp.npairs = r;
     sp.dpg = dpg; sp.dps = dps; sp.dpz = dpz; sp.drec = drec; sp.dnode_f = dnf; sp.dedge_f = def;
-    u64 st[16];
-    rc = run_sweep(g, sp, st);
+    SweepOut so;
+    rc = run_sweep(g, sp, so);
+    timing_add(g, so);
     if (!rc) {
         if (hipMemcpy(out, drec, (size_t)r * 24, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(MANTRA_E_INTERNAL, "copy records");
         if (!rc && node_f) {

@@ -985,15 +985,15 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
     P.q = q;
     P.qout = q;
     P.lam = 0;
-    int64_t i = q - R.qoff;
+    const int64_t i = q - R.qoff + R.base;
     if (a.ps) {
         P.g = a.pg ? a.pg[q] : 0;
         P.s = a.ps[q];
         P.z = a.pz[q];
     } else {
         int64_t idx;
-        if (R.graph >= 0) { P.g = R.graph; idx = R.base + i; }
-        else { P.g = (int32_t)(i / R.per_graph); idx = R.base + (i % R.per_graph); }
+        if (R.graph >= 0) { P.g = R.graph; idx = i; }
+        else { P.g = (int32_t)(i / R.per_graph); idx = i % R.per_graph; }
         int32_t noff = a.g.seg_noff[P.g];
         int32_t ng = a.g.seg_noff[P.g + 1] - noff;
         u64 st = (u64)R.stream + (u64)STREAMS_PER_GRAPH * (u64)P.g;
@@ -1011,7 +1011,7 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
     P.level = (P.opt == OPT_SH || P.opt == OPT_SFM);
 }
 
-__global__ void __launch_bounds__(64, 5) k_sweep(LaunchArgs a) {
+__global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int l = lane_id();
     const int64_t slab = blockIdx.x;
@@ -1033,6 +1033,7 @@ __global__ void __launch_bounds__(64, 5) k_sweep(LaunchArgs a) {
     u32 serial = S.hdr[0];
     u32 agstamp = S.hdr[1];
     u32 stamp = 1;  // reverse table stamps (0 = empty)
+    const u64 t_begin = wall_clock64();
     __syncthreads();
     for (;;) {
         u32 qq = 0;
@@ -1130,6 +1131,13 @@ __global__ void __launch_bounds__(64, 5) k_sweep(LaunchArgs a) {
             if (flags & REC_SELFCHECK) atomicAdd((unsigned long long *)&a.stats[6], 1ull);
             atomicAdd((unsigned long long *)&a.stats[7], (unsigned long long)X.touched_n);
             atomicAdd((unsigned long long *)&a.stats[8], (unsigned long long)X.edges_n);
+            if (R->rstat && !(flags & REC_ARCS_LIMIT)) {
+                if (flags & REC_OVERFLOW) atomicAdd((unsigned long long *)&R->rstat[0], 1ull);
+                if (reach) atomicAdd((unsigned long long *)&R->rstat[1], 1ull);
+                if (flags & REC_HOPS_LIMIT) atomicAdd((unsigned long long *)&R->rstat[2], 1ull);
+                atomicAdd((unsigned long long *)&R->rstat[3], (unsigned long long)fo.swept);
+                atomicAdd((unsigned long long *)&R->rstat[4], (unsigned long long)fo.arcs);
+            }
             if (flags & REC_ARCS_LIMIT) {
                 atomicAdd((unsigned long long *)&a.stats[5], 1ull);
                 int pos = atomicAdd(&a.retry[0], 1);
@@ -1138,7 +1146,16 @@ __global__ void __launch_bounds__(64, 5) k_sweep(LaunchArgs a) {
         }
         __syncthreads();
     }
-    if (l == 0) { S.hdr[0] = serial; S.hdr[1] = agstamp; }
+    if (l == 0) {
+        S.hdr[0] = serial;
+        S.hdr[1] = agstamp;
+        // load balance of the persistent grid: busy time of this slab, the
+        // last finish and the first start (constant-rate wall clock)
+        const u64 t_end = wall_clock64();
+        atomicAdd((unsigned long long *)&a.stats[9], (unsigned long long)(t_end - t_begin));
+        atomicMax((unsigned long long *)&a.stats[10], (unsigned long long)t_end);
+        atomicMax((unsigned long long *)&a.stats[11], (unsigned long long)~t_begin);
+    }
 }
 
 // ------------------------------------------------------------ reductions
