@@ -163,9 +163,25 @@ int mantra_poll(uint64_t ticket, mantra_result *out, int32_t timeout_ms);
  * sums (0: a default share of free memory), maximum concurrent requests. */
 int mantra_serve_config(mantra_graph *g, uint64_t mem_budget_bytes, int32_t max_active);
 
-/* Launch configuration: number of persistent workgroups (0: automatic) and
- * per-slab arc capacity (0: automatic).  Measurement knob. */
-int mantra_set_launch(mantra_graph *g, int32_t n_slabs, int64_t arc_cap);
+/* Launch configuration of the sweep (it changes how the work is scheduled,
+ * never a result). */
+typedef struct {
+    int32_t n_slabs;      /* persistent workgroups per launch, each one pair at a
+                             time (0: as many as fit the device) */
+    int64_t arc_cap;      /* appearance-DAG arc records per workgroup (0: from
+                             free memory); a pair that overflows them is re-run
+                             with room for every edge */
+    int32_t order;        /* MANTRA_ORDER_*: the order pairs are handed out in */
+    int32_t graph_rounds; /* 1: blocking requests replay one captured HIP graph
+                             per progressive round */
+} mantra_launch_config;
+
+#define MANTRA_ORDER_LONGEST_FIRST 0 /* decreasing estimated window (default) */
+#define MANTRA_ORDER_DRAWN 1         /* sample order */
+
+int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg);
+/* the configuration in force, automatic values resolved */
+int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg);
 
 /* Work and timing of the last blocking call on g: device time of the sweep
  * kernel launches (HIP events on the graph's stream), their count, the

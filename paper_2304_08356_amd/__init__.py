@@ -87,8 +87,17 @@ class Graph:
         return {"n": n.value, "m_unique": mu.value, "n_duplicates": nd.value, "t_min": t0.value,
                 "t_max": t1.value, "n_graphs": G.value}
 
-    def set_launch(self, n_slabs=0, arc_cap=0):
-        _lib.check(_lib._lib.mantra_set_launch(self._h, int(n_slabs), int(arc_cap)))
+    def set_launch(self, n_slabs=0, arc_cap=0, order="longest", graph_rounds=False):
+        """Launch configuration (scheduling only; results do not change)."""
+        cfg = _lib.LaunchConfig(n_slabs=int(n_slabs), arc_cap=int(arc_cap),
+                                order=_lib.ORDER[order] if isinstance(order, str) else int(order),
+                                graph_rounds=1 if graph_rounds else 0)
+        _lib.check(_lib._lib.mantra_set_launch(self._h, ctypes.byref(cfg)))
+
+    def get_launch(self):
+        cfg = _lib.LaunchConfig()
+        _lib.check(_lib._lib.mantra_get_launch(self._h, ctypes.byref(cfg)))
+        return cfg.to_dict()
 
     def last_timing(self):
         ms = ctypes.c_double(); nl = ctypes.c_int64(); w = ctypes.c_int64(); a = ctypes.c_int64()

@@ -40,6 +40,16 @@ class Request(ctypes.Structure):
                 ("node_bc", P), ("edge_bc", P)]
 
 
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("n_slabs", I32), ("arc_cap", I64), ("order", I32), ("graph_rounds", I32)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ORDER = {"longest": 0, "drawn": 1}
+
+
 class Result(ctypes.Structure):
     _fields_ = [("status", I32), ("flags", U32), ("samples", I64), ("rounds", I64), ("omega", I64),
                 ("s_boot", I64), ("s1", I64), ("n_overflow", I64), ("n_reachable", I64),
@@ -62,7 +72,8 @@ SIGNATURES = {
     "mantra_submit": (I32, [P, P, P]),
     "mantra_poll": (I32, [U64, P, I32]),
     "mantra_serve_config": (I32, [P, U64, I32]),
-    "mantra_set_launch": (I32, [P, I32, I64]),
+    "mantra_set_launch": (I32, [P, P]),
+    "mantra_get_launch": (I32, [P, P]),
     "mantra_last_timing": (I32, [P, P, P, P, P, P, P, P]),
     "mantra_last_error": (ctypes.c_char_p, []),
 }

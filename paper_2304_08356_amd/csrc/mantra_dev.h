@@ -19,6 +19,7 @@ constexpr int kC = kWave * kE;       // batch capacity (edges or arcs)
 constexpr int kFwN = 2 * kC;         // LDS forwarding / tail table slots
 constexpr int kFwBits = kFwN == 128 ? 7 : (kFwN == 256 ? 8 : (kFwN == 512 ? 9 : 10));
 static_assert((1 << kFwBits) == kFwN, "table size must be a power of two");
+constexpr int kOrderBuckets = 160;   // log-scale cost buckets of the launch order (4 per octave)
 constexpr int kAliveN = 512;         // alive-set hash slots of the reverse sweep (no LDS bitmap)
 constexpr u32 kHInf = 0xFFFFu;       // "unreached" hop count
 constexpr u64 kUMax = ~0ull;

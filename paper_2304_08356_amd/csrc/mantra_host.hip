@@ -368,6 +368,18 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o) {
     a.stats = g->dstats;
     a.retry = g->dretry;
     size_t lb = lds_bytes(g->nmax);
+    if (g->order_mode == MANTRA_ORDER_LONGEST_FIRST && sp.npairs > ns) {
+        if (sp.npairs > g->order_cap) {
+            hipFree(g->dbucket); hipFree(g->dorder);
+            g->dbucket = nullptr; g->dorder = nullptr;
+            g->order_cap = std::max<int64_t>(sp.npairs, 4096);
+            HIPCHK(dalloc(&g->dbucket, (size_t)g->order_cap));
+            HIPCHK(dalloc(&g->dorder, (size_t)g->order_cap));
+        }
+        if (!g->dhist) HIPCHK(dalloc(&g->dhist, (size_t)kOrderBuckets));
+        HIPCHK(mantra_launch_order(&a, g->dbucket, g->dhist, g->dorder, g->st));
+        a.pq = g->dorder;
+    }
     HIPCHK(hipEventRecord(g->ev0, g->st));
     HIPCHK(mantra_launch_sweep(&a, ns, lb, g->st));
     HIPCHK(hipEventRecord(g->ev1, g->st));
@@ -766,6 +778,7 @@ void mantra_graph_destroy(mantra_graph *g) {
     hipFree(g->dU); hipFree(g->dV); hipFree(g->dT); hipFree(g->dout_t); hipFree(g->din_t);
     hipFree(g->dout_off); hipFree(g->din_off); hipFree(g->dseg_eoff); hipFree(g->dseg_noff); hipFree(g->dperm);
     hipFree(g->dwork); hipFree(g->dstats); hipFree(g->dretry); hipFree(g->dpart); hipFree(g->dreqs);
+    hipFree(g->dbucket); hipFree(g->dorder); hipFree(g->dhist);
     if (g->ev0) hipEventDestroy(g->ev0);
     if (g->ev1) hipEventDestroy(g->ev1);
     if (g->st) hipStreamDestroy(g->st);
@@ -784,13 +797,26 @@ int mantra_graph_info(const mantra_graph *g, int32_t *n, int64_t *m_unique, int6
     return MANTRA_OK;
 }
 
-int mantra_set_launch(mantra_graph *g, int32_t n_slabs, int64_t arc_cap) {
-    if (!g) return fail(MANTRA_E_INVALID, "graph is NULL");
-    if (n_slabs < 0 || arc_cap < 0) return fail(MANTRA_E_INVALID, "negative launch setting");
+int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg) {
+    if (!g || !cfg) return fail(MANTRA_E_INVALID, "graph or config is NULL");
+    if (cfg->n_slabs < 0 || cfg->arc_cap < 0) return fail(MANTRA_E_INVALID, "negative launch setting");
+    if (cfg->order != MANTRA_ORDER_LONGEST_FIRST && cfg->order != MANTRA_ORDER_DRAWN)
+        return fail(MANTRA_E_INVALID, "unknown pair order %d", cfg->order);
     std::lock_guard<std::mutex> lk(g->mu);
-    g->user_slabs = n_slabs;
-    g->user_cap = arc_cap;
-    g->pool.release();
+    if (g->user_slabs != cfg->n_slabs || g->user_cap != cfg->arc_cap) g->pool.release();
+    g->user_slabs = cfg->n_slabs;
+    g->user_cap = cfg->arc_cap;
+    g->order_mode = cfg->order;
+    g->graph_rounds = cfg->graph_rounds ? 1 : 0;
+    return MANTRA_OK;
+}
+
+int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {
+    if (!g || !cfg) return fail(MANTRA_E_INVALID, "graph or config is NULL");
+    cfg->n_slabs = auto_slabs(g);
+    cfg->arc_cap = auto_cap(g, cfg->n_slabs);
+    cfg->order = g->order_mode;
+    cfg->graph_rounds = g->graph_rounds;
     return MANTRA_OK;
 }
 

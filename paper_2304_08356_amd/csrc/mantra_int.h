@@ -27,6 +27,8 @@ extern "C" {
 hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
 hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st);
 hipError_t mantra_launch_fill(mantra::u64 *p, mantra::u64 val, int64_t n, hipStream_t st);
+hipError_t mantra_launch_order(const mantra::LaunchArgs *a, mantra::u32 *bucket, mantra::u64 *hist,
+                               int32_t *order, hipStream_t st);
 size_t mantra_tab_lds_bytes(void);
 int mantra_sweep_occupancy(size_t lds_bytes);
 }
@@ -101,6 +103,13 @@ struct mantra_graph {
     mantra::SlabPool pool, pool_big;
     int user_slabs = 0;
     int64_t user_cap = 0;
+    int order_mode = MANTRA_ORDER_LONGEST_FIRST;
+    int graph_rounds = 0;
+    // launch order scratch
+    mantra::u32 *dbucket = nullptr;
+    int32_t *dorder = nullptr;
+    mantra::u64 *dhist = nullptr;
+    int64_t order_cap = 0;
     // misc device buffers
     mantra::u32 *dwork = nullptr;
     mantra::u64 *dstats = nullptr;

@@ -1158,6 +1158,84 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
     }
 }
 
+// ------------------------------------------------------------ pair order
+
+// first index in [a, b) with arr[i] >= x (arr ascending), one thread
+__device__ int64_t lower_bound_1(const int32_t *arr, int64_t a, int64_t b, int32_t x) {
+    while (a < b) {
+        const int64_t m = a + (b - a) / 2;
+        if (arr[m] < x) a = m + 1; else b = m;
+    }
+    return a;
+}
+
+// Cost estimate of every launch slot's pair, in edges of the time-sorted
+// stream: the window from the first departure of s to the last arrival at z
+// (exact for sh, which sweeps all of it); for the optimalities that stop at
+// the first arrival at z, the window up to z's kPairKeyK-th in-edge after the
+// departure (z's arrival cannot come earlier than its first in-edge, and
+// targets with few in-edges are the ones reached late).  The launch runs the
+// slots in decreasing order of the estimate, bucketed on a log scale with
+// four buckets per octave (a counting sort: histogram, scan, scatter), so
+// that the longest sweeps start first.
+constexpr int kPairKeyK = 8;
+
+__device__ __forceinline__ u32 order_bucket(u64 est) {
+    const u64 x = est + 1;
+    const int e = 63 - __clzll((long long)x);
+    const u32 frac = e >= 2 ? (u32)((x >> (e - 2)) & 3ull) : (u32)((x << (2 - e)) & 3ull);
+    const u32 b = 4u * (u32)e + frac;
+    return b < (u32)kOrderBuckets ? b : (u32)kOrderBuckets - 1;
+}
+
+__global__ void __launch_bounds__(256) k_pair_keys(LaunchArgs a, u32 *bucket, u64 *hist) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= a.npairs) return;
+    a.pq = nullptr;
+    Pair P;
+    resolve_pair(a, slot, P);
+    const int32_t gs = P.noff + P.s, gz = P.noff + P.z;
+    const int64_t o0 = a.g.out_off[gs], o1 = a.g.out_off[gs + 1];
+    const int64_t i0 = a.g.in_off[gz], i1 = a.g.in_off[gz + 1];
+    const int64_t od = lower_bound_1(a.g.out_t, o0, o1, P.t0);
+    const int64_t id = lower_bound_1(a.g.in_t, i0, i1, P.t1 == INT32_MAX ? P.t1 : P.t1 + 1) - 1;
+    u64 est = 0;
+    if (od < o1 && id >= i0) {
+        const int32_t dep = a.g.out_t[od], lin = a.g.in_t[id];
+        if (dep <= P.t1 && lin >= P.t0 && lin >= dep) {
+            int32_t tend = lin;
+            if (P.opt != OPT_SH) {
+                const int64_t j = lower_bound_1(a.g.in_t, i0, id + 1, dep == INT32_MAX ? dep : dep + 1) + (kPairKeyK - 1);
+                tend = a.g.in_t[j < id ? j : id];
+            }
+            const int64_t lo = lower_bound_1(a.g.T, P.elo, P.ehi, dep);
+            const int64_t hi = lower_bound_1(a.g.T, lo, P.ehi, tend == INT32_MAX ? tend : tend + 1);
+            est = (u64)(hi - lo);
+        }
+    }
+    const u32 b = order_bucket(est);
+    bucket[slot] = b;
+    atomicAdd((unsigned long long *)&hist[b], 1ull);
+}
+
+// cursor[b] = number of slots in buckets above b (one thread: kOrderBuckets steps)
+__global__ void k_order_scan(u64 *hist) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    u64 run = 0;
+    for (int b = kOrderBuckets - 1; b >= 0; --b) {
+        const u64 h = hist[b];
+        hist[b] = run;
+        run += h;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_order_scatter(int64_t npairs, const u32 *bucket, u64 *cursor, int32_t *order) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= npairs) return;
+    const u64 pos = atomicAdd((unsigned long long *)&cursor[bucket[slot]], 1ull);
+    order[pos] = (int32_t)slot;
+}
+
 // ------------------------------------------------------------ reductions
 
 // per block: max_v W[v], sum_v B[v], max_v R[v][j] (j < c)
@@ -1220,6 +1298,19 @@ hipError_t mantra_launch_fill(mantra::u64 *p, mantra::u64 val, int64_t n, hipStr
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(mantra::k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, p, val, n);
+    return hipGetLastError();
+}
+// slot order of a launch, longest estimated sweep first: order[npairs];
+// bucket[npairs] and hist[kOrderBuckets] are scratch
+hipError_t mantra_launch_order(const mantra::LaunchArgs *a, mantra::u32 *bucket, mantra::u64 *hist,
+                               int32_t *order, hipStream_t st) {
+    if (a->npairs <= 0) return hipSuccess;
+    const int64_t blocks = (a->npairs + 255) / 256;
+    hipLaunchKernelGGL(mantra::k_fill_u64, dim3(1), dim3(256), 0, st, hist, 0ull, (int64_t)mantra::kOrderBuckets);
+    hipLaunchKernelGGL(mantra::k_pair_keys, dim3((unsigned)blocks), dim3(256), 0, st, *a, bucket, hist);
+    hipLaunchKernelGGL(mantra::k_order_scan, dim3(1), dim3(64), 0, st, hist);
+    hipLaunchKernelGGL(mantra::k_order_scatter, dim3((unsigned)blocks), dim3(256), 0, st, a->npairs,
+                       (const mantra::u32 *)bucket, hist, order);
     return hipGetLastError();
 }
 size_t mantra_tab_lds_bytes(void) { return sizeof(mantra::TabLds); }
