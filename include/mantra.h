@@ -172,8 +172,11 @@ typedef struct {
                              free memory); a pair that overflows them is re-run
                              with room for every edge */
     int32_t order;        /* MANTRA_ORDER_*: the order pairs are handed out in */
-    int32_t graph_rounds; /* 1: blocking requests replay one captured HIP graph
-                             per progressive round */
+    int32_t graph_rounds; /* 1: the progressive rounds of a blocking request
+                             replay one captured HIP graph (counters, order,
+                             sweep and reduction) */
+    int32_t per_pair_launch; /* 1: the unbatched form, one single-workgroup
+                                launch per pair (a baseline for measurement) */
 } mantra_launch_config;
 
 #define MANTRA_ORDER_LONGEST_FIRST 0 /* decreasing estimated window (default) */

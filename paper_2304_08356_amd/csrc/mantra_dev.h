@@ -82,7 +82,9 @@ struct LaunchArgs {
     const DevReq *reqs;
     int32_t nreq;
     int32_t lds_bitmap;      // 1: reached-bitmap of nmax bits in LDS
-    int64_t npairs;
+    int64_t npairs;              // launch slots (grid sizes); the pairs are slots qbase..np-1
+    const int64_t *npairs_dev;   // np read from device memory (graph replays), or null: np = npairs
+    int64_t qbase;               // first slot this launch takes
     const int32_t *pg, *ps, *pz; // explicit pairs (or null: RNG mode)
     const int32_t *pq;           // explicit launch slot -> original pair number (retries), or null
     void *rec;                   // mantra_pair_record[npairs] or null

@@ -324,34 +324,73 @@ static int64_t auto_cap(const mantra_graph *g, int nslabs) {
     return std::max<int64_t>(cap, 1024);
 }
 
+template <class T>
+static int grow(T **p, int64_t &cap, int64_t need, int64_t minimum) {
+    if (need <= cap && *p) return MANTRA_OK;
+    hipFree(*p);
+    *p = nullptr;
+    cap = std::max(need, minimum);
+    HIPCHK(dalloc(p, (size_t)cap));
+    return MANTRA_OK;
+}
+
+void RoundGraph::release() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    ns = 0;
+}
+
+// the kernels of one launch: clear the counters, order the slots (longest
+// estimated window first), sweep; with rg, also the request's reduction
+static int issue_kernels(mantra_graph *g, LaunchArgs &a, int ns, size_t lb, const RoundGraph *rg) {
+    HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, g->dstats, g->st));
+    if (g->order_mode == MANTRA_ORDER_LONGEST_FIRST && a.npairs > ns) {
+        HIPCHK(mantra_launch_order(&a, g->dbucket, g->dhist, g->dorder, g->st));
+        a.pq = g->dorder;
+    }
+    if (!rg) HIPCHK(hipEventRecord(g->ev0, g->st));
+    HIPCHK(mantra_launch_sweep(&a, ns, lb, g->st));
+    if (!rg) HIPCHK(hipEventRecord(g->ev1, g->st));
+    if (rg) {
+        ReduceArgs ra;
+        ra.W = rg->W; ra.B = rg->B; ra.R = rg->R; ra.n = g->n_total; ra.c = rg->c; ra.part = g->dpart;
+        HIPCHK(mantra_launch_reduce(&ra, reduce_blocks(g->n_total), g->st));
+    }
+    return MANTRA_OK;
+}
+
 // launch the sweep over all pairs of spec; re-run pairs whose arcs did not
-// fit with a pool of few slabs and the largest capacity
-int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o) {
+// fit with a pool of few slabs and the largest capacity.  With rg (a
+// progressive round of one blocking request), the launch sequence and the
+// request's reduction are one HIP graph, captured for rg->cap slots on first
+// use and replayed with the slice and its pair count in device memory.
+int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg) {
     memset(o.st, 0, sizeof o.st);
     o.ms = 0;
     o.launches = 0;
+    o.reduced = false;
     if (sp.npairs <= 0) return MANTRA_OK;
     hipSetDevice(g->device);
+    const int64_t slots = rg ? std::max(rg->cap, sp.npairs) : sp.npairs;
     int ns = auto_slabs(g);
-    if ((int64_t)ns > sp.npairs) ns = (int)sp.npairs;
+    if ((int64_t)ns > slots) ns = (int)slots;
+    if (g->per_pair) ns = 1;
     int64_t cap = auto_cap(g, auto_slabs(g));
     int rc = pool_ensure(g, g->pool, std::max(ns, g->pool.nslabs), std::max(cap, g->pool.cap));
     if (rc) return rc;
-    if ((int)sp.reqs.size() > g->dreq_cap) {
-        hipFree(g->dreqs);
-        g->dreqs = nullptr;
-        g->dreq_cap = std::max<int>(64, (int)sp.reqs.size());
-        HIPCHK(dalloc(&g->dreqs, (size_t)g->dreq_cap));
-    }
-    if (sp.npairs + 1 > g->retry_cap) {
-        hipFree(g->dretry);
-        g->retry_cap = std::max<int64_t>(sp.npairs + 1, 4096);
-        HIPCHK(dalloc(&g->dretry, (size_t)g->retry_cap));
-    }
+    int64_t rcap = g->dreq_cap;
+    if ((rc = grow(&g->dreqs, rcap, (int64_t)sp.reqs.size(), 64))) return rc;
+    g->dreq_cap = (int)rcap;
+    if ((rc = grow(&g->dretry, g->retry_cap, slots + 1, 4096))) return rc;
+    int64_t oc = g->order_cap;
+    if ((rc = grow(&g->dbucket, oc, slots, 4096))) return rc;
+    if ((rc = grow(&g->dorder, g->order_cap, slots, 4096))) return rc;
+    if (!g->dhist) HIPCHK(dalloc(&g->dhist, (size_t)kOrderBuckets));
+    if (!g->dnp) HIPCHK(dalloc(&g->dnp, 1));
+    if (rg && (rc = reduce_part_ensure(g, rg->c))) return rc;
     HIPCHK(hipMemcpyAsync(g->dreqs, sp.reqs.data(), sizeof(DevReq) * sp.reqs.size(), hipMemcpyHostToDevice, g->st));
-    HIPCHK(hipMemsetAsync(g->dwork, 0, sizeof(u32), g->st));
-    HIPCHK(hipMemsetAsync(g->dstats, 0, sizeof(u64) * 16, g->st));
-    HIPCHK(hipMemsetAsync(g->dretry, 0, sizeof(int32_t), g->st));
     LaunchArgs a;
     memset(&a, 0, sizeof a);
     a.g = g->dev();
@@ -359,7 +398,9 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o) {
     a.reqs = g->dreqs;
     a.nreq = (int32_t)sp.reqs.size();
     a.lds_bitmap = lds_bitmap_ok(g->nmax);
-    a.npairs = sp.npairs;
+    a.npairs = slots;
+    a.npairs_dev = nullptr;
+    a.qbase = 0;
     a.pg = sp.dpg; a.ps = sp.dps; a.pz = sp.dpz; a.pq = nullptr;
     a.rec = sp.drec;
     a.node_f = sp.dnode_f;
@@ -367,35 +408,60 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o) {
     a.work = g->dwork;
     a.stats = g->dstats;
     a.retry = g->dretry;
-    size_t lb = lds_bytes(g->nmax);
-    if (g->order_mode == MANTRA_ORDER_LONGEST_FIRST && sp.npairs > ns) {
-        if (sp.npairs > g->order_cap) {
-            hipFree(g->dbucket); hipFree(g->dorder);
-            g->dbucket = nullptr; g->dorder = nullptr;
-            g->order_cap = std::max<int64_t>(sp.npairs, 4096);
-            HIPCHK(dalloc(&g->dbucket, (size_t)g->order_cap));
-            HIPCHK(dalloc(&g->dorder, (size_t)g->order_cap));
+    const size_t lb = lds_bytes(g->nmax);
+    float ms = 0;
+    if (g->per_pair) {
+        // the unbatched form: one single-workgroup launch per pair
+        HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, g->dstats, g->st));
+        HIPCHK(hipEventRecord(g->ev0, g->st));
+        for (int64_t q = 0; q < sp.npairs; ++q) {
+            a.qbase = q;
+            a.npairs = q + 1;
+            HIPCHK(hipMemsetAsync(g->dwork, 0, sizeof(u32), g->st));
+            HIPCHK(mantra_launch_sweep(&a, 1, lb, g->st));
+            o.launches += 1;
         }
-        if (!g->dhist) HIPCHK(dalloc(&g->dhist, (size_t)kOrderBuckets));
-        HIPCHK(mantra_launch_order(&a, g->dbucket, g->dhist, g->dorder, g->st));
-        a.pq = g->dorder;
+        HIPCHK(hipEventRecord(g->ev1, g->st));
+        a.qbase = 0;
+        a.npairs = sp.npairs;
+    } else if (rg) {
+        HIPCHK(hipMemcpyAsync(g->dnp, &sp.npairs, sizeof(int64_t), hipMemcpyHostToDevice, g->st));
+        a.npairs_dev = g->dnp;
+        // buffers moved since the capture: capture again
+        if (rg->exec && (rg->ns != ns || memcmp(&rg->args, &a, sizeof a) != 0)) rg->release();
+        if (!rg->exec) {
+            rg->cap = slots;
+            rg->ns = ns;
+            memcpy(&rg->args, &a, sizeof a);
+            HIPCHK(hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal));
+            int crc = issue_kernels(g, a, ns, lb, rg);
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(g->st, &gr);
+            if (crc) { if (gr) hipGraphDestroy(gr); return crc; }
+            HIPCHK(e);
+            rg->graph = gr;
+            HIPCHK(hipGraphInstantiate(&rg->exec, rg->graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipEventRecord(g->ev0, g->st));
+        HIPCHK(hipGraphLaunch(rg->exec, g->st));
+        HIPCHK(hipEventRecord(g->ev1, g->st));
+        o.launches += 1;
+        o.reduced = true;
+    } else {
+        if ((rc = issue_kernels(g, a, ns, lb, nullptr))) return rc;
+        o.launches += 1;
     }
-    HIPCHK(hipEventRecord(g->ev0, g->st));
-    HIPCHK(mantra_launch_sweep(&a, ns, lb, g->st));
-    HIPCHK(hipEventRecord(g->ev1, g->st));
     int32_t nretry = 0;
     HIPCHK(hipMemcpyAsync(&nretry, g->dretry, sizeof(int32_t), hipMemcpyDeviceToHost, g->st));
     HIPCHK(hipStreamSynchronize(g->st));
-    float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
     o.ms += ms;
-    o.launches += 1;
     u64 st1[16];
     HIPCHK(hipMemcpy(st1, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
     if (nretry > 0) {
-        // pairs whose appearance-DAG arcs exceeded the slab capacity
         // pairs whose arcs overflowed get slabs that hold every edge of the
         // graph, as many as a fifth of device memory allows
+        o.reduced = false;
         int64_t cap2 = g->m + 1;
         int64_t fit = (int64_t)(device_bytes(g) / 5 / (slab_state_bytes(g) + (size_t)cap2 * 32));
         int ns2 = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int>(nretry, 64), fit));
@@ -406,11 +472,11 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o) {
         int32_t *dq = nullptr;
         HIPCHK(dalloc(&dq, (size_t)nretry));
         HIPCHK(hipMemcpy(dq, q.data() + 1, sizeof(int32_t) * nretry, hipMemcpyHostToDevice));
-        HIPCHK(hipMemsetAsync(g->dwork, 0, sizeof(u32), g->st));
-        HIPCHK(hipMemsetAsync(g->dstats, 0, sizeof(u64) * 16, g->st));
-        HIPCHK(hipMemsetAsync(g->dretry, 0, sizeof(int32_t), g->st));
+        HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, g->dstats, g->st));
         a.sl = g->pool_big.view();
         a.npairs = nretry;
+        a.npairs_dev = nullptr;
+        a.qbase = 0;
         a.pq = dq;
         HIPCHK(hipEventRecord(g->ev0, g->st));
         HIPCHK(mantra_launch_sweep(&a, ns2, lb, g->st));
@@ -431,7 +497,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o) {
     memcpy(o.st, st1, sizeof(st1));
     // busy share of the first launch's persistent grid
     const u64 span = st1[10] - ~st1[11];
-    o.balance = span ? (double)st1[9] / ((double)ns * (double)span) : 1.0;
+    o.balance = span && !g->per_pair ? (double)st1[9] / ((double)ns * (double)span) : 1.0;
     if (st1[6]) return fail(MANTRA_E_INTERNAL, "%llu pairs failed flow conservation", (unsigned long long)st1[6]);
     return MANTRA_OK;
 }
@@ -452,19 +518,29 @@ static void timing_add(mantra_graph *g, const SweepOut &o) {
 }
 
 // per-block partials of max W, sum B, max R_j
+int reduce_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256)); }
+
+int reduce_part_ensure(mantra_graph *g, int c) {
+    if (g->dpart && g->part_c >= c) return MANTRA_OK;
+    hipFree(g->dpart);
+    g->dpart = nullptr;
+    g->part_blocks = 1024;
+    g->part_c = std::max(c, 64);
+    HIPCHK(dalloc(&g->dpart, (size_t)1024 * (2 + g->part_c)));
+    return MANTRA_OK;
+}
+
+// launch (unless a graph replay already did) and read back the reduction
 static int reduce(mantra_graph *g, const double *W, const double *B, const double *R, int64_t n, int c,
-                  double *maxW, double *sumB, std::vector<double> &maxR) {
-    int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
-    if (g->part_blocks < blocks || g->part_c < c) {
-        hipFree(g->dpart);
-        g->dpart = nullptr;
-        g->part_blocks = 1024;
-        g->part_c = std::max(c, 64);
-        HIPCHK(dalloc(&g->dpart, (size_t)1024 * (2 + g->part_c)));
+                  double *maxW, double *sumB, std::vector<double> &maxR, bool launched = false) {
+    const int blocks = reduce_blocks(n);
+    int rc = reduce_part_ensure(g, c);
+    if (rc) return rc;
+    if (!launched) {
+        ReduceArgs ra;
+        ra.W = W; ra.B = B; ra.R = R; ra.n = n; ra.c = c; ra.part = g->dpart;
+        HIPCHK(mantra_launch_reduce(&ra, blocks, g->st));
     }
-    ReduceArgs ra;
-    ra.W = W; ra.B = B; ra.R = R; ra.n = n; ra.c = c; ra.part = g->dpart;
-    HIPCHK(mantra_launch_reduce(&ra, blocks, g->st));
     std::vector<double> part((size_t)blocks * (2 + c));
     HIPCHK(hipMemcpyAsync(part.data(), g->dpart, sizeof(double) * part.size(), hipMemcpyDeviceToHost, g->st));
     HIPCHK(hipStreamSynchronize(g->st));
@@ -572,6 +648,7 @@ size_t req_mem_bytes(const mantra_graph *g, const mantra_request &rq) {
 }
 
 void req_release(ReqRun &q) {
+    q.rg.release();
     q.acc.release();
     q.boot.release();
     hipFree(q.rstat);
@@ -682,7 +759,7 @@ int req_advance(mantra_graph *g, ReqRun &q) {
     if (g->G == 1) {
         double mw, sumB;
         std::vector<double> mr;
-        if ((rc = reduce(g, q.acc.W, q.acc.B, q.acc.R, g->n_total, c, &mw, &sumB, mr))) return rc;
+        if ((rc = reduce(g, q.acc.W, q.acc.B, q.acc.R, g->n_total, c, &mw, &sumB, mr, q.reduced))) return rc;
         const double W = std::max(mw, 0.0) / (double)r;
         double Rc = 0;
         for (int j = 0; j < c; ++j) Rc += mr[(size_t)j] / (double)r;
@@ -732,10 +809,17 @@ static int run_request(mantra_graph *g, const mantra_request &rq, mantra_result 
         const int64_t cnt = req_pending(q);
         sp.reqs.push_back(req_slice(q, cnt, 0));
         sp.npairs = cnt;
+        // progressive rounds: one graph, captured for the largest round
+        RoundGraph *rg = nullptr;
+        if (g->graph_rounds && !g->per_pair && q.phase == ReqRun::ROUND && q.rq.fixed_r <= 0) {
+            rg = &q.rg;
+            if (!rg->exec) { rg->cap = q.om; rg->W = q.acc.W; rg->B = q.acc.B; rg->R = q.acc.R; rg->c = q.c; }
+        }
         SweepOut o;
-        rc = run_sweep(g, sp, o);
+        rc = run_sweep(g, sp, o, rg);
         timing_add(g, o);
         q.R.gpu_ms += o.ms;
+        q.reduced = o.reduced;
         if (!rc) rc = req_advance(g, q);
     }
     q.rc = rc;
@@ -778,7 +862,7 @@ void mantra_graph_destroy(mantra_graph *g) {
     hipFree(g->dU); hipFree(g->dV); hipFree(g->dT); hipFree(g->dout_t); hipFree(g->din_t);
     hipFree(g->dout_off); hipFree(g->din_off); hipFree(g->dseg_eoff); hipFree(g->dseg_noff); hipFree(g->dperm);
     hipFree(g->dwork); hipFree(g->dstats); hipFree(g->dretry); hipFree(g->dpart); hipFree(g->dreqs);
-    hipFree(g->dbucket); hipFree(g->dorder); hipFree(g->dhist);
+    hipFree(g->dbucket); hipFree(g->dorder); hipFree(g->dhist); hipFree(g->dnp);
     if (g->ev0) hipEventDestroy(g->ev0);
     if (g->ev1) hipEventDestroy(g->ev1);
     if (g->st) hipStreamDestroy(g->st);
@@ -808,6 +892,7 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg) {
     g->user_cap = cfg->arc_cap;
     g->order_mode = cfg->order;
     g->graph_rounds = cfg->graph_rounds ? 1 : 0;
+    g->per_pair = cfg->per_pair_launch ? 1 : 0;
     return MANTRA_OK;
 }
 
@@ -817,6 +902,7 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {
     cfg->arc_cap = auto_cap(g, cfg->n_slabs);
     cfg->order = g->order_mode;
     cfg->graph_rounds = g->graph_rounds;
+    cfg->per_pair_launch = g->per_pair;
     return MANTRA_OK;
 }
 

@@ -27,6 +27,7 @@ extern "C" {
 hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
 hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st);
 hipError_t mantra_launch_fill(mantra::u64 *p, mantra::u64 val, int64_t n, hipStream_t st);
+hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u64 *stats, hipStream_t st);
 hipError_t mantra_launch_order(const mantra::LaunchArgs *a, mantra::u32 *bucket, mantra::u64 *hist,
                                int32_t *order, hipStream_t st);
 size_t mantra_tab_lds_bytes(void);
@@ -105,6 +106,8 @@ struct mantra_graph {
     int64_t user_cap = 0;
     int order_mode = MANTRA_ORDER_LONGEST_FIRST;
     int graph_rounds = 0;
+    int per_pair = 0;               // unbatched form: one launch per pair
+    int64_t *dnp = nullptr;         // pair count of a graph replay
     // launch order scratch
     mantra::u32 *dbucket = nullptr;
     int32_t *dorder = nullptr;
@@ -154,9 +157,24 @@ struct SweepOut {
     double ms = 0;
     int launches = 0;
     double balance = 1.0;  // busy share of the persistent grid
+    bool reduced = false;  // the graph replay also ran the request's reduction
 };
 
-int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o);
+// the launch sequence of one request's progressive rounds as a HIP graph
+struct RoundGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t cap = 0;                  // launch slots it was captured for
+    LaunchArgs args;                  // kernel arguments at capture
+    int ns = 0;
+    const double *W = nullptr, *B = nullptr, *R = nullptr;  // the reduction's sums
+    int c = 0;
+    void release();
+};
+
+int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg = nullptr);
+int reduce_blocks(int64_t n);
+int reduce_part_ensure(mantra_graph *g, int c);
 // persistent workgroups of a launch on this graph
 int auto_slabs(const mantra_graph *g);
 
@@ -190,6 +208,8 @@ struct ReqRun {
     int64_t issued = 0;            // pairs of the phase handed to launches
     int64_t om = 0;
     int round = 0;
+    RoundGraph rg;                 // graph of the rounds (blocking calls with graph_rounds)
+    bool reduced = false;          // the last launch already ran the phase reduction
     int rc = MANTRA_OK;
     std::string err;               // error text of rc
     std::chrono::steady_clock::time_point t_start;  // submission (set by req_begin if unset)

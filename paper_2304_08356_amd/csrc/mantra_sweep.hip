@@ -1035,11 +1035,12 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
     u32 stamp = 1;  // reverse table stamps (0 = empty)
     const u64 t_begin = wall_clock64();
     __syncthreads();
+    const int64_t np = a.npairs_dev ? *a.npairs_dev : a.npairs;
     for (;;) {
         u32 qq = 0;
         if (l == 0) qq = atomicAdd(a.work, 1u);
-        int64_t q = (int64_t)(u32)uni((int)qq);
-        if (q >= a.npairs) break;
+        const int64_t q = a.qbase + (int64_t)(u32)uni((int)qq);
+        if (q >= np) break;
         Pair P;
         resolve_pair(a, q, P);
         serial += 1;
@@ -1190,7 +1191,7 @@ __device__ __forceinline__ u32 order_bucket(u64 est) {
 
 __global__ void __launch_bounds__(256) k_pair_keys(LaunchArgs a, u32 *bucket, u64 *hist) {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= a.npairs) return;
+    if (slot >= (a.npairs_dev ? *a.npairs_dev : a.npairs)) return;
     a.pq = nullptr;
     Pair P;
     resolve_pair(a, slot, P);
@@ -1229,9 +1230,10 @@ __global__ void k_order_scan(u64 *hist) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_order_scatter(int64_t npairs, const u32 *bucket, u64 *cursor, int32_t *order) {
+__global__ void __launch_bounds__(256) k_order_scatter(int64_t npairs, const int64_t *npairs_dev, const u32 *bucket,
+                                                       u64 *cursor, int32_t *order) {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= npairs) return;
+    if (slot >= (npairs_dev ? *npairs_dev : npairs)) return;
     const u64 pos = atomicAdd((unsigned long long *)&cursor[bucket[slot]], 1ull);
     order[pos] = (int32_t)slot;
 }
@@ -1274,6 +1276,10 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
     }
 }
 
+__global__ void k_zero_u32(u32 *a, u32 *b) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) { *a = 0u; *b = 0u; }
+}
+
 __global__ void k_fill_u64(u64 *p, u64 val, int64_t n) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t st = (int64_t)gridDim.x * blockDim.x;
@@ -1309,8 +1315,15 @@ hipError_t mantra_launch_order(const mantra::LaunchArgs *a, mantra::u32 *bucket,
     hipLaunchKernelGGL(mantra::k_fill_u64, dim3(1), dim3(256), 0, st, hist, 0ull, (int64_t)mantra::kOrderBuckets);
     hipLaunchKernelGGL(mantra::k_pair_keys, dim3((unsigned)blocks), dim3(256), 0, st, *a, bucket, hist);
     hipLaunchKernelGGL(mantra::k_order_scan, dim3(1), dim3(64), 0, st, hist);
-    hipLaunchKernelGGL(mantra::k_order_scatter, dim3((unsigned)blocks), dim3(256), 0, st, a->npairs,
+    hipLaunchKernelGGL(mantra::k_order_scatter, dim3((unsigned)blocks), dim3(256), 0, st, a->npairs, a->npairs_dev,
                        (const mantra::u32 *)bucket, hist, order);
+    return hipGetLastError();
+}
+// zero the launch counters (work counter, retry count, statistics) with
+// kernels, so that the sequence can be captured in a graph
+hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u64 *stats, hipStream_t st) {
+    hipLaunchKernelGGL(mantra::k_zero_u32, dim3(1), dim3(64), 0, st, work, retry);
+    hipLaunchKernelGGL(mantra::k_fill_u64, dim3(1), dim3(64), 0, st, stats, 0ull, (int64_t)16);
     return hipGetLastError();
 }
 size_t mantra_tab_lds_bytes(void) { return sizeof(mantra::TabLds); }

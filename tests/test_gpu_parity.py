@@ -277,3 +277,59 @@ def test_launch_configs_same_results(lib):
     finally:
         gg.set_launch()
     assert gg.get_launch()["order"] == 0
+
+
+@pytest.mark.parametrize("opt", ["sh", "sfm", "pfm"])
+def test_graph_rounds_match_eager(lib, opt):
+    """Progressive rounds replayed from one captured HIP graph (several
+    replays, with the host's reductions and bound checks between them) give
+    the eager launches' schedule, stop and estimates; on the tiny workload
+    also the oracle's Algorithm 1."""
+    G = workload("tiny-uniform-n100")
+    gg, og = both(lib, G)
+    eager = gg.run(opt, eps=0.02, delta=0.1, seed=21, c=16)
+    gg.set_launch(graph_rounds=True)
+    try:
+        graph = gg.run(opt, eps=0.02, delta=0.1, seed=21, c=16)
+        again = gg.run(opt, eps=0.02, delta=0.1, seed=21, c=16)  # a fresh capture per request
+    finally:
+        gg.set_launch()
+    assert eager[2]["rounds"] >= 3, eager[2]
+    ref = omantra.estimate(og, opt, 0.02, 0.1, 21, c=16, mode=0)
+    for got in (graph, again):
+        for k in ("samples", "rounds", "omega", "s1", "n_reachable", "flags"):
+            assert got[2][k] == eager[2][k], (k, got[2][k], eager[2][k])
+        ok, worst = rel_close(got[0], eager[0], rel=1e-12, abs_floor=1e-300)
+        assert ok, worst
+        ok, worst = rel_close(got[0], ref["node_bc"], rel=1e-12, abs_floor=1e-300)
+        assert ok, worst
+    # a larger graph: rounds of thousands of pairs
+    H = chung_lu_graph(4000, 80_000, 2.3, 5000, seed=77, times="pareto")
+    hg = lib.Graph.of(H)
+    e2 = hg.run(opt, eps=0.04, delta=0.1, seed=22, c=8, edges=True)
+    hg.set_launch(graph_rounds=True)
+    g2 = hg.run(opt, eps=0.04, delta=0.1, seed=22, c=8, edges=True)
+    for k in ("samples", "rounds", "omega", "s1", "n_reachable"):
+        assert g2[2][k] == e2[2][k], k
+    for x, y in ((g2[0], e2[0]), (g2[1], e2[1])):
+        ok, worst = rel_close(x, y, rel=1e-12, abs_floor=1e-300)
+        assert ok, worst
+
+
+def test_per_pair_launches_match(tiny_workload):
+    """The unbatched form (one launch per pair) computes the same records
+    and sums as the persistent launch."""
+    G, gg, og = tiny_workload
+    S, Z = oracle.draw_pairs(31, oracle.STREAM_PAIR, G.n, 0, 120)
+    rec0, nf0, _ = gg.count_pairs("sfm", S, Z, node_f=True)
+    nb0, _, r0 = gg.run("sh", fixed_r=150, seed=32, c=4)
+    gg.set_launch(per_pair_launch=True)
+    try:
+        rec1, nf1, _ = gg.count_pairs("sfm", S, Z, node_f=True)
+        nb1, _, r1 = gg.run("sh", fixed_r=150, seed=32, c=4)
+        assert gg.last_timing()["launches"] == 150
+    finally:
+        gg.set_launch()
+    assert np.array_equal(rec0, rec1) and np.array_equal(nf0, nf1)
+    ok, worst = rel_close(nb0, nb1, rel=1e-12, abs_floor=1e-300)
+    assert ok, worst
