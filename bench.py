@@ -1,35 +1,64 @@
 """Benchmark of the temporal-betweenness hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--no-forms] [--no-serve] [--no-cpu-baseline]
+    python bench.py --calibrate-copy     (plain copy kernel for the traffic counters)
 
 Workload "mid-chunglu-n50k": directed Chung-Lu temporal graph (degree
 exponent 2.3, n = 50,000, |E| = 2,000,000, bursty Pareto(1.5) renewal
 timestamps over 10^5 ticks), shortest-foremost paths, a fixed sample of
 r = 20,000 pairs per step, node and temporal-edge betweenness, c = 25
 Rademacher vectors.  One step = one whole pass of the hot path: pair and sign
-sampling, forward sweep, reverse dependency sweep, accumulation of the
-estimator sums, the MCERA reduction and the bound on the host.  The graph is
-resident in HBM before the timed region.
+sampling, launch ordering, forward sweep, reverse dependency sweep,
+accumulation of the estimator sums, the MCERA reduction and the bound on the
+host.  The graph is resident in HBM before the timed region.
 
-Prints one JSON line (metric: sampled pairs/s) with a "roofline" object for
-the dominant kernel (the sweep; algorithmic bytes per launch over its mean
-HIP-event duration) and a "cpu_baseline" object (the oracle on the host's
-cores over a bounded sample of the same workload).
+Prints one JSON line (value: sampled pairs/s of the steps) with
+ - "roofline": the sweep kernel's algorithmic bytes per launch over its mean
+   HIP-event duration, against the HBM peak; "traffic" is the DRAM bytes per
+   launch that rocprofv3's FETCH_SIZE / WRITE_SIZE counters read for this
+   kernel source (null once the source differs from the profiled one);
+ - "forms": Algorithm 1 at eps = 0.01, delta = 0.1 on the same graph, as
+   persistent launches, as one replayed HIP graph per round, and the
+   unbatched one-launch-per-pair form (timed on a fixed sample);
+ - "serve": requests with Poisson arrivals (random windows, optimalities,
+   eps in {0.01, 0.005}) through the serving scheduler: p50/p99 latency;
+ - "cpu_baseline": the oracle on the host's cores, on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "sampled pairs/s + temporal edges/s (HBM GB/s vs peak); p50/p99 request latency"
 WORKLOAD = "mid-chunglu-n50k"
 OPT = "sfm"
 R_PER_STEP = 20_000
 C = 25
 HBM_PEAK_GBS = 8000.0
+SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip")
+
+# DRAM traffic of the sweep kernel on the step above (rocprofv3 --pmc
+# FETCH_SIZE, then WRITE_SIZE, summed over the k_sweep dispatches of the
+# profiled run, divided by their count, and scaled by the ratio of bytes to
+# counter bytes that the same counters give for a plain copy of known size),
+# valid for the kernel source with this SHA-256 only.
+TRAFFIC = {
+    "sweep_sha256": "b766b3db4ab30aa7b0a03123d47bc419e07c0e6e2dc1ac25a6db1e9de71917bc",
+    "fetch_bytes_per_launch": 5.229e11,   # 2.55331e8 KiB x 1.99994
+    "write_bytes_per_launch": 7.674e10,   # 7.49416e7 KiB x 1.00000
+}
+
+
+def sha256(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def algorithmic_bytes(t, c):
@@ -42,7 +71,6 @@ def algorithmic_bytes(t, c):
 
 
 def cpu_baseline(G, seed, budget_s=15.0):
-    import numpy as np
     import oracle
     og = oracle.Graph.of(G)
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
@@ -61,12 +89,101 @@ def cpu_baseline(G, seed, budget_s=15.0):
                 done, C, t_used)}
 
 
+def forms(gg, torch, seed):
+    """Algorithm 1 at eps = 0.01, delta = 0.1 (sfm, c = 25) in three launch forms."""
+    out = {}
+    for name, cfg in (("batched", {}), ("graph", {"graph_rounds": True})):
+        gg.set_launch(**cfg)
+        gg.run(OPT, eps=0.01, delta=0.1, seed=seed + 99, c=C)  # warm (pool, capture path)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, res = gg.run(OPT, eps=0.01, delta=0.1, seed=seed, c=C)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"pairs": res["samples"] + res["s_boot"], "rounds": res["rounds"], "wall_s": wall,
+                     "pairs_per_s": (res["samples"] + res["s_boot"]) / wall, "xi": res["xi"]}
+    # the unbatched form: one single-workgroup launch per pair, on a fixed
+    # sample (a whole progressive run this way takes minutes)
+    r = 256
+    gg.set_launch(per_pair_launch=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gg.run(OPT, fixed_r=r, seed=seed, c=C)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out["plain"] = {"pairs": r, "wall_s": wall, "pairs_per_s": r / wall,
+                    "note": "fixed sample of %d pairs, one launch per pair" % r}
+    gg.set_launch()
+    base = out["plain"]["pairs_per_s"]
+    for k in ("batched", "graph"):
+        out[k]["speedup_vs_plain"] = out[k]["pairs_per_s"] / base
+    return out
+
+
+def serve(gg, G, torch, n_req=12, rate=50.0, seed=4002):
+    """Poisson arrivals at `rate` req/s; each request a random window of
+    5-100% of the span, a uniform optimality and eps in {0.01, 0.005}."""
+    import numpy as np
+    from synthgen import request_stream
+    reqs = request_stream(n_req, rate, int(G.t.min()), int(G.t.max()), seed)
+    opts = ("sh", "fm", "sfm", "pfm")
+    lat = [None] * n_req
+    pairs = [0] * n_req
+    errs = []  # saturated fm counts (E_OVERFLOW): reported, never rounded
+    t_start = time.perf_counter()
+
+    def waiter(i, tk):
+        try:
+            res = tk.poll(timeout_ms=-1)
+        except Exception as e:  # noqa: BLE001 - saturated fm counts are reported, not fatal
+            res = tk.result
+            errs.append(str(e))
+        if res is not None:
+            lat[i] = res["latency_ms"]
+            pairs[i] = res["samples"] + res["s_boot"]
+
+    threads = []
+    for i, rq in enumerate(reqs):
+        delay = t_start + rq["arrival_s"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tk = gg.submit(opts[rq["opt"]], eps=rq["eps"], delta=rq["delta"], seed=rq["seed"] % (2**63), c=C,
+                       t0=rq["t0"], t1=rq["t1"])
+        th = threading.Thread(target=waiter, args=(i, tk))
+        th.start()
+        threads.append(th)
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    L = np.array([x for x in lat if x is not None])
+    return {"requests": n_req, "offered_req_per_s": rate, "completed": int(L.size), "wall_s": wall,
+            "completed_req_per_s": L.size / wall, "pairs_per_s": sum(pairs) / wall,
+            "p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99)),
+            "overflowed": len(errs), "workload": WORKLOAD + " windows/optimalities/eps of the serving recipe"}
+
+
+def calibrate_copy(torch):
+    """A plain device-to-device copy of known size, for scaling the traffic
+    counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
+    n = 1 << 28  # 256 Mi floats = 1 GiB each way
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--seed", type=int, default=2002)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -74,10 +191,13 @@ def main():
               "independent, so N GPUs would each take 1/N of the pairs)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+    assert torch.cuda.is_available(), "bench needs the GPU"
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
     import paper_2304_08356_amd as pk
     from synthgen import workload
 
-    assert torch.cuda.is_available(), "bench needs the GPU"
     G = workload(WORKLOAD)
     gg = pk.Graph.of(G)
     for i in range(args.warmup):
@@ -85,12 +205,15 @@ def main():
     torch.cuda.synchronize()
     tot = {"sweep_ms": 0.0, "launches": 0, "window_edges": 0, "arcs": 0, "touched_nodes": 0,
            "touched_edges": 0}
+    bal = 0.0
     t0 = time.perf_counter()
     for k in range(args.steps):
         _, _, res = gg.run(OPT, fixed_r=R_PER_STEP, seed=args.seed + k, c=C, edges=True)
         t = gg.last_timing()
         for key in tot:
             tot[key] += t[key]
+        bal += t["balance"] * t["sweep_ms"]
+        print("step %d: %.1f ms sweep" % (k, t["sweep_ms"]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     pairs = R_PER_STEP * args.steps
@@ -98,8 +221,11 @@ def main():
     kern_ms = tot["sweep_ms"] / max(1, tot["launches"])
     abytes = algorithmic_bytes(tot, C) / max(1, tot["launches"])
     achieved = abytes / (kern_ms / 1e3) / 1e9
+    traffic = None
+    if TRAFFIC["sweep_sha256"] == sha256(SWEEP_SRC) and TRAFFIC["fetch_bytes_per_launch"]:
+        traffic = TRAFFIC["fetch_bytes_per_launch"] + TRAFFIC["write_bytes_per_launch"]
     out = {
-        "metric": "sampled pairs/s",
+        "metric": METRIC,
         "value": pairs / wall,
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -117,10 +243,15 @@ def main():
         "mean_window_edges": tot["window_edges"] / pairs,
         "mean_arcs": tot["arcs"] / pairs,
         "sweep_ms_per_launch": kern_ms,
+        "grid_balance": bal / max(tot["sweep_ms"], 1e-9),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "mantra::k_sweep", "algorithmic_bytes_per_launch": abytes},
     }
+    if not args.no_forms:
+        out["forms"] = forms(gg, torch, args.seed)
+    if not args.no_serve:
+        out["serve"] = serve(gg, G, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(G, args.seed)
     print(json.dumps(out), flush=True)

@@ -9,6 +9,7 @@ from .graphs import (  # noqa: F401
     uniform_graph,
     chung_lu_graph,
     packed_uniform_graphs,
+    request_stream,
     workload,
     WORKLOADS,
 )
