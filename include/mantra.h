@@ -70,10 +70,13 @@ typedef struct {
 #define MANTRA_REC_OVERFLOW 1u   /* sigma (or an fm visit count) saturated */
 #define MANTRA_REC_HOPS_LIMIT 4u /* a hop count would exceed 65534 */
 
-/* Build a device-resident graph from m edges (src[i], dst[i], t[i]).
- * Rejects ids outside [0, n), self-loops and negative times
- * (MANTRA_E_INVALID); merges exact duplicate triples (counted in
- * mantra_graph_info).  The arrays are copied; the caller keeps them. */
+/* Build a device-resident temporal graph (Preliminaries: a set of temporal
+ * edges (u, v, t) over nodes 0..n-1) from m edges (src[i], dst[i], t[i]),
+ * host arrays of int32.  Rejects ids outside [0, n), self-loops and times
+ * outside [0, 2^31-2] (MANTRA_E_INVALID); merges exact duplicate triples (the
+ * edge set is a set; the count is in mantra_graph_info).  The arrays are
+ * copied; the caller keeps them.  *out receives the handle (NULL on error);
+ * MANTRA_E_NODEV without a gfx950 device, MANTRA_E_OOM if it does not fit. */
 int mantra_graph_create(const int32_t *src, const int32_t *dst, const int32_t *t, int64_t m,
                         int32_t n, uint32_t flags, mantra_graph **out);
 
@@ -91,13 +94,17 @@ void mantra_graph_destroy(mantra_graph *g);
 int mantra_graph_info(const mantra_graph *g, int32_t *n, int64_t *m_unique, int64_t *n_duplicates,
                       int32_t *t_min, int32_t *t_max, int32_t *n_graphs);
 
-/* Test / measurement entry point: exact counts for r explicit pairs
- * (s[q], z[q]) in window [t0, t1].  out[r] receives the records.  Optional
- * dense outputs (NULL to skip): node_f[r*n] gets f(v|s,z) = N(v)/sigma and
- * edge_f[r*m] gets f(e|s,z) per input edge index (duplicates share their
- * merged edge's value), for pairs whose counts did not saturate.  For packed
- * graphs, graph[q] names the pair's graph (NULL for a single graph) and node
- * ids are local. */
+/* Test / measurement entry point: the per-pair quantities of Definition 1
+ * and of the estimator of Section 4.1 for r explicit pairs (s[q], z[q]) in the
+ * window [t0, t1] (host int32 arrays of length r, s[q] != z[q]).  out[r]
+ * receives the records.  Optional dense outputs (host, row-major, NULL to
+ * skip): node_f[r*n] gets f(v|s,z) = N(v)/sigma and edge_f[r*m] gets
+ * f(e|s,z) (Appendix, temporal edges) per input edge index (duplicates share
+ * their merged edge's value), for pairs whose counts did not saturate; at
+ * most 4e9 doubles each (MANTRA_E_INVALID beyond).  For packed graphs,
+ * graph[q] names the pair's graph (NULL for a single graph) and node ids are
+ * local to it.  Records of saturated pairs carry MANTRA_REC_OVERFLOW; the
+ * call itself still returns MANTRA_OK. */
 int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r,
                        const int32_t *graph, const int32_t *s, const int32_t *z,
                        mantra_pair_record *out, double *node_f, double *edge_f);
@@ -142,20 +149,33 @@ typedef struct {
 #define MANTRA_RES_STOP_XI 2u      /* stopped because xi <= eps */
 #define MANTRA_RES_STOP_OMEGA 4u   /* stopped because |S| >= omega */
 
-/* Algorithm 1 on the whole span with the paper's defaults (c = 25): blocking.
- * node_bc[n] receives the estimates. */
+/* Algorithm 1 (bootstrap, sample-size bound of Theorem 3, progressive
+ * rounds stopped by the c-MCERA bound of Theorem 1) on the whole time span
+ * with the experimental defaults (c = 25), blocking.  node_bc (host, [n],
+ * caller-owned) receives the estimates of the temporal betweenness of every
+ * node, input node order.  MANTRA_E_OVERFLOW (estimates NaN) if a sampled
+ * pair's count saturated; out (may be NULL) gets the run's statistics. */
 int mantra_estimate(mantra_graph *g, mantra_opt opt, double eps, double delta, uint64_t seed,
                     double *node_bc, mantra_result *out);
 
-/* Blocking run of one request (window, c, fixed sample, edge estimates). */
+/* Blocking run of one request: Algorithm 1 as above, or with fixed_r > 0 a
+ * fixed sample of fixed_r pairs (per packed graph), over the request's window,
+ * with c sign vectors and, with MANTRA_F_EDGE_BC, temporal-edge estimates in
+ * edge_bc[m] (input edge order).  Same errors as mantra_estimate. */
 int mantra_run(mantra_graph *g, const mantra_request *req, mantra_result *out);
 
-/* Serving: non-blocking submission to the graph's scheduler, which batches the
- * rounds of all admitted requests into shared launches.  Admission is by the
- * device memory a request's sums need; a request that can never fit returns
- * MANTRA_E_TOO_LARGE.  mantra_poll waits up to timeout_ms (0: no wait, < 0:
- * forever) and returns MANTRA_OK (result filled, ticket consumed),
- * MANTRA_PENDING, or an error (ticket consumed). */
+/* Serving (not in the paper: a request loop around Algorithm 1).  Non-blocking
+ * submission to the graph's scheduler thread, which batches the phases of all
+ * admitted requests into shared sweep launches.  Admission is FIFO by the
+ * device memory a request's sums need (8n(2+c) + 8m with edge estimates,
+ * + 24n for the bootstrap); a request that can never fit the budget returns
+ * MANTRA_E_TOO_LARGE at once, invalid requests MANTRA_E_INVALID.  The
+ * buffers named in the request must stay valid until the ticket finishes.
+ * mantra_poll waits up to timeout_ms (0: no wait, < 0: forever) and returns
+ * MANTRA_OK (result filled, ticket consumed), MANTRA_PENDING, or the request's
+ * error (result filled, ticket consumed); MANTRA_E_INVALID for an unknown or
+ * consumed ticket.  Destroying the graph fails the requests it still holds
+ * (MANTRA_E_INTERNAL). */
 int mantra_submit(mantra_graph *g, const mantra_request *req, uint64_t *ticket);
 int mantra_poll(uint64_t ticket, mantra_result *out, int32_t timeout_ms);
 
