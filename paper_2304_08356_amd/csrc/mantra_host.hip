@@ -259,13 +259,25 @@ static size_t slab_state_bytes(const mantra_graph *g) {
 
 // device memory and the share of it the slab pool (state and arc buffers)
 // may take
-static size_t device_bytes(const mantra_graph *g) {
-    size_t fr = 0, tot = 0;
+static void device_mem(const mantra_graph *g, size_t *fr, size_t *tot) {
+    *fr = 0;
+    *tot = 0;
     hipSetDevice(g->device);
-    hipMemGetInfo(&fr, &tot);
+    hipMemGetInfo(fr, tot);
+}
+static size_t device_bytes(const mantra_graph *g) {
+    size_t fr, tot;
+    device_mem(g, &fr, &tot);
     return tot;
 }
-static size_t pool_budget(const mantra_graph *g) { return (size_t)(0.45 * (double)device_bytes(g)); }
+// 45% of the device, less when other graphs or callers already hold memory
+// (the graph's own pool counts as available)
+static size_t pool_budget(const mantra_graph *g) {
+    size_t fr, tot;
+    device_mem(g, &fr, &tot);
+    const size_t own = g->pool.nslabs ? (size_t)g->pool.nslabs * (slab_state_bytes(g) + (size_t)g->pool.cap * 32) : 0;
+    return (size_t)std::min(0.45 * (double)tot, 0.7 * (double)(fr + own));
+}
 
 int auto_slabs(const mantra_graph *g) {
     if (g->user_slabs > 0) return g->user_slabs;
@@ -463,7 +475,9 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         // graph, as many as a fifth of device memory allows
         o.reduced = false;
         int64_t cap2 = g->m + 1;
-        int64_t fit = (int64_t)(device_bytes(g) / 5 / (slab_state_bytes(g) + (size_t)cap2 * 32));
+        size_t fr, tot;
+        device_mem(g, &fr, &tot);
+        int64_t fit = (int64_t)(std::min(tot / 5, fr / 2) / (slab_state_bytes(g) + (size_t)cap2 * 32));
         int ns2 = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int>(nretry, 64), fit));
         rc = pool_ensure(g, g->pool_big, ns2, cap2);
         if (rc) return rc;
@@ -488,6 +502,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         u64 st2[16];
         HIPCHK(hipMemcpy(st2, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
         hipFree(dq);
+        g->pool_big.release();  // rare and large: not kept between launches
         int32_t n2 = 0;
         HIPCHK(hipMemcpy(&n2, g->dretry, sizeof(int32_t), hipMemcpyDeviceToHost));
         if (n2 > 0) return fail(MANTRA_E_INTERNAL, "arc buffer of a full window overflowed");
