@@ -206,6 +206,15 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg);
 /* the configuration in force, automatic values resolved */
 int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg);
 
+/* Autotuner: times the sweep on a calibration sample of sample_pairs pairs
+ * (0: twice the automatic grid) drawn for optimality opt from the bootstrap
+ * stream of seed, under candidate grid sizes (all, 3/4 and 1/2 of the
+ * resident workgroups) and both pair orders, then keeps the fastest as the
+ * graph's launch configuration and writes it to *best (may be NULL).
+ * Blocking; results of later calls do not depend on the choice. */
+int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint64_t seed,
+                    mantra_launch_config *best);
+
 /* Work and timing of the last blocking call on g: device time of the sweep
  * kernel launches (HIP events on the graph's stream), their count, the
  * totals over its pairs of swept window edges, recorded appearance-DAG arcs,

@@ -95,6 +95,13 @@ class Graph:
                                 per_pair_launch=1 if per_pair_launch else 0)
         _lib.check(_lib._lib.mantra_set_launch(self._h, ctypes.byref(cfg)))
 
+    def autotune(self, opt, sample_pairs=0, seed=0):
+        """Pick the launch configuration by timing candidates on a
+        calibration sample; returns the configuration kept."""
+        cfg = _lib.LaunchConfig()
+        _lib.check(_lib._lib.mantra_autotune(self._h, _opt(opt), int(sample_pairs), int(seed), ctypes.byref(cfg)))
+        return cfg.to_dict()
+
     def get_launch(self):
         cfg = _lib.LaunchConfig()
         _lib.check(_lib._lib.mantra_get_launch(self._h, ctypes.byref(cfg)))

@@ -74,6 +74,7 @@ SIGNATURES = {
     "mantra_serve_config": (I32, [P, U64, I32]),
     "mantra_set_launch": (I32, [P, P]),
     "mantra_get_launch": (I32, [P, P]),
+    "mantra_autotune": (I32, [P, I32, I64, U64, P]),
     "mantra_last_timing": (I32, [P, P, P, P, P, P, P, P]),
     "mantra_last_error": (ctypes.c_char_p, []),
 }

@@ -841,6 +841,67 @@ static int run_request(mantra_graph *g, const mantra_request &rq, mantra_result 
     return req_finish(g, q, res);
 }
 
+// ------------------------------------------------------------------ autotuner
+
+// Times candidate launch configurations on a calibration sample of pairs
+// (their own stream, so no request's pairs are touched) and keeps the
+// fastest: the number of persistent workgroups (pairs in flight) and the
+// order pairs are handed out in.  The arc capacity follows the slab count
+// (the rest of the pool budget).  Results never depend on the choice.
+static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t seed, mantra_launch_config *best) {
+    const int saved_slabs = g->user_slabs, saved_order = g->order_mode;
+    const int64_t saved_cap = g->user_cap;
+    g->user_slabs = 0;
+    g->user_cap = 0;
+    const int full = auto_slabs(g);
+    if (sample <= 0) sample = std::max<int64_t>(2 * (int64_t)full, 256);
+    mantra_request rq;
+    memset(&rq, 0, sizeof rq);
+    rq.opt = opt;
+    rq.t0 = 0;
+    rq.t1 = INT32_MAX;
+    rq.seed = seed;
+    std::vector<int> slabs = {full, std::max(1, (3 * full) / 4), std::max(1, full / 2)};
+    slabs.erase(std::unique(slabs.begin(), slabs.end()), slabs.end());
+    double best_ms = INFINITY;
+    int best_slabs = full, best_order = MANTRA_ORDER_LONGEST_FIRST;
+    int rc = MANTRA_OK;
+    for (int order : {MANTRA_ORDER_LONGEST_FIRST, MANTRA_ORDER_DRAWN}) {
+        for (int ns : slabs) {
+            g->user_slabs = ns;
+            g->order_mode = order;
+            LaunchSpec sp;
+            DevReq d = make_req(rq, STREAM_BOOT, 0, 0, sample, nullptr, 0);
+            d.graph = g->G == 1 ? 0 : -1;
+            d.per_graph = (sample + g->G - 1) / g->G;
+            sp.reqs.push_back(d);
+            sp.npairs = g->G == 1 ? sample : d.per_graph * g->G;
+            SweepOut o;
+            rc = run_sweep(g, sp, o);
+            if (rc) break;
+            if (o.ms < best_ms) { best_ms = o.ms; best_slabs = ns; best_order = order; }
+        }
+        if (rc) break;
+    }
+    if (rc) {
+        g->user_slabs = saved_slabs;
+        g->user_cap = saved_cap;
+        g->order_mode = saved_order;
+        return rc;
+    }
+    g->user_slabs = best_slabs == full ? 0 : best_slabs;
+    g->user_cap = 0;
+    g->order_mode = best_order;
+    if (best) {
+        best->n_slabs = best_slabs;
+        best->arc_cap = auto_cap(g, best_slabs);
+        best->order = best_order;
+        best->graph_rounds = g->graph_rounds;
+        best->per_pair_launch = g->per_pair;
+    }
+    return MANTRA_OK;
+}
+
 }  // namespace mantra
 
 // ------------------------------------------------------------------ C ABI
@@ -909,6 +970,16 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg) {
     g->graph_rounds = cfg->graph_rounds ? 1 : 0;
     g->per_pair = cfg->per_pair_launch ? 1 : 0;
     return MANTRA_OK;
+}
+
+int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint64_t seed, mantra_launch_config *best) {
+    if (!g) return fail(MANTRA_E_INVALID, "graph is NULL");
+    if (opt < MANTRA_SH || opt > MANTRA_PFM) return fail(MANTRA_E_INVALID, "unknown optimality %d", (int)opt);
+    if (sample_pairs < 0) return fail(MANTRA_E_INVALID, "negative sample size");
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (g->per_pair) return fail(MANTRA_E_INVALID, "the per-pair launch form has nothing to tune");
+    timing_reset(g);
+    return autotune(g, opt, sample_pairs, seed, best);
 }
 
 int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {

@@ -274,6 +274,16 @@ def test_launch_configs_same_results(lib):
                 ok, worst = rel_close(x, y, rel=1e-12, abs_floor=1e-300)
                 assert ok, (cfg, worst)
             assert res["n_reachable"] == ref[3]["n_reachable"] and res["window_edges"] == ref[3]["window_edges"]
+        # the autotuner's pick changes nothing either
+        best = gg.autotune("sfm", sample_pairs=512, seed=5)
+        assert best["n_slabs"] >= 1 and best["order"] in (0, 1)
+        assert gg.get_launch()["order"] == best["order"]
+        rec, _, _ = gg.count_pairs("sfm", S, Z)
+        nb, eb, res = gg.run("sh", fixed_r=1500, seed=93, c=8, edges=True)
+        assert np.array_equal(rec, ref[0])
+        for x, y in ((nb, ref[1]), (eb, ref[2])):
+            ok, worst = rel_close(x, y, rel=1e-12, abs_floor=1e-300)
+            assert ok, ("autotuned", best, worst)
     finally:
         gg.set_launch()
     assert gg.get_launch()["order"] == 0
