@@ -47,6 +47,12 @@ __device__ __forceinline__ u64 rl64(u64 x, int l) {
     return ((u64)(u32)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32) |
            (u64)(u32)__builtin_amdgcn_readlane((int)(u32)x, l);
 }
+// 64-bit value of lane src (per-lane source, through ds_bpermute)
+__device__ __forceinline__ u64 shfl64(u64 x, int src) {
+    const u32 lo = (u32)__shfl((int)(u32)x, src);
+    const u32 hi = (u32)__shfl((int)(u32)(x >> 32), src);
+    return ((u64)hi << 32) | lo;
+}
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ u64 uni64(u64 x) { return rl64(x, __builtin_amdgcn_readfirstlane(lane_id())); }
 
@@ -96,19 +102,14 @@ __device__ __forceinline__ int64_t wave_upper_bound(const int32_t *arr, int64_t 
 
 // ------------------------------------------------------------ LDS layout
 
-enum : u32 { FM_NEEDED = 1u, FM_COMMITTED = 2u };
-
-struct FwdLds {
-    u32 fk[kFwN];         // forwarding table: node + 1 (0 = empty)
-    u32 fm[kFwN];         // FM_NEEDED | FM_COMMITTED
-    u64 ftm[kFwN];        // bit tau: the node is a run head at tick tau of the batch
-    u32 fh[kFwN];         // last committed h
-    u64 fS[kFwN];         // last committed S
+constexpr int kBloomWords = 16;  // 512-bit filter of a batch's run-head nodes
+struct FwdLds {           // forward: reductions of multi-edge runs, head filter
     u32 rmin[kWave];      // per run (by run-start lane): min hop candidate
     u64 rlo[kWave];       // per run: count sum, low 32-bit halves
     u64 rhi[kWave];       //                      high 32-bit halves
-    int32_t dtick[kWave]; // per tick: latest earlier tick one of its edges reads
+    u32 bloom[kBloomWords];
 };
+__device__ __forceinline__ u32 bloom_bit(int32_t node) { return ((u32)node * 2654435761u) >> 23; }  // 9 bits
 struct RevLds {           // reverse: tail state by node, per batch
     u64 tb_key[kFwN];
     u64 tb_acc[kFwN];
@@ -147,32 +148,6 @@ __device__ __forceinline__ int tab_insert(u64 *keys, u32 stamp, u32 node, int *f
     }
     return -1;
 }
-// forwarding table (forward, cleared per batch): find / insert
-__device__ __forceinline__ int fw_find(const u32 *fk, u32 node) {
-    u32 sl = hslot(node);
-    for (int it = 0; it < kFwN; ++it) {
-        u32 k = fk[sl];
-        if (k == 0) return -1;
-        if (k == node + 1) return (int)sl;
-        sl = (sl + 1) & (kFwN - 1);
-    }
-    return -1;
-}
-__device__ __forceinline__ int fw_insert(u32 *fk, u32 node) {
-    u32 sl = hslot(node);
-    for (int it = 0; it < kFwN; ++it) {
-        u32 k = fk[sl];
-        if (k == node + 1) return (int)sl;
-        if (k == 0) {
-            u32 old = atomicCAS(&fk[sl], 0u, node + 1);
-            if (old == 0u || old == node + 1) return (int)sl;
-            continue;  // claimed by another node: look again at this slot
-        }
-        sl = (sl + 1) & (kFwN - 1);
-    }
-    return -1;
-}
-
 __device__ __forceinline__ void lds_sat_add(u64 *p, u64 x) {
     u64 cur = *p;
     for (;;) {
@@ -407,37 +382,30 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
 
 // ------------------------------------------------------------ forward sweep
 
-// element j of a per-slice register array (j is wave-uniform)
-__device__ __forceinline__ u64 pick4(const u64 *m, int j) {
-    u64 r = m[0];
-#pragma unroll
-    for (int i = 1; i < kE; ++i) if (j == i) r = m[i];
-    return r;
+// edges of the batch at b: lane l holds edge b + l (past the window: time
+// INT32_MAX, head -1); tnext = time of edge b + 64, INT32_MAX past the window
+__device__ __forceinline__ void load_batch(const LaunchArgs &a, const Pair &P, int64_t b, int32_t &t, int32_t &u,
+                                           int32_t &v, int32_t &tnext) {
+    const int l = lane_id();
+    const int64_t i = b + l;
+    const bool ld = i < P.hi;
+    t = ld ? a.g.T[i] : INT32_MAX;
+    u = ld ? a.g.U[i] : 0;
+    v = ld ? a.g.V[i] : -1;
+    tnext = (b + kWave < P.hi) ? a.g.T[b + kWave] : INT32_MAX;
 }
 
-__device__ __forceinline__ int32_t pick4i(const int32_t *m, int j) {
-    int32_t r = m[0];
-#pragma unroll
-    for (int i = 1; i < kE; ++i) if (j == i) r = m[i];
-    return r;
-}
-
-// first set bit at offset >= pos over the batch masks, or `none`
-__device__ __forceinline__ int next_bit(const u64 *m, int pos, int none) {
-    for (int j = pos >> 6; j < kE; ++j) {
-        u64 x = pick4(m, j);
-        int b = (j == (pos >> 6)) ? (pos & 63) : 0;
-        x &= kUMax << b;
-        if (x) return j * kWave + (__ffsll((long long)x) - 1);
-    }
-    return none;
-}
-
+// Forward sweep of one pair over its window [P.lo, P.hi), in batches of up to
+// 64 edges (one per lane) that hold whole ticks; a tick longer than 64 edges
+// is a batch of its own (fwd_long_tick).  Within a batch, the edges of tick
+// tau read the state committed before tau: the state at batch start (loaded
+// from the slab) or the commit of an earlier tick of the same batch, passed
+// from the committing lane's registers.  Maximal runs of ticks that read no
+// commit made inside the run ("segments") are processed together.
 __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, FwdLds &L,
                         u32 &agstamp, FwdOut &o) {
     static_assert(kE == 1, "the forward sweep is written for one edge per lane");
     const int l = lane_id();
-    const int32_t *U = a.g.U, *V = a.g.V, *T = a.g.T;
     const int opt = P.opt;
     const u64 le = (l == kWave - 1) ? kUMax : ((2ull << l) - 1ull);  // lanes <= l
     const u32 kBig = 0xFFFFFFFFu;
@@ -449,18 +417,14 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
     o.arcs = 0;
     o.flags = 0;
     o.t_arr = -1;
+    int32_t t, u, v, tnext;
+    load_batch(a, P, b0, t, u, v, tnext);
     while (b0 < P.hi && !done) {
         // ---- batch: up to 64 edges, whole ticks
         const int64_t avail = P.hi - b0;
         const int nb = avail < kWave ? (int)avail : kWave;
-        const bool ld = l < nb;
-        const int32_t t = ld ? T[b0 + l] : INT32_MAX;
-        const int32_t u = ld ? U[b0 + l] : 0;
-        const int32_t v = ld ? V[b0 + l] : -1;
-        for (int i = l; i < kFwN; i += kWave) { L.fk[i] = 0u; L.fm[i] = 0u; L.ftm[i] = 0ull; }
         int nbat = nb;
         if (nb == kWave && b0 + kWave < P.hi) {
-            const int32_t tnext = T[b0 + kWave];
             const int32_t tlast = rl32(t, kWave - 1);
             if (tnext == tlast) {
                 const int first = __ffsll((long long)ballot(t == tlast)) - 1;
@@ -468,8 +432,8 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                     // one tick longer than a batch
                     int64_t g1 = P.hi;
                     for (int64_t i = b0 + kWave; i < P.hi; i += kWave) {
-                        int64_t idx = i + l;
-                        u64 m = ballot(idx < P.hi && T[idx] != tlast);
+                        const int64_t idx = i + l;
+                        const u64 m = ballot(idx < P.hi && a.g.T[idx] != tlast);
                         if (m) { g1 = i + (__ffsll((long long)m) - 1); break; }
                     }
                     __syncthreads();
@@ -479,6 +443,7 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                     if (o.flags & REC_HOPS_LIMIT) return;
                     if (o.arcs > a.sl.cap) { o.flags |= REC_ARCS_LIMIT; return; }
                     if (zhit && opt != OPT_SH) done = true;
+                    load_batch(a, P, b0, t, u, v, tnext);
                     continue;
                 }
                 nbat = first;
@@ -507,55 +472,77 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             const u64 th = S.F[2 * (int64_t)v], x = S.F[2 * (int64_t)v + 1];
             if ((u32)th == P.tag) { hr = true; hv = (u32)(th >> 32) & 0xFFFFu; sv = x; }
         }
+        // the next batch's edges, in flight while this one is processed
+        int32_t t2, u2, v2, tn2;
+        load_batch(a, P, b0 + nbat, t2, u2, v2, tn2);
         // no tail reached at batch start: no tick of the batch can commit
         if (!ballot(rt)) {
             b0 += nbat;
             o.swept = b0 - P.lo;
+            t = t2; u = u2; v = v2; tnext = tn2;
             continue;
         }
+        // ---- in-batch dependencies: mu (mh) = run-head lanes of earlier ticks
+        // whose head is my tail (my head).  A 512-bit filter of the run heads
+        // outside the last tick (LDS) flags the lanes that may have one; each
+        // flagged lane is then matched exactly with two ballots.
+        u64 mu = 0, mh = 0;
+        if (ntick > 1) {
+            const int last0 = 63 - __clzll((long long)gm);  // first lane of the last tick
+            if (l < kBloomWords) L.bloom[l] = 0u;
+            __syncthreads();
+            if (rs && l < last0) {
+                const u32 b = bloom_bit(v);
+                atomicOr(&L.bloom[b >> 5], 1u << (b & 31));
+            }
+            __syncthreads();
+            bool pos = false;
+            if (in && tid > 0) {
+                const u32 bu = bloom_bit(u);
+                pos = (L.bloom[bu >> 5] >> (bu & 31)) & 1u;
+                if (rs) {
+                    const u32 bv = bloom_bit(v);
+                    pos = pos || ((L.bloom[bv >> 5] >> (bv & 31)) & 1u);
+                }
+            }
+            u64 cand = ballot(pos);
+            while (cand) {
+                const int i = __ffsll((long long)cand) - 1;
+                cand &= cand - 1ull;
+                const int first_i = 63 - __clzll((long long)(gm & ((2ull << i) - 1ull)));  // i's tick start
+                const u64 earlier = (1ull << first_i) - 1ull;
+                const int32_t ui = rl32(u, i), vi = rl32(v, i);
+                const u64 mU = ballot(rs && v == ui) & earlier;
+                const u64 mH = ((rsall >> i) & 1ull) ? (ballot(rs && v == vi) & earlier) : 0ull;
+                if (l == i) { mu = mU; mh = mH; }
+            }
+        }
+        // tick of the latest lane I depend on (-1: none)
+        int dtk = -1;
+        if (mu | mh) {
+            const int jl = 63 - __clzll((long long)(mu | mh));
+            dtk = __popcll(gm & ((2ull << jl) - 1ull)) - 1;
+        }
         if (rs) { L.rmin[l] = kBig; L.rlo[l] = 0ull; L.rhi[l] = 0ull; }
-        L.dtick[l] = -1;
         __syncthreads();
-        // ---- in-batch dependencies: at which ticks is each head node a run head
-        int slv = -1, slu = -1;
-        if (rs) {
-            slv = fw_insert(L.fk, (u32)v);
-            if (slv >= 0) atomicOr((unsigned long long *)&L.ftm[slv], 1ull << tid);
-        }
-        __syncthreads();
-        const u64 before = (tid > 0) ? ((1ull << tid) - 1ull) : 0ull;
-        int dep = -1;
-        bool nt = false, nh = false;
-        if (in) {
-            slu = fw_find(L.fk, (u32)u);
-            if (slu >= 0) {
-                const u64 m = L.ftm[slu] & before;
-                if (m) { nt = true; dep = 63 - __clzll((long long)m); atomicOr(&L.fm[slu], FM_NEEDED); }
-            }
-        }
-        if (rs && slv >= 0) {
-            const u64 m = L.ftm[slv] & before;
-            if (m) {
-                nh = true;
-                const int d2 = 63 - __clzll((long long)m);
-                dep = d2 > dep ? d2 : dep;
-                atomicOr(&L.fm[slv], FM_NEEDED);
-            }
-        }
-        if (dep >= 0) atomicMax(&L.dtick[tid], dep);
-        __syncthreads();
-        const bool nd = rs && slv >= 0 && (L.fm[slv] & FM_NEEDED);
-        const int32_t dt = L.dtick[l];  // lane tau: D(tau)
+        // committed state of this batch's run heads (valid where cm is set)
+        u64 cm = 0;
+        u32 ch = 0;
+        u64 cS = 0;
         // ---- segments: maximal runs of ticks that read nothing committed inside them
         int ta = 0;
         while (ta < ntick && !done) {
-            int tb = ta + 1;
-            while (tb < ntick && rl32(dt, tb) < ta) ++tb;
+            const u64 br = ballot(in && tid > ta && dtk >= ta);
+            const int tb = br ? rl32(tid, __ffsll((long long)br) - 1) : ntick;
             const bool act = in && tid >= ta && tid < tb;
-            bool reached = act && rt;
-            u32 h_u = hu;
-            u64 s_u = su;
-            if (act && nt && (L.fm[slu] & FM_COMMITTED)) { reached = true; h_u = L.fh[slu]; s_u = L.fS[slu]; }
+            // tail state: the latest commit of this batch to my tail, else batch start
+            const u64 cu = mu & cm;
+            const int su_lane = cu ? 63 - __clzll((long long)cu) : l;
+            const u32 fh_u = (u32)__shfl((int)ch, su_lane);
+            const u64 fS_u = shfl64(cS, su_lane);
+            bool reached = act && (rt || cu != 0);
+            u32 h_u = cu ? fh_u : hu;
+            u64 s_u = cu ? fS_u : su;
             if (!ballot(reached)) { ta = tb; continue; }
             if (ballot(reached && h_u + 1 >= kHInf)) { o.flags |= REC_HOPS_LIMIT; return; }
             const u32 cand = reached ? h_u + 1 : kBig;
@@ -587,16 +574,18 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                     else { const u64 x = hi << 32; c = x + lo; if (c < x) c = kUMax; }
                 }
             }
-            // run heads decide
+            // run heads decide; head state: the latest commit of this batch to
+            // my head, else batch start
+            const u64 cv = mh & cm;
+            const int sv_lane = cv ? 63 - __clzll((long long)cv) : l;
+            const u32 fh_v = (u32)__shfl((int)ch, sv_lane);
+            const u64 fS_v = shfl64(cS, sv_lane);
             bool ok = false;
             u32 nh2 = 0;
             u64 nS = 0;
             if (lead) {
-                bool rv = hr;
-                u32 h_v = hv;
-                u64 S_v = sv;
-                if (nh && (L.fm[slv] & FM_COMMITTED)) { rv = true; h_v = L.fh[slv]; S_v = L.fS[slv]; }
-                ok = head_commit(opt, rv, h_v, S_v, d, c, v, P.z, zh, &nh2, &nS);
+                const bool rv = hr || cv != 0;
+                ok = head_commit(opt, rv, cv ? fh_v : hv, cv ? fS_v : sv, d, c, v, P.z, zh, &nh2, &nS);
             }
             // fm/sfm/pfm stop at the tick where z is first reached: later ticks
             // of the segment are dropped
@@ -611,12 +600,10 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                 S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh2 << 32);
                 S.F[2 * (int64_t)v + 1] = nS;
                 if (a.lds_bitmap) atomicOr(&bm[v >> 5], 1u << (v & 31));
-                if (nd) {
-                    L.fh[slv] = nh2;
-                    L.fS[slv] = nS;
-                    atomicOr(&L.fm[slv], FM_COMMITTED);
-                }
+                ch = nh2;
+                cS = nS;
             }
+            cm |= ballot(ok);
             const u64 zm = ballot(ok && v == P.z);
             if (zm) {
                 const int zl = __ffsll((long long)zm) - 1;
@@ -647,10 +634,19 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
         if (!done) o.swept = (b0 + nbat) - P.lo;
         __syncthreads();
         b0 += nbat;
+        t = t2; u = u2; v = v2; tnext = tn2;
     }
     o.reached = zh != kHInf;
     o.zh = zh;
     o.zS = zS;
+}
+
+// element j of a per-slice register array (j is wave-uniform)
+__device__ __forceinline__ u64 pick4(const u64 *m, int j) {
+    u64 r = m[0];
+#pragma unroll
+    for (int i = 1; i < kE; ++i) if (j == i) r = m[i];
+    return r;
 }
 
 // ------------------------------------------------------------ reverse sweep
