@@ -523,8 +523,6 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             const int jl = 63 - __clzll((long long)(mu | mh));
             dtk = __popcll(gm & ((2ull << jl) - 1ull)) - 1;
         }
-        if (rs) { L.rmin[l] = kBig; L.rlo[l] = 0ull; L.rhi[l] = 0ull; }
-        __syncthreads();
         // committed state of this batch's run heads (valid where cm is set)
         u64 cm = 0;
         u32 ch = 0;
@@ -536,13 +534,16 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             const int tb = br ? rl32(tid, __ffsll((long long)br) - 1) : ntick;
             const bool act = in && tid >= ta && tid < tb;
             // tail state: the latest commit of this batch to my tail, else batch start
-            const u64 cu = mu & cm;
-            const int su_lane = cu ? 63 - __clzll((long long)cu) : l;
-            const u32 fh_u = (u32)__shfl((int)ch, su_lane);
-            const u64 fS_u = shfl64(cS, su_lane);
+            const u64 cu = act ? (mu & cm) : 0ull;
             bool reached = act && (rt || cu != 0);
-            u32 h_u = cu ? fh_u : hu;
-            u64 s_u = cu ? fS_u : su;
+            u32 h_u = hu;
+            u64 s_u = su;
+            if (ballot(cu != 0)) {
+                const int src = cu ? 63 - __clzll((long long)cu) : l;
+                const u32 fh = (u32)__shfl((int)ch, src);
+                const u64 fS = shfl64(cS, src);
+                if (cu) { h_u = fh; s_u = fS; }
+            }
             if (!ballot(reached)) { ta = tb; continue; }
             if (ballot(reached && h_u + 1 >= kHInf)) { o.flags |= REC_HOPS_LIMIT; return; }
             const u32 cand = reached ? h_u + 1 : kBig;
@@ -558,6 +559,9 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                 c = s_u;
                 lead = reached;
             } else {
+                // runs of several edges: min and exact 96-bit sum through LDS
+                if (act && rs) { L.rmin[l] = kBig; L.rlo[l] = 0ull; L.rhi[l] = 0ull; }
+                __syncthreads();
                 if (reached) atomicMin(&L.rmin[rsl], cand);
                 __syncthreads();
                 d = act ? L.rmin[rsl] : kBig;
@@ -576,17 +580,19 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             }
             // run heads decide; head state: the latest commit of this batch to
             // my head, else batch start
-            const u64 cv = mh & cm;
-            const int sv_lane = cv ? 63 - __clzll((long long)cv) : l;
-            const u32 fh_v = (u32)__shfl((int)ch, sv_lane);
-            const u64 fS_v = shfl64(cS, sv_lane);
+            const u64 cv = lead ? (mh & cm) : 0ull;
+            u32 h_v = hv;
+            u64 S_v = sv;
+            if (ballot(cv != 0)) {
+                const int src = cv ? 63 - __clzll((long long)cv) : l;
+                const u32 fh = (u32)__shfl((int)ch, src);
+                const u64 fS = shfl64(cS, src);
+                if (cv) { h_v = fh; S_v = fS; }
+            }
             bool ok = false;
             u32 nh2 = 0;
             u64 nS = 0;
-            if (lead) {
-                const bool rv = hr || cv != 0;
-                ok = head_commit(opt, rv, cv ? fh_v : hv, cv ? fS_v : sv, d, c, v, P.z, zh, &nh2, &nS);
-            }
+            if (lead) ok = head_commit(opt, hr || cv != 0, h_v, S_v, d, c, v, P.z, zh, &nh2, &nS);
             // fm/sfm/pfm stop at the tick where z is first reached: later ticks
             // of the segment are dropped
             int cut = tb;
