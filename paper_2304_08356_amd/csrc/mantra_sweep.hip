@@ -102,14 +102,14 @@ __device__ __forceinline__ int64_t wave_upper_bound(const int32_t *arr, int64_t 
 
 // ------------------------------------------------------------ LDS layout
 
-constexpr int kBloomWords = 16;  // 512-bit filter of a batch's run-head nodes
-struct FwdLds {           // forward: reductions of multi-edge runs, head filter
+constexpr int kHeadSlots = 128;  // hashed lane masks of a batch's run heads
+struct FwdLds {           // forward: reductions of multi-edge runs, head table
     u32 rmin[kWave];      // per run (by run-start lane): min hop candidate
     u64 rlo[kWave];       // per run: count sum, low 32-bit halves
     u64 rhi[kWave];       //                      high 32-bit halves
-    u32 bloom[kBloomWords];
+    u64 hmask[kHeadSlots];  // lanes of the run heads whose node hashes to the slot
 };
-__device__ __forceinline__ u32 bloom_bit(int32_t node) { return ((u32)node * 2654435761u) >> 23; }  // 9 bits
+__device__ __forceinline__ u32 head_slot(int32_t node) { return ((u32)node * 2654435761u) >> 25; }  // 7 bits
 struct RevLds {           // reverse: tail state by node, per batch
     u64 tb_key[kFwN];
     u64 tb_acc[kFwN];
@@ -482,69 +482,75 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             t = t2; u = u2; v = v2; tnext = tn2;
             continue;
         }
-        // ---- in-batch dependencies: mu (mh) = run-head lanes of earlier ticks
-        // whose head is my tail (my head).  A 512-bit filter of the run heads
-        // outside the last tick (LDS) flags the lanes that may have one; each
-        // flagged lane is then matched exactly with two ballots.
-        u64 mu = 0, mh = 0;
+        // ---- in-batch dependencies.  pred (hpred) = the latest run-head lane of
+        // an earlier tick whose head is my tail (my head), or -1.  Every run
+        // head publishes its node's state after its tick (committed or not),
+        // so a lane reads its node's state from that one lane.  The lanes come
+        // from a table of head-lane masks hashed by node (LDS), checked
+        // against the lane's node; on a hash collision the next lower lane of
+        // the slot is tried.
+        int pred = -1, hpred = -1;
         if (ntick > 1) {
             const int last0 = 63 - __clzll((long long)gm);  // first lane of the last tick
-            if (l < kBloomWords) L.bloom[l] = 0u;
+            L.hmask[2 * l] = 0ull;
+            L.hmask[2 * l + 1] = 0ull;
             __syncthreads();
-            if (rs && l < last0) {
-                const u32 b = bloom_bit(v);
-                atomicOr(&L.bloom[b >> 5], 1u << (b & 31));
-            }
+            if (rs && l < last0) atomicOr((unsigned long long *)&L.hmask[head_slot(v)], 1ull << l);
             __syncthreads();
-            bool pos = false;
-            if (in && tid > 0) {
-                const u32 bu = bloom_bit(u);
-                pos = (L.bloom[bu >> 5] >> (bu & 31)) & 1u;
-                if (rs) {
-                    const u32 bv = bloom_bit(v);
-                    pos = pos || ((L.bloom[bv >> 5] >> (bv & 31)) & 1u);
+            const int first_l = 63 - __clzll((long long)(gm & le));  // my tick's first lane
+            const u64 earlier = first_l > 0 ? ((1ull << first_l) - 1ull) : 0ull;
+            u64 m_u = (in && earlier) ? (L.hmask[head_slot(u)] & earlier) : 0ull;
+            u64 m_h = (rs && earlier) ? (L.hmask[head_slot(v)] & earlier) : 0ull;
+            while (ballot(m_u != 0 || m_h != 0)) {
+                const int ju = m_u ? 63 - __clzll((long long)m_u) : l;
+                const int jh = m_h ? 63 - __clzll((long long)m_h) : l;
+                const int32_t vju = __shfl(v, ju);
+                const int32_t vjh = __shfl(v, jh);
+                if (m_u) {
+                    if (vju == u) { pred = ju; m_u = 0; }
+                    else m_u &= ~(1ull << ju);
                 }
-            }
-            u64 cand = ballot(pos);
-            while (cand) {
-                const int i = __ffsll((long long)cand) - 1;
-                cand &= cand - 1ull;
-                const int first_i = 63 - __clzll((long long)(gm & ((2ull << i) - 1ull)));  // i's tick start
-                const u64 earlier = (1ull << first_i) - 1ull;
-                const int32_t ui = rl32(u, i), vi = rl32(v, i);
-                const u64 mU = ballot(rs && v == ui) & earlier;
-                const u64 mH = ((rsall >> i) & 1ull) ? (ballot(rs && v == vi) & earlier) : 0ull;
-                if (l == i) { mu = mU; mh = mH; }
+                if (m_h) {
+                    if (vjh == v) { hpred = jh; m_h = 0; }
+                    else m_h &= ~(1ull << jh);
+                }
             }
         }
         // tick of the latest lane I depend on (-1: none)
-        int dtk = -1;
-        if (mu | mh) {
-            const int jl = 63 - __clzll((long long)(mu | mh));
-            dtk = __popcll(gm & ((2ull << jl) - 1ull)) - 1;
-        }
-        // committed state of this batch's run heads (valid where cm is set)
-        u64 cm = 0;
-        u32 ch = 0;
-        u64 cS = 0;
+        const int dj = pred > hpred ? pred : hpred;
+        const int dtk = dj >= 0 ? __popcll(gm & ((2ull << dj) - 1ull)) - 1 : -1;
+        // state of my head node after my tick, published by run heads
+        u32 pub_h = kHInf;
+        u64 pub_S = 0;
         // ---- segments: maximal runs of ticks that read nothing committed inside them
         int ta = 0;
         while (ta < ntick && !done) {
             const u64 br = ballot(in && tid > ta && dtk >= ta);
             const int tb = br ? rl32(tid, __ffsll((long long)br) - 1) : ntick;
             const bool act = in && tid >= ta && tid < tb;
-            // tail state: the latest commit of this batch to my tail, else batch start
-            const u64 cu = act ? (mu & cm) : 0ull;
-            bool reached = act && (rt || cu != 0);
-            u32 h_u = hu;
+            // tail state: published by an earlier tick of this batch, else batch start
+            const bool fu = act && pred >= 0;
+            u32 h_u = rt ? hu : kHInf;
             u64 s_u = su;
-            if (ballot(cu != 0)) {
-                const int src = cu ? 63 - __clzll((long long)cu) : l;
-                const u32 fh = (u32)__shfl((int)ch, src);
-                const u64 fS = shfl64(cS, src);
-                if (cu) { h_u = fh; s_u = fS; }
+            // head state before my tick, likewise
+            const bool fh = act && rs && hpred >= 0;
+            u32 cur_h = hr ? hv : kHInf;
+            u64 cur_S = sv;
+            if (ballot(fu || fh)) {
+                const int src_u = fu ? pred : l, src_h = fh ? hpred : l;
+                const u32 ph_u = (u32)__shfl((int)pub_h, src_u);
+                const u64 pS_u = shfl64(pub_S, src_u);
+                const u32 ph_h = (u32)__shfl((int)pub_h, src_h);
+                const u64 pS_h = shfl64(pub_S, src_h);
+                if (fu) { h_u = ph_u; s_u = pS_u; }
+                if (fh) { cur_h = ph_h; cur_S = pS_h; }
             }
-            if (!ballot(reached)) { ta = tb; continue; }
+            const bool reached = act && h_u != kHInf;
+            if (!ballot(reached)) {
+                if (act && rs) { pub_h = cur_h; pub_S = cur_S; }
+                ta = tb;
+                continue;
+            }
             if (ballot(reached && h_u + 1 >= kHInf)) { o.flags |= REC_HOPS_LIMIT; return; }
             const u32 cand = reached ? h_u + 1 : kBig;
             const u64 am = ballot(act);
@@ -578,21 +584,11 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                     else { const u64 x = hi << 32; c = x + lo; if (c < x) c = kUMax; }
                 }
             }
-            // run heads decide; head state: the latest commit of this batch to
-            // my head, else batch start
-            const u64 cv = lead ? (mh & cm) : 0ull;
-            u32 h_v = hv;
-            u64 S_v = sv;
-            if (ballot(cv != 0)) {
-                const int src = cv ? 63 - __clzll((long long)cv) : l;
-                const u32 fh = (u32)__shfl((int)ch, src);
-                const u64 fS = shfl64(cS, src);
-                if (cv) { h_v = fh; S_v = fS; }
-            }
+            // run heads decide
             bool ok = false;
             u32 nh2 = 0;
             u64 nS = 0;
-            if (lead) ok = head_commit(opt, hr || cv != 0, h_v, S_v, d, c, v, P.z, zh, &nh2, &nS);
+            if (lead) ok = head_commit(opt, cur_h != kHInf, cur_h, cur_S, d, c, v, P.z, zh, &nh2, &nS);
             // fm/sfm/pfm stop at the tick where z is first reached: later ticks
             // of the segment are dropped
             int cut = tb;
@@ -606,10 +602,8 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                 S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh2 << 32);
                 S.F[2 * (int64_t)v + 1] = nS;
                 if (a.lds_bitmap) atomicOr(&bm[v >> 5], 1u << (v & 31));
-                ch = nh2;
-                cS = nS;
             }
-            cm |= ballot(ok);
+            if (act && rs) { pub_h = ok ? nh2 : cur_h; pub_S = ok ? nS : cur_S; }
             const u64 zm = ballot(ok && v == P.z);
             if (zm) {
                 const int zl = __ffsll((long long)zm) - 1;
