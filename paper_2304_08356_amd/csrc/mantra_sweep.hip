@@ -460,17 +460,26 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
         const int tid = __popcll(gm & le) - 1;
         const int ntick = __popcll(gm);
         const int rsl = 63 - __clzll((long long)((rsall & le) | 1ull));  // lane of my run's start
-        // ---- state at batch start: reached bitmap, then the per-node state
+        // ---- state at batch start.  With the LDS bitmap, a set bit is exactly
+        // a node whose state this pair wrote: the reached test needs no load,
+        // and the state loads of a live batch are in flight while its
+        // dependencies are worked out.  Without it, the state's pair tag
+        // decides.
         bool rt = false, hr = false;
         u32 hu = 0, hv = 0;
         u64 su = 0, sv = 0;
-        if (in && (a.lds_bitmap ? bm_test(bm, u) : true)) {
-            const u64 th = S.F[2 * (int64_t)u], x = S.F[2 * (int64_t)u + 1];
-            if ((u32)th == P.tag) { rt = true; hu = (u32)(th >> 32) & 0xFFFFu; su = x; }
-        }
-        if (rs && (a.lds_bitmap ? bm_test(bm, v) : true)) {
-            const u64 th = S.F[2 * (int64_t)v], x = S.F[2 * (int64_t)v + 1];
-            if ((u32)th == P.tag) { hr = true; hv = (u32)(th >> 32) & 0xFFFFu; sv = x; }
+        if (a.lds_bitmap) {
+            rt = in && bm_test(bm, u);
+            hr = rs && bm_test(bm, v);
+        } else {
+            if (in) {
+                const u64 th = S.F[2 * (int64_t)u], x = S.F[2 * (int64_t)u + 1];
+                if ((u32)th == P.tag) { rt = true; hu = (u32)(th >> 32) & 0xFFFFu; su = x; }
+            }
+            if (rs) {
+                const u64 th = S.F[2 * (int64_t)v], x = S.F[2 * (int64_t)v + 1];
+                if ((u32)th == P.tag) { hr = true; hv = (u32)(th >> 32) & 0xFFFFu; sv = x; }
+            }
         }
         // the next batch's edges, in flight while this one is processed
         int32_t t2, u2, v2, tn2;
@@ -481,6 +490,10 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             o.swept = b0 - P.lo;
             t = t2; u = u2; v = v2; tnext = tn2;
             continue;
+        }
+        if (a.lds_bitmap) {
+            if (rt) { const u64 th = S.F[2 * (int64_t)u]; su = S.F[2 * (int64_t)u + 1]; hu = (u32)(th >> 32) & 0xFFFFu; }
+            if (hr) { const u64 th = S.F[2 * (int64_t)v]; sv = S.F[2 * (int64_t)v + 1]; hv = (u32)(th >> 32) & 0xFFFFu; }
         }
         // ---- in-batch dependencies.  pred (hpred) = the latest run-head lane of
         // an earlier tick whose head is my tail (my head), or -1.  Every run
