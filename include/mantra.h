@@ -208,8 +208,8 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg);
 
 /* Autotuner: times the sweep on a calibration sample of sample_pairs pairs
  * (0: twice the automatic grid) drawn for optimality opt from the bootstrap
- * stream of seed, under candidate grid sizes (all, 3/4 and 1/2 of the
- * resident workgroups) and both pair orders, then keeps the fastest as the
+ * stream of seed, under candidate grid sizes (all, 7/8, 3/4, 5/8 and 1/2 of
+ * the resident workgroups) and both pair orders, then keeps the fastest as the
  * graph's launch configuration and writes it to *best (may be NULL).
  * Blocking; results of later calls do not depend on the choice. */
 int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint64_t seed,

@@ -861,7 +861,8 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
     rq.t0 = 0;
     rq.t1 = INT32_MAX;
     rq.seed = seed;
-    std::vector<int> slabs = {full, std::max(1, (3 * full) / 4), std::max(1, full / 2)};
+    std::vector<int> slabs = {full, std::max(1, (7 * full) / 8), std::max(1, (3 * full) / 4),
+                              std::max(1, (5 * full) / 8), std::max(1, full / 2)};
     slabs.erase(std::unique(slabs.begin(), slabs.end()), slabs.end());
     double best_ms = INFINITY;
     int best_slabs = full, best_order = MANTRA_ORDER_LONGEST_FIRST;

@@ -465,20 +465,24 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
         // and the state loads of a live batch are in flight while its
         // dependencies are worked out.  Without it, the state's pair tag
         // decides.
+        // (thu, su) / (thv, sv): the slab's {tag | hops << 32, count} words;
+        // the hops are taken out where they are first used, so that nothing
+        // waits for the loads before then
         bool rt = false, hr = false;
-        u32 hu = 0, hv = 0;
-        u64 su = 0, sv = 0;
+        u64 thu = 0, thv = 0, su = 0, sv = 0;
         if (a.lds_bitmap) {
             rt = in && bm_test(bm, u);
             hr = rs && bm_test(bm, v);
         } else {
             if (in) {
-                const u64 th = S.F[2 * (int64_t)u], x = S.F[2 * (int64_t)u + 1];
-                if ((u32)th == P.tag) { rt = true; hu = (u32)(th >> 32) & 0xFFFFu; su = x; }
+                thu = S.F[2 * (int64_t)u];
+                su = S.F[2 * (int64_t)u + 1];
+                rt = (u32)thu == P.tag;
             }
             if (rs) {
-                const u64 th = S.F[2 * (int64_t)v], x = S.F[2 * (int64_t)v + 1];
-                if ((u32)th == P.tag) { hr = true; hv = (u32)(th >> 32) & 0xFFFFu; sv = x; }
+                thv = S.F[2 * (int64_t)v];
+                sv = S.F[2 * (int64_t)v + 1];
+                hr = (u32)thv == P.tag;
             }
         }
         // the next batch's edges, in flight while this one is processed
@@ -492,8 +496,15 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             continue;
         }
         if (a.lds_bitmap) {
-            if (rt) { const u64 th = S.F[2 * (int64_t)u]; su = S.F[2 * (int64_t)u + 1]; hu = (u32)(th >> 32) & 0xFFFFu; }
-            if (hr) { const u64 th = S.F[2 * (int64_t)v]; sv = S.F[2 * (int64_t)v + 1]; hv = (u32)(th >> 32) & 0xFFFFu; }
+            // every lane loads (lanes with nothing to load read the origin's
+            // state, one line for all of them): no merge of a loaded value
+            // with a default, so no early wait for the loads
+            const int64_t iu = rt ? (int64_t)u : (int64_t)P.s;
+            const int64_t iv = hr ? (int64_t)v : (int64_t)P.s;
+            thu = S.F[2 * iu];
+            su = S.F[2 * iu + 1];
+            thv = S.F[2 * iv];
+            sv = S.F[2 * iv + 1];
         }
         // ---- in-batch dependencies.  pred (hpred) = the latest run-head lane of
         // an earlier tick whose head is my tail (my head), or -1.  Every run
@@ -543,11 +554,13 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             const bool act = in && tid >= ta && tid < tb;
             // tail state: published by an earlier tick of this batch, else batch start
             const bool fu = act && pred >= 0;
-            u32 h_u = rt ? hu : kHInf;
+            // (the tag test is implied by the bitmap; it keeps the whole loaded
+            // word live, so that no register of an in-flight load is reused)
+            u32 h_u = (rt && (u32)thu == P.tag) ? ((u32)(thu >> 32) & 0xFFFFu) : kHInf;
             u64 s_u = su;
             // head state before my tick, likewise
             const bool fh = act && rs && hpred >= 0;
-            u32 cur_h = hr ? hv : kHInf;
+            u32 cur_h = (hr && (u32)thv == P.tag) ? ((u32)(thv >> 32) & 0xFFFFu) : kHInf;
             u64 cur_S = sv;
             if (ballot(fu || fh)) {
                 const int src_u = fu ? pred : l, src_h = fh ? hpred : l;
