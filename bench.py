@@ -201,7 +201,7 @@ def main():
     G = workload(WORKLOAD)
     gg = pk.Graph.of(G)
     # launch configuration picked by the autotuner on a calibration sample
-    tuned = gg.autotune(OPT, seed=args.seed + 7)
+    tuned = gg.autotune(OPT, sample_pairs=R_PER_STEP, seed=args.seed + 7)
     for i in range(args.warmup):
         gg.run(OPT, fixed_r=R_PER_STEP, seed=args.seed + 1000 + i, c=C, edges=True)
     torch.cuda.synchronize()
