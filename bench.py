@@ -1,6 +1,6 @@
 """Benchmark of the temporal-betweenness hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--slabs N]
                     [--no-forms] [--no-serve] [--no-cpu-baseline]
     python bench.py --calibrate-copy     (plain copy kernel for the traffic counters)
 
@@ -50,9 +50,9 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip
 # counter bytes that the same counters give for a plain copy of known size),
 # valid for the kernel source with this SHA-256 only.
 TRAFFIC = {
-    "sweep_sha256": "b766b3db4ab30aa7b0a03123d47bc419e07c0e6e2dc1ac25a6db1e9de71917bc",
-    "fetch_bytes_per_launch": 5.229e11,   # 2.55331e8 KiB x 1.99994
-    "write_bytes_per_launch": 7.674e10,   # 7.49416e7 KiB x 1.00000
+    "sweep_sha256": "e2a17b826b86e7114af1944797fa011711d8643aca6557a704400f07e8958e4e",
+    "fetch_bytes_per_launch": 4.915e11,   # 2.39982e8 KiB x 1.99994
+    "write_bytes_per_launch": 7.843e10,   # 7.65943e7 KiB x 1.00000
 }
 
 
@@ -184,6 +184,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--slabs", type=int, default=0,
+                    help="fixed number of persistent workgroups instead of the autotuner's pick "
+                         "(profiling runs: every sweep launch of the run is then alike)")
     ap.add_argument("--seed", type=int, default=2002)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -201,7 +204,11 @@ def main():
     G = workload(WORKLOAD)
     gg = pk.Graph.of(G)
     # launch configuration picked by the autotuner on a calibration sample
-    tuned = gg.autotune(OPT, sample_pairs=R_PER_STEP, seed=args.seed + 7)
+    if args.slabs > 0:
+        gg.set_launch(n_slabs=args.slabs)
+        tuned = gg.get_launch()
+    else:
+        tuned = gg.autotune(OPT, sample_pairs=R_PER_STEP, seed=args.seed + 7)
     for i in range(args.warmup):
         gg.run(OPT, fixed_r=R_PER_STEP, seed=args.seed + 1000 + i, c=C, edges=True)
     torch.cuda.synchronize()
