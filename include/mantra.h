@@ -197,6 +197,9 @@ typedef struct {
                              sweep and reduction) */
     int32_t per_pair_launch; /* 1: the unbatched form, one single-workgroup
                                 launch per pair (a baseline for measurement) */
+    int32_t hub_nodes;    /* forward state of the hub_nodes highest-degree nodes
+                             of each pair kept in LDS (graphs whose reached
+                             bitmap fits LDS; 0: none) */
 } mantra_launch_config;
 
 #define MANTRA_ORDER_LONGEST_FIRST 0 /* decreasing estimated window (default) */
@@ -209,7 +212,8 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg);
 /* Autotuner: times the sweep on a calibration sample of sample_pairs pairs
  * (0: twice the automatic grid) drawn for optimality opt from the bootstrap
  * stream of seed, under candidate grid sizes (all, 7/8, 3/4, 5/8 and 1/2 of
- * the resident workgroups) and both pair orders, then keeps the fastest as the
+ * the resident workgroups) and both pair orders, then with 256 hub nodes in
+ * LDS at the best of those, then keeps the fastest as the
  * graph's launch configuration and writes it to *best (may be NULL).
  * Blocking; results of later calls do not depend on the choice. */
 int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint64_t seed,

@@ -87,12 +87,13 @@ class Graph:
         return {"n": n.value, "m_unique": mu.value, "n_duplicates": nd.value, "t_min": t0.value,
                 "t_max": t1.value, "n_graphs": G.value}
 
-    def set_launch(self, n_slabs=0, arc_cap=0, order="longest", graph_rounds=False, per_pair_launch=False):
+    def set_launch(self, n_slabs=0, arc_cap=0, order="longest", graph_rounds=False, per_pair_launch=False,
+                   hub_nodes=0):
         """Launch configuration (scheduling only; results do not change)."""
         cfg = _lib.LaunchConfig(n_slabs=int(n_slabs), arc_cap=int(arc_cap),
                                 order=_lib.ORDER[order] if isinstance(order, str) else int(order),
                                 graph_rounds=1 if graph_rounds else 0,
-                                per_pair_launch=1 if per_pair_launch else 0)
+                                per_pair_launch=1 if per_pair_launch else 0, hub_nodes=int(hub_nodes))
         _lib.check(_lib._lib.mantra_set_launch(self._h, ctypes.byref(cfg)))
 
     def autotune(self, opt, sample_pairs=0, seed=0):

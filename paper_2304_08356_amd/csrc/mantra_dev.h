@@ -82,6 +82,7 @@ struct LaunchArgs {
     const DevReq *reqs;
     int32_t nreq;
     int32_t lds_bitmap;      // 1: reached-bitmap of nmax bits in LDS
+    int32_t hub_nodes;       // with the bitmap: forward state of nodes < hub_nodes lives in LDS
     int64_t npairs;              // launch slots (grid sizes); the pairs are slots qbase..np-1
     const int64_t *npairs_dev;   // np read from device memory (graph replays), or null: np = npairs
     int64_t qbase;               // first slot this launch takes

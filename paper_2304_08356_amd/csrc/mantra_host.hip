@@ -244,10 +244,20 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
 // tails; beyond 8 KB it costs more occupancy than it saves, and the reached
 // test reads the gathered per-node state (its pair tag) instead.
 static int lds_bitmap_ok(int64_t nmax) { return ((nmax + 31) / 32) * 4 <= 8 * 1024; }
-static size_t lds_bytes(int64_t nmax) {
+// forward state of the top hub nodes in LDS (bitmap graphs only)
+static int hub_nodes(const mantra_graph *g) {
+    if (!lds_bitmap_ok(g->nmax)) return 0;
+    return (int)std::min<int64_t>(g->hub_nodes, g->nmax);
+}
+static size_t lds_bytes(const mantra_graph *g) {
+    const int64_t nmax = g->nmax;
     size_t b = mantra_tab_lds_bytes();
-    if (lds_bitmap_ok(nmax)) b += (size_t)((nmax + 31) / 32) * 4;
-    else b += (size_t)kAliveN * 4;  // alive-set hash of the reverse sweep
+    if (lds_bitmap_ok(nmax)) {
+        b += ((size_t)((nmax + 31) / 32) * 4 + 7) & ~(size_t)7;
+        b += (size_t)hub_nodes(g) * 12;
+    } else {
+        b += (size_t)kAliveN * 4;  // alive-set hash of the reverse sweep
+    }
     return b;
 }
 
@@ -285,7 +295,7 @@ int auto_slabs(const mantra_graph *g) {
     hipGetDeviceProperties(&pr, g->device);
     int cus = pr.multiProcessorCount > 0 ? pr.multiProcessorCount : 256;
     // resident workgroups per CU (registers and LDS), as the runtime reports
-    size_t lb = lds_bytes(g->nmax);
+    size_t lb = lds_bytes(g);
     int per_cu = mantra_sweep_occupancy(lb);
     if (per_cu <= 0) {
         int by_lds = (int)((160 * 1024) / (lb ? lb : 1));
@@ -410,6 +420,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     a.reqs = g->dreqs;
     a.nreq = (int32_t)sp.reqs.size();
     a.lds_bitmap = lds_bitmap_ok(g->nmax);
+    a.hub_nodes = hub_nodes(g);
     a.npairs = slots;
     a.npairs_dev = nullptr;
     a.qbase = 0;
@@ -420,7 +431,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     a.work = g->dwork;
     a.stats = g->dstats;
     a.retry = g->dretry;
-    const size_t lb = lds_bytes(g->nmax);
+    const size_t lb = lds_bytes(g);
     float ms = 0;
     if (g->per_pair) {
         // the unbatched form: one single-workgroup launch per pair
@@ -804,6 +815,8 @@ int req_finish(mantra_graph *g, ReqRun &q, mantra_result *out) {
         rc = fail(MANTRA_E_OVERFLOW, "%lld sampled pairs saturated", (long long)q.R.n_overflow);
     if (rc == MANTRA_E_OVERFLOW && q.rq.node_bc)
         for (int64_t v = 0; v < g->n_total; ++v) q.rq.node_bc[v] = NAN;
+    if (rc == MANTRA_E_OVERFLOW && q.edges)
+        for (int64_t i = 0; i < g->m_in; ++i) q.rq.edge_bc[i] = NAN;
     q.R.latency_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q.t_start).count();
     q.R.status = rc;
     if (rc < 0 && q.rc == MANTRA_OK) q.err = g_err;
@@ -849,10 +862,11 @@ static int run_request(mantra_graph *g, const mantra_request &rq, mantra_result 
 // order pairs are handed out in.  The arc capacity follows the slab count
 // (the rest of the pool budget).  Results never depend on the choice.
 static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t seed, mantra_launch_config *best) {
-    const int saved_slabs = g->user_slabs, saved_order = g->order_mode;
+    const int saved_slabs = g->user_slabs, saved_order = g->order_mode, saved_hub = g->hub_nodes;
     const int64_t saved_cap = g->user_cap;
     g->user_slabs = 0;
     g->user_cap = 0;
+    g->hub_nodes = 0;
     const int full = auto_slabs(g);
     if (sample <= 0) sample = std::max<int64_t>(2 * (int64_t)full, 256);
     mantra_request rq;
@@ -865,40 +879,57 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
                               std::max(1, (5 * full) / 8), std::max(1, full / 2)};
     slabs.erase(std::unique(slabs.begin(), slabs.end()), slabs.end());
     double best_ms = INFINITY;
-    int best_slabs = full, best_order = MANTRA_ORDER_LONGEST_FIRST;
+    int best_slabs = full, best_order = MANTRA_ORDER_LONGEST_FIRST, best_hub = 0;
     int rc = MANTRA_OK;
+    auto time_one = [&](double *ms) {
+        LaunchSpec sp;
+        DevReq d = make_req(rq, STREAM_BOOT, 0, 0, sample, nullptr, 0);
+        d.graph = g->G == 1 ? 0 : -1;
+        d.per_graph = (sample + g->G - 1) / g->G;
+        sp.reqs.push_back(d);
+        sp.npairs = g->G == 1 ? sample : d.per_graph * g->G;
+        SweepOut o;
+        const int r = run_sweep(g, sp, o);
+        *ms = o.ms;
+        return r;
+    };
     for (int order : {MANTRA_ORDER_LONGEST_FIRST, MANTRA_ORDER_DRAWN}) {
         for (int ns : slabs) {
             g->user_slabs = ns;
             g->order_mode = order;
-            LaunchSpec sp;
-            DevReq d = make_req(rq, STREAM_BOOT, 0, 0, sample, nullptr, 0);
-            d.graph = g->G == 1 ? 0 : -1;
-            d.per_graph = (sample + g->G - 1) / g->G;
-            sp.reqs.push_back(d);
-            sp.npairs = g->G == 1 ? sample : d.per_graph * g->G;
-            SweepOut o;
-            rc = run_sweep(g, sp, o);
-            if (rc) break;
-            if (o.ms < best_ms) { best_ms = o.ms; best_slabs = ns; best_order = order; }
+            double ms = 0;
+            if ((rc = time_one(&ms))) break;
+            if (ms < best_ms) { best_ms = ms; best_slabs = ns; best_order = order; }
         }
         if (rc) break;
+    }
+    // hub nodes' state in LDS at the best grid (it costs LDS per workgroup)
+    if (!rc && lds_bitmap_ok(g->nmax)) {
+        g->user_slabs = best_slabs;
+        g->order_mode = best_order;
+        g->hub_nodes = 256;
+        double ms = 0;
+        rc = time_one(&ms);
+        if (!rc && ms < best_ms) { best_ms = ms; best_hub = 256; }
     }
     if (rc) {
         g->user_slabs = saved_slabs;
         g->user_cap = saved_cap;
         g->order_mode = saved_order;
+        g->hub_nodes = saved_hub;
         return rc;
     }
     g->user_slabs = best_slabs == full ? 0 : best_slabs;
     g->user_cap = 0;
     g->order_mode = best_order;
+    g->hub_nodes = best_hub;
     if (best) {
         best->n_slabs = best_slabs;
         best->arc_cap = auto_cap(g, best_slabs);
         best->order = best_order;
         best->graph_rounds = g->graph_rounds;
         best->per_pair_launch = g->per_pair;
+        best->hub_nodes = hub_nodes(g);
     }
     return MANTRA_OK;
 }
@@ -963,6 +994,7 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg) {
     if (cfg->n_slabs < 0 || cfg->arc_cap < 0) return fail(MANTRA_E_INVALID, "negative launch setting");
     if (cfg->order != MANTRA_ORDER_LONGEST_FIRST && cfg->order != MANTRA_ORDER_DRAWN)
         return fail(MANTRA_E_INVALID, "unknown pair order %d", cfg->order);
+    if (cfg->hub_nodes < 0 || cfg->hub_nodes > 4096) return fail(MANTRA_E_INVALID, "hub_nodes outside 0..4096");
     std::lock_guard<std::mutex> lk(g->mu);
     if (g->user_slabs != cfg->n_slabs || g->user_cap != cfg->arc_cap) g->pool.release();
     g->user_slabs = cfg->n_slabs;
@@ -970,6 +1002,7 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg) {
     g->order_mode = cfg->order;
     g->graph_rounds = cfg->graph_rounds ? 1 : 0;
     g->per_pair = cfg->per_pair_launch ? 1 : 0;
+    g->hub_nodes = cfg->hub_nodes;
     return MANTRA_OK;
 }
 
@@ -990,6 +1023,7 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {
     cfg->order = g->order_mode;
     cfg->graph_rounds = g->graph_rounds;
     cfg->per_pair_launch = g->per_pair;
+    cfg->hub_nodes = hub_nodes(g);
     return MANTRA_OK;
 }
 

@@ -105,6 +105,7 @@ struct mantra_graph {
     int user_slabs = 0;
     int64_t user_cap = 0;
     int order_mode = MANTRA_ORDER_LONGEST_FIRST;
+    int hub_nodes = 0;              // forward state of nodes below this id in LDS
     int graph_rounds = 0;
     int per_pair = 0;               // unbatched form: one launch per pair
     int64_t *dnp = nullptr;         // pair count of a graph replay

@@ -190,6 +190,14 @@ struct Slab {
     int32_t *touched;
 };
 
+// forward state of the highest-degree nodes (internal ids below K) in LDS:
+// hops and count, valid where the reached bitmap is set (no pair tag)
+struct Hub {
+    u32 *h;
+    u64 *s;
+    int32_t K;
+};
+
 struct FwdOut {
     bool reached;
     u32 zh;
@@ -246,7 +254,7 @@ __device__ __forceinline__ bool head_commit(int opt, bool rv, u32 hv, u64 Sv, u3
 // slab's global per-node scratch (AG), four passes, commits after all reads.
 // Such a tick always forms a batch of its own.
 
-__device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm,
+__device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
                               int64_t g0, int64_t g1, int32_t t, u32 &agstamp, FwdOut &o,
                               u32 &zh, u64 &zS, bool &zhit) {
     const int l = lane_id();
@@ -263,7 +271,9 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
         u64 Su = 0;
         if (act) {
             bool maybe = a.lds_bitmap ? bm_test(bm, u) : true;
-            if (maybe) {
+            if (maybe && u < H.K) {
+                rt = true; hu = H.h[u]; Su = H.s[u];
+            } else if (maybe) {
                 u64 th = S.F[2 * (int64_t)u], sv = S.F[2 * (int64_t)u + 1];
                 if ((u32)th == P.tag) { rt = true; hu = (u32)(th >> 32) & 0xFFFFu; Su = sv; }
             }
@@ -319,14 +329,19 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
                 u32 hv = 0;
                 u64 Sv = 0;
                 bool maybe = a.lds_bitmap ? bm_test(bm, v) : true;
-                if (maybe) {
+                if (maybe && v < H.K) {
+                    rv = true; hv = H.h[v]; Sv = H.s[v];
+                } else if (maybe) {
                     u64 th = S.F[2 * (int64_t)v], sv = S.F[2 * (int64_t)v + 1];
                     if ((u32)th == P.tag) { rv = true; hv = (u32)(th >> 32) & 0xFFFFu; Sv = sv; }
                 }
                 if (head_commit(P.opt, rv, hv, Sv, d, c, v, P.z, zh, &nh, &nS)) {
                     ok = agstamp;
-                    S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh << 32);
-                    S.F[2 * (int64_t)v + 1] = nS;
+                    if (v < H.K) { H.h[v] = nh; H.s[v] = nS; }
+                    else {
+                        S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh << 32);
+                        S.F[2 * (int64_t)v + 1] = nS;
+                    }
                     if (a.lds_bitmap) atomicOr(&bm[v >> 5], 1u << (v & 31));
                     zl = (v == P.z);
                 }
@@ -402,7 +417,7 @@ __device__ __forceinline__ void load_batch(const LaunchArgs &a, const Pair &P, i
 // from the slab) or the commit of an earlier tick of the same batch, passed
 // from the committing lane's registers.  Maximal runs of ticks that read no
 // commit made inside the run ("segments") are processed together.
-__device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, FwdLds &L,
+__device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H, FwdLds &L,
                         u32 &agstamp, FwdOut &o) {
     static_assert(kE == 1, "the forward sweep is written for one edge per lane");
     const int l = lane_id();
@@ -437,7 +452,7 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                         if (m) { g1 = i + (__ffsll((long long)m) - 1); break; }
                     }
                     __syncthreads();
-                    fwd_long_tick(a, P, S, bm, b0, g1, tlast, agstamp, o, zh, zS, zhit);
+                    fwd_long_tick(a, P, S, bm, H, b0, g1, tlast, agstamp, o, zh, zS, zhit);
                     o.swept = g1 - P.lo;
                     b0 = g1;
                     if (o.flags & REC_HOPS_LIMIT) return;
@@ -470,6 +485,8 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
         // waits for the loads before then
         bool rt = false, hr = false;
         u64 thu = 0, thv = 0, su = 0, sv = 0;
+        u32 lhu = 0, lhv = 0;
+        u64 lsu = 0, lsv = 0;
         if (a.lds_bitmap) {
             rt = in && bm_test(bm, u);
             hr = rs && bm_test(bm, v);
@@ -499,12 +516,19 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             // every lane loads (lanes with nothing to load read the origin's
             // state, one line for all of them): no merge of a loaded value
             // with a default, so no early wait for the loads
-            const int64_t iu = rt ? (int64_t)u : (int64_t)P.s;
-            const int64_t iv = hr ? (int64_t)v : (int64_t)P.s;
+            // hub nodes' state is in LDS (loaded for every lane, index 0 for
+            // the others)
+            const int64_t iu = (rt && u >= H.K) ? (int64_t)u : (int64_t)P.s;
+            const int64_t iv = (hr && v >= H.K) ? (int64_t)v : (int64_t)P.s;
             thu = S.F[2 * iu];
             su = S.F[2 * iu + 1];
             thv = S.F[2 * iv];
             sv = S.F[2 * iv + 1];
+            if (H.K > 0) {
+                const int ju = u < H.K ? u : 0, jv = v < H.K ? v : 0;
+                lhu = H.h[ju]; lsu = H.s[ju];
+                lhv = H.h[jv]; lsv = H.s[jv];
+            }
         }
         // ---- in-batch dependencies.  pred (hpred) = the latest run-head lane of
         // an earlier tick whose head is my tail (my head), or -1.  Every run
@@ -556,12 +580,14 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             const bool fu = act && pred >= 0;
             // (the tag test is implied by the bitmap; it keeps the whole loaded
             // word live, so that no register of an in-flight load is reused)
-            u32 h_u = (rt && (u32)thu == P.tag) ? ((u32)(thu >> 32) & 0xFFFFu) : kHInf;
-            u64 s_u = su;
+            const bool hub_u = u < H.K;
+            u32 h_u = !rt ? kHInf : hub_u ? lhu : ((u32)thu == P.tag) ? ((u32)(thu >> 32) & 0xFFFFu) : kHInf;
+            u64 s_u = hub_u ? lsu : su;
             // head state before my tick, likewise
             const bool fh = act && rs && hpred >= 0;
-            u32 cur_h = (hr && (u32)thv == P.tag) ? ((u32)(thv >> 32) & 0xFFFFu) : kHInf;
-            u64 cur_S = sv;
+            const bool hub_v = v < H.K;
+            u32 cur_h = !hr ? kHInf : hub_v ? lhv : ((u32)thv == P.tag) ? ((u32)(thv >> 32) & 0xFFFFu) : kHInf;
+            u64 cur_S = hub_v ? lsv : sv;
             if (ballot(fu || fh)) {
                 const int src_u = fu ? pred : l, src_h = fh ? hpred : l;
                 const u32 ph_u = (u32)__shfl((int)pub_h, src_u);
@@ -625,8 +651,11 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             const bool keep = tid < cut;
             ok = ok && keep;
             if (ok) {
-                S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh2 << 32);
-                S.F[2 * (int64_t)v + 1] = nS;
+                if (v < H.K) { H.h[v] = nh2; H.s[v] = nS; }
+                else {
+                    S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh2 << 32);
+                    S.F[2 * (int64_t)v + 1] = nS;
+                }
                 if (a.lds_bitmap) atomicOr(&bm[v >> 5], 1u << (v & 31));
             }
             if (act && rs) { pub_h = ok ? nh2 : cur_h; pub_S = ok ? nS : cur_S; }
@@ -1051,6 +1080,10 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
     TabLds &tab = *reinterpret_cast<TabLds *>(lds_raw);
     u32 *bm = reinterpret_cast<u32 *>(lds_raw + sizeof(TabLds));
     const int64_t bmw = a.lds_bitmap ? (a.sl.nmax + 31) / 32 : 0;
+    Hub H;
+    H.K = a.lds_bitmap ? a.hub_nodes : 0;
+    H.s = reinterpret_cast<u64 *>(lds_raw + sizeof(TabLds) + ((bmw * 4 + 7) & ~7ll));
+    H.h = reinterpret_cast<u32 *>(H.s + H.K);
     for (int i = l; i < kFwN; i += kWave) { tab.r.tb_key[i] = 0; }
     u32 serial = S.hdr[0];
     u32 agstamp = S.hdr[1];
@@ -1086,12 +1119,15 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
             for (int64_t w = l; w < bmw; w += kWave) bm[w] = 0;
             __syncthreads();
             if (l == 0) {
-                S.F[2 * (int64_t)P.s] = (u64)P.tag;  // h = 0
-                S.F[2 * (int64_t)P.s + 1] = 1ull;
+                if (P.s < H.K) { H.h[P.s] = 0u; H.s[P.s] = 1ull; }
+                else {
+                    S.F[2 * (int64_t)P.s] = (u64)P.tag;  // h = 0
+                    S.F[2 * (int64_t)P.s + 1] = 1ull;
+                }
                 if (a.lds_bitmap) bm[P.s >> 5] |= 1u << (P.s & 31);
             }
             __syncthreads();
-            forward(a, P, S, bm, tab.f, agstamp, fo);
+            forward(a, P, S, bm, H, tab.f, agstamp, fo);
             __syncthreads();
             // the reverse table reuses the forward's LDS: empty it
             for (int i = l; i < kFwN; i += kWave) { tab.r.tb_key[i] = 0; }
@@ -1114,7 +1150,15 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
             if ((u32)th == P.tag && (!P.level || ((u32)(th >> 32) & 0xFFFFu) == 0u)) bo = ld_agent(&S.R[2 * (int64_t)P.s + 1]);
             if (bo != sigma) flags |= REC_SELFCHECK;
         }
-        if (X.ovf) flags |= REC_OVERFLOW;
+        if (X.ovf) {
+            // an fm visit count wrapped during the reverse sweep: the pair is
+            // reported as saturated, so the f(e) it already wrote are cleared
+            // (its sums are void: the request fails with MANTRA_E_OVERFLOW)
+            flags |= REC_OVERFLOW;
+            if (a.edge_f)
+                for (int64_t i = l; i < fo.arcs; i += kWave)
+                    a.edge_f[P.qout * a.g.m + (int64_t)(u32)S.arcx[3 * i]] = 0.0;
+        }
         // finalize: f(v) = N(v) / sigma into the sums; reset N
         bool accum = do_rev && !(flags & REC_OVERFLOW);
         const DevReq *R = P.req;

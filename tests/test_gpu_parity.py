@@ -257,7 +257,7 @@ def test_launch_configs_same_results(lib):
     S, Z = oracle.draw_pairs(92, oracle.STREAM_PAIR, G.n, 0, 600)
     ref = None
     configs = [dict(order="longest"), dict(order="drawn"), dict(n_slabs=7, order="longest"),
-               dict(n_slabs=64, arc_cap=2048, order="drawn")]
+               dict(n_slabs=64, arc_cap=2048, order="drawn"), dict(hub_nodes=256), dict(n_slabs=9, hub_nodes=1000)]
     try:
         for cfg in configs:
             gg.set_launch(**cfg)
@@ -343,3 +343,29 @@ def test_per_pair_launches_match(tiny_workload):
     assert np.array_equal(rec0, rec1) and np.array_equal(nf0, nf1)
     ok, worst = rel_close(nb0, nb1, rel=1e-12, abs_floor=1e-300)
     assert ok, worst
+
+
+@pytest.mark.parametrize("opt", OPTS)
+def test_hub_state_in_lds(lib, opt):
+    """Forward state of the highest-degree nodes kept in LDS: bit-exact on
+    random tiny graphs (all pairs), on ticks longer than a batch and on a
+    head with 600 in-edges at one time (hub heads and tails on every path)."""
+    from synthgen.graphs import TemporalGraph
+    for seed in range(6):
+        rng = np.random.default_rng(900 + seed)
+        n, src, dst, t = tiny_graph(rng)
+        gg, og = both(lib, TemporalGraph(n, src, dst, t))
+        gg.set_launch(hub_nodes=max(1, n // 3))
+        S, Z = all_pairs(n)
+        compare_pairs(gg, og, opt, S, Z, ctx="hub-tiny%d" % seed)
+    G = uniform_graph(80, 4000, 6, seed=77)
+    gg, og = both(lib, G)
+    gg.set_launch(hub_nodes=40)
+    S, Z = oracle.draw_pairs(5, 0, G.n, 0, 200)
+    compare_pairs(gg, og, opt, S, Z, ctx="hub-bigtick")
+    H = chung_lu_graph(3000, 60_000, 2.3, 4000, seed=91, times="pareto")
+    hg, ho = both(lib, H)
+    hg.set_launch(hub_nodes=256)
+    S, Z = oracle.draw_pairs(94, oracle.STREAM_PAIR, H.n, 0, 60)
+    compare_pairs(hg, ho, opt, S, Z, ctx="hub-cl")
+    assert hg.get_launch()["hub_nodes"] == 256
