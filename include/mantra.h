@@ -164,6 +164,41 @@ int mantra_estimate(mantra_graph *g, mantra_opt opt, double eps, double delta, u
  * edge_bc[m] (input edge order).  Same errors as mantra_estimate. */
 int mantra_run(mantra_graph *g, const mantra_request *req, mantra_result *out);
 
+/* Result of mantra_distances (appendix on temporal distance metrics,
+ * Algorithm 2).  d(u, v) is the number of temporal edges of the
+ * (*)-optimal walks from u to v (for sfm: the fewest among the walks
+ * arriving first; for fm: the fewest among all walks arriving first; for pfm:
+ * that of the prefix-foremost walks).  With R[h] = (n / r) * (sampled pairs
+ * (u, v), v != u, with d(u, v) <= h), the paper's R array: */
+typedef struct {
+    int64_t sources;        /* r */
+    int64_t reached_pairs;  /* sampled (source, node) pairs joined by a walk */
+    int32_t d_lb;           /* D_LB: the largest distance seen (a lower bound on
+                               the (*)-temporal diameter D; VD = D + 1) */
+    int32_t d_tau;          /* D_tau: least h with R[h] / R[D_LB] >= tau; -1 if
+                               no sampled pair is reachable */
+    double zeta;            /* connectivity rate R[D_LB] / (n (n - 1)) */
+    double psi;             /* average distance over reachable pairs,
+                               sum_h h (R[h] - R[h-1]) / R[D_LB]; 0 if none */
+    double rho;             /* average internal nodes over all n (n - 1)
+                               ordered pairs, sum_h (h - 1)(R[h] - R[h-1])
+                               / (n (n - 1)) (unreachable pairs count 0) */
+    int64_t window_edges;   /* temporal edges swept, summed over sources */
+    double gpu_ms;          /* device time of the sweep */
+} mantra_distance_result;
+
+/* Algorithm 2: r sources drawn uniformly (with replacement) from the seed's
+ * source stream, each swept forward from its first departure to the end of
+ * [t0, t1] (t1 < t0: the whole span) without a target; the distances of every
+ * node it reaches form the per-hop counts, from which the quantities above
+ * follow.  hist (host, may be NULL when hist_len = 0) receives the raw counts:
+ * hist[h] = sampled pairs at distance exactly h for h < hist_len - 1, the
+ * last entry every larger distance.  tau in [0, 1].  Single graphs only
+ * (packed: MANTRA_E_INVALID), n >= 2, 1 <= r <= 2^31 - 1.  MANTRA_E_LIMIT if
+ * a distance exceeds 65534.  Blocking. */
+int mantra_distances(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r, uint64_t seed,
+                     double tau, uint64_t *hist, int32_t hist_len, mantra_distance_result *out);
+
 /* Serving (not in the paper: a request loop around Algorithm 1).  Non-blocking
  * submission to the graph's scheduler thread, which batches the phases of all
  * admitted requests into shared sweep launches.  Admission is FIFO by the

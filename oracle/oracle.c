@@ -635,3 +635,53 @@ int64_t orc_accumulate(const orc_graph *g, int32_t opt, int32_t t0, int32_t t1, 
     free(outs);
     return noverflow;
 }
+
+/* ------------------------------------------------------------------------ */
+/* distances from single sources (the temporal BFS of Algorithm 2)           */
+
+/*
+ * For each source S[q] (q < k) and every node v: hops[q*n + v] = the hop
+ * count of the record of the pair (S[q], v) -- the fewest hops over all walks
+ * for sh, over the walks arriving first for sfm and fm, the hops of the
+ * prefix-foremost walks for pfm -- or -1 where v is not reachable in the
+ * window and for v = S[q].  The window starts at t0 for every source (the
+ * pair record's window: a walk of s starts at its first departure >= t0).
+ * Sources are evaluated in parallel.  Returns 0, or -1 on a bad argument.
+ */
+int orc_source_hops(const orc_graph *g, int32_t opt, int32_t t0, int32_t t1, int32_t mode, int64_t k,
+                    const int32_t *S, int32_t *hops, int32_t nthreads) {
+    int32_t n = g->n;
+    if (opt < 0 || opt > 3) return -1;
+    for (int64_t q = 0; q < k; ++q)
+        if (S[q] < 0 || S[q] >= n) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < k; ++q) {
+        int32_t s = S[q];
+        int32_t *out = hops + q * (int64_t)n;
+        pws w;
+        memset(&w, 0, sizeof(w));
+        pws_build(g, t0, t1, &w);
+        if (mode == 0) forward_explicit(&w, s); else forward_prefix(&w, n, s, opt);
+        earliest(&w, n);
+        forward_pfm(&w, s);
+        for (int32_t v = 0; v < n; ++v) {
+            out[v] = -1;
+            if (v == s || w.first_app[v] < 0) continue;
+            if (opt == OPT_SH) {
+                int32_t d = DINF;
+                for (int64_t a = w.app_off[v]; a < w.app_off[v + 1]; ++a)
+                    if (w.reach[a] && w.dist[a] < d) d = w.dist[a];
+                out[v] = d;
+            } else if (opt == OPT_PFM) {
+                out[v] = w.hopP[w.first_app[v]];
+            } else {
+                out[v] = w.dist[w.first_app[v]];
+            }
+        }
+        pws_free(&w);
+    }
+    return 0;
+}

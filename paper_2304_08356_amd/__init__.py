@@ -159,6 +159,16 @@ class Graph:
                                              _p(node_bc), ctypes.byref(res)))
         return node_bc, res.to_dict()
 
+    def distances(self, opt, r, seed=0, tau=0.9, t0=0, t1=T_MAX, hist_len=64):
+        """Algorithm 2 from r sampled sources: returns (hist[hist_len] of
+        sampled pairs per distance, the last bin taking larger ones; result
+        dict with d_lb, d_tau, zeta, psi, rho)."""
+        hist = np.zeros(max(int(hist_len), 0), dtype=np.uint64)
+        res = _lib.DistanceResult()
+        _lib.check(_lib._lib.mantra_distances(self._h, _opt(opt), int(t0), int(t1), int(r), int(seed), float(tau),
+                                              _p(hist) if hist.size else None, int(hist.size), ctypes.byref(res)))
+        return hist, res.to_dict()
+
     # serving
     def serve_config(self, mem_budget_bytes=0, max_active=0):
         _lib.check(_lib._lib.mantra_serve_config(self._h, int(mem_budget_bytes), int(max_active)))

@@ -61,6 +61,14 @@ class Result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class DistanceResult(ctypes.Structure):
+    _fields_ = [("sources", I64), ("reached_pairs", I64), ("d_lb", I32), ("d_tau", I32), ("zeta", F64),
+                ("psi", F64), ("rho", F64), ("window_edges", I64), ("gpu_ms", F64)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # every symbol include/mantra.h declares, with (restype, argtypes)
 SIGNATURES = {
     "mantra_graph_create": (I32, [P, P, P, I64, I32, U32, P]),
@@ -70,6 +78,7 @@ SIGNATURES = {
     "mantra_count_pairs": (I32, [P, I32, I32, I32, I64, P, P, P, P, P, P]),
     "mantra_estimate": (I32, [P, I32, F64, F64, U64, P, P]),
     "mantra_run": (I32, [P, P, P]),
+    "mantra_distances": (I32, [P, I32, I32, I32, I64, U64, F64, P, I32, P]),
     "mantra_submit": (I32, [P, P, P]),
     "mantra_poll": (I32, [U64, P, I32]),
     "mantra_serve_config": (I32, [P, U64, I32]),

@@ -366,14 +366,18 @@ void RoundGraph::release() {
 
 // the kernels of one launch: clear the counters, order the slots (longest
 // estimated window first), sweep; with rg, also the request's reduction
-static int issue_kernels(mantra_graph *g, LaunchArgs &a, int ns, size_t lb, const RoundGraph *rg) {
+static hipError_t launch_sweep(const LaunchArgs &a, bool sources, int ns, size_t lb, hipStream_t st) {
+    return sources ? mantra_launch_sweep_sources(&a, ns, lb, st) : mantra_launch_sweep(&a, ns, lb, st);
+}
+
+static int issue_kernels(mantra_graph *g, LaunchArgs &a, int ns, size_t lb, const RoundGraph *rg, bool sources) {
     HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, g->dstats, g->st));
     if (g->order_mode == MANTRA_ORDER_LONGEST_FIRST && a.npairs > ns) {
         HIPCHK(mantra_launch_order(&a, g->dbucket, g->dhist, g->dorder, g->st));
         a.pq = g->dorder;
     }
     if (!rg) HIPCHK(hipEventRecord(g->ev0, g->st));
-    HIPCHK(mantra_launch_sweep(&a, ns, lb, g->st));
+    HIPCHK(launch_sweep(a, sources, ns, lb, g->st));
     if (!rg) HIPCHK(hipEventRecord(g->ev1, g->st));
     if (rg) {
         ReduceArgs ra;
@@ -441,7 +445,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
             a.qbase = q;
             a.npairs = q + 1;
             HIPCHK(hipMemsetAsync(g->dwork, 0, sizeof(u32), g->st));
-            HIPCHK(mantra_launch_sweep(&a, 1, lb, g->st));
+            HIPCHK(launch_sweep(a, sp.sources, 1, lb, g->st));
             o.launches += 1;
         }
         HIPCHK(hipEventRecord(g->ev1, g->st));
@@ -457,7 +461,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
             rg->ns = ns;
             memcpy(&rg->args, &a, sizeof a);
             HIPCHK(hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal));
-            int crc = issue_kernels(g, a, ns, lb, rg);
+            int crc = issue_kernels(g, a, ns, lb, rg, sp.sources);
             hipGraph_t gr = nullptr;
             hipError_t e = hipStreamEndCapture(g->st, &gr);
             if (crc) { if (gr) hipGraphDestroy(gr); return crc; }
@@ -471,7 +475,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         o.launches += 1;
         o.reduced = true;
     } else {
-        if ((rc = issue_kernels(g, a, ns, lb, nullptr))) return rc;
+        if ((rc = issue_kernels(g, a, ns, lb, nullptr, sp.sources))) return rc;
         o.launches += 1;
     }
     int32_t nretry = 0;
@@ -504,7 +508,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         a.qbase = 0;
         a.pq = dq;
         HIPCHK(hipEventRecord(g->ev0, g->st));
-        HIPCHK(mantra_launch_sweep(&a, ns2, lb, g->st));
+        HIPCHK(launch_sweep(a, sp.sources, ns2, lb, g->st));
         HIPCHK(hipEventRecord(g->ev1, g->st));
         HIPCHK(hipStreamSynchronize(g->st));
         HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
@@ -1137,6 +1141,85 @@ int mantra_estimate(mantra_graph *g, mantra_opt opt, double eps, double delta, u
     rq.opt = opt; rq.t0 = 0; rq.t1 = INT32_MAX; rq.eps = eps; rq.delta = delta; rq.seed = seed; rq.c = 25;
     rq.node_bc = node_bc;
     return mantra_run(g, &rq, out);
+}
+
+int mantra_distances(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r, uint64_t seed,
+                     double tau, uint64_t *hist, int32_t hist_len, mantra_distance_result *out) {
+    if (!g || !out) return fail(MANTRA_E_INVALID, "graph or result is NULL");
+    if (opt < MANTRA_SH || opt > MANTRA_PFM) return fail(MANTRA_E_INVALID, "unknown optimality %d", (int)opt);
+    if (g->G != 1) return fail(MANTRA_E_INVALID, "distances need a single graph");
+    if (g->n_total < 2) return fail(MANTRA_E_INVALID, "distances need n >= 2");
+    if (r < 1 || r > INT32_MAX) return fail(MANTRA_E_INVALID, "r = %lld outside 1..2^31-1", (long long)r);
+    if (!(tau >= 0.0 && tau <= 1.0)) return fail(MANTRA_E_INVALID, "tau must be in [0, 1]");
+    if (hist_len < 0 || (hist_len > 0 && !hist)) return fail(MANTRA_E_INVALID, "bad hist buffer");
+    std::lock_guard<std::mutex> lk(g->mu);
+    hipSetDevice(g->device);
+    timing_reset(g);
+    // every finite distance has its own bin: 0..kHInf-1, then the largest
+    const int64_t nb = (int64_t)kHInf;
+    u64 *dbuf = nullptr;
+    HIPCHK(dalloc(&dbuf, (size_t)(nb + 1 + RS_N)));
+    u64 *dhist = dbuf, *drs = dbuf + nb + 1;
+    int rc = MANTRA_OK;
+    if (hipMemsetAsync(dbuf, 0, sizeof(u64) * (size_t)(nb + 1 + RS_N), g->st) != hipSuccess)
+        rc = fail(MANTRA_E_INTERNAL, "clear distance counts");
+    mantra_request rq;
+    memset(&rq, 0, sizeof rq);
+    rq.opt = opt; rq.t0 = t0; rq.t1 = t1; rq.seed = seed;
+    norm_window(rq);
+    LaunchSpec sp;
+    DevReq d = make_req(rq, STREAM_SRC, 0, 0, r, nullptr, 0);
+    d.mode = MODE_DISTANCES;
+    d.hist_len = (int32_t)nb;
+    d.hist = dhist;
+    d.rstat = drs;
+    sp.reqs.push_back(d);
+    sp.npairs = r;
+    sp.sources = true;
+    SweepOut so;
+    std::vector<u64> h((size_t)nb + 1);
+    u64 rs[RS_N];
+    if (!rc) rc = run_sweep(g, sp, so);
+    if (!rc) {
+        timing_add(g, so);
+        if (hipMemcpy(h.data(), dhist, sizeof(u64) * (size_t)(nb + 1), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(rs, drs, sizeof rs, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = fail(MANTRA_E_INTERNAL, "copy distance counts");
+    }
+    hipFree(dbuf);
+    if (rc) return rc;
+    if (rs[RS_HOPS]) return fail(MANTRA_E_LIMIT, "%llu sources reached a distance above 65534",
+                                 (unsigned long long)rs[RS_HOPS]);
+    // Algorithm 2's closing formulas on exact integer sums of the counts
+    const int32_t dlb = (int32_t)h[(size_t)nb];
+    unsigned __int128 tot = 0, sh = 0, shm1 = 0;
+    for (int64_t k = 1; k <= dlb; ++k) {
+        tot += h[(size_t)k];
+        sh += (unsigned __int128)h[(size_t)k] * (u64)k;
+        shm1 += (unsigned __int128)h[(size_t)k] * (u64)(k - 1);
+    }
+    const double n = (double)g->n_total, rr = (double)r;
+    memset(out, 0, sizeof *out);
+    out->sources = r;
+    out->reached_pairs = (int64_t)tot;
+    out->d_lb = dlb;
+    out->d_tau = -1;
+    if (tot) {
+        // D_tau: the first h whose share of the reachable pairs is >= tau
+        unsigned __int128 cum = 0;
+        for (int64_t k = 0; k <= dlb; ++k) {
+            cum += h[(size_t)k];
+            if ((double)cum / (double)tot >= tau) { out->d_tau = (int32_t)k; break; }
+        }
+        out->psi = (double)sh / (double)tot;
+    }
+    out->zeta = (double)tot / (rr * (n - 1.0));
+    out->rho = (double)shm1 / (rr * (n - 1.0));
+    out->window_edges = (int64_t)rs[RS_WINDOW];
+    out->gpu_ms = so.ms;
+    for (int32_t k = 0; k < hist_len; ++k) hist[k] = 0;
+    for (int64_t k = 0; k <= dlb && hist_len > 0; ++k) hist[std::min<int64_t>(k, hist_len - 1)] += h[(size_t)k];
+    return MANTRA_OK;
 }
 
 }  // extern "C"

@@ -180,6 +180,7 @@ struct Pair {
     const DevReq *req;
     u32 tag;
     bool level;            // sh / sfm: hop levels matter
+    bool single;           // distances: one source, every node its target (z = -1, no arcs)
 };
 
 struct Slab {
@@ -206,6 +207,7 @@ struct FwdOut {
     int64_t arcs;
     int64_t swept;
     u32 flags;
+    int64_t reached_n;    // single source: nodes listed in S.touched
 };
 
 __device__ __forceinline__ bool bm_test(const u32 *bm, int32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
@@ -254,6 +256,7 @@ __device__ __forceinline__ bool head_commit(int opt, bool rv, u32 hv, u64 Sv, u3
 // slab's global per-node scratch (AG), four passes, commits after all reads.
 // Such a tick always forms a batch of its own.
 
+template <bool SINGLE>
 __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
                               int64_t g0, int64_t g1, int32_t t, u32 &agstamp, FwdOut &o,
                               u32 &zh, u64 &zS, bool &zhit) {
@@ -316,7 +319,7 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
         bool act = idx < g1;
         int32_t v = act ? V[idx] : 0;
         bool rs = act && ((idx == g0) || V[idx - 1] != v);
-        bool zl = false;
+        bool zl = false, fa = false;
         u32 nh = 0;
         u64 nS = 0;
         if (rs) {
@@ -337,6 +340,10 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
                 }
                 if (head_commit(P.opt, rv, hv, Sv, d, c, v, P.z, zh, &nh, &nS)) {
                     ok = agstamp;
+                    if (SINGLE && !rv) {  // first arrival: list of reached nodes, hops (fm / sfm / pfm)
+                        if (P.opt != OPT_SH) S.N[v] = (u64)nh + 1ull;
+                        fa = true;
+                    }
                     if (v < H.K) { H.h[v] = nh; H.s[v] = nS; }
                     else {
                         S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh << 32);
@@ -347,6 +354,11 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
                 }
             }
             S.AGF[v] = ok;
+        }
+        if (SINGLE) {
+            const u64 fm_ = ballot(fa);
+            if (fa) S.touched[o.reached_n + mbcnt(fm_)] = v;
+            o.reached_n += __popcll(fm_);
         }
         u64 zm = ballot(zl);
         if (zm) {
@@ -378,7 +390,7 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
                 if (S.AGF[v] == agstamp) {
                     hu = (u32)x0;
                     d = (u32)ld_agent(&S.AG[2 * (int64_t)v]);
-                    if (!P.level || hu + 1 == d) {
+                    if ((!P.level || hu + 1 == d) && !SINGLE) {
                         rec = true;
                         u = U[idx];
                         su = S.XS[2 * (idx - g0) + 1];
@@ -417,6 +429,7 @@ __device__ __forceinline__ void load_batch(const LaunchArgs &a, const Pair &P, i
 // from the slab) or the commit of an earlier tick of the same batch, passed
 // from the committing lane's registers.  Maximal runs of ticks that read no
 // commit made inside the run ("segments") are processed together.
+template <bool SINGLE>
 __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H, FwdLds &L,
                         u32 &agstamp, FwdOut &o) {
     static_assert(kE == 1, "the forward sweep is written for one edge per lane");
@@ -452,7 +465,7 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                         if (m) { g1 = i + (__ffsll((long long)m) - 1); break; }
                     }
                     __syncthreads();
-                    fwd_long_tick(a, P, S, bm, H, b0, g1, tlast, agstamp, o, zh, zS, zhit);
+                    fwd_long_tick<SINGLE>(a, P, S, bm, H, b0, g1, tlast, agstamp, o, zh, zS, zhit);
                     o.swept = g1 - P.lo;
                     b0 = g1;
                     if (o.flags & REC_HOPS_LIMIT) return;
@@ -658,6 +671,17 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                 }
                 if (a.lds_bitmap) atomicOr(&bm[v >> 5], 1u << (v & 31));
             }
+            if (SINGLE) {
+                // first arrivals: the list of reached nodes, and the hops
+                // committed there (fm / sfm / pfm)
+                const bool fa = ok && cur_h == kHInf;
+                const u64 fm_ = ballot(fa);
+                if (fa) {
+                    if (opt != OPT_SH) S.N[v] = (u64)nh2 + 1ull;
+                    S.touched[o.reached_n + mbcnt(fm_)] = v;
+                }
+                o.reached_n += __popcll(fm_);
+            }
             if (act && rs) { pub_h = ok ? nh2 : cur_h; pub_S = ok ? nS : cur_S; }
             const u64 zm = ballot(ok && v == P.z);
             if (zm) {
@@ -672,7 +696,7 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             }
             // arcs of the segment
             const bool okr = single ? ok : (__shfl((int)ok, rsl) != 0);
-            const bool rec = tight && okr && keep;
+            const bool rec = tight && okr && keep && !SINGLE;
             const u64 m = ballot(rec);
             if (m) {
                 if (rec) put_arc(S, a.sl.cap, o.arcs + mbcnt(m), v, t, (u32)(b0 + l), u, s_u, h_u, d);
@@ -1025,6 +1049,8 @@ __device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
 
 // ------------------------------------------------------------ the kernel
 
+// SINGLE (the distance kernel): slots are single sources, no target
+template <bool SINGLE = false>
 __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
     // a retry launch names the original launch slots through pq
     const int64_t q = a.pq ? (int64_t)a.pq[slot] : slot;
@@ -1040,7 +1066,7 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
     if (a.ps) {
         P.g = a.pg ? a.pg[q] : 0;
         P.s = a.ps[q];
-        P.z = a.pz[q];
+        P.z = SINGLE ? -1 : a.pz[q];
     } else {
         int64_t idx;
         if (R.graph >= 0) { P.g = R.graph; idx = i; }
@@ -1052,7 +1078,7 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
         u64 zp = __umul64hi(rng_word(R.seed, st, (u64)idx, 1), (u64)(ng - 1));
         // pairs are drawn over input ids, then mapped to internal ids
         P.s = a.g.perm[noff + (int32_t)s] - noff;
-        P.z = a.g.perm[noff + (int32_t)(zp + (zp >= s ? 1 : 0))] - noff;
+        P.z = SINGLE ? -1 : a.g.perm[noff + (int32_t)(zp + (zp >= s ? 1 : 0))] - noff;
         if (R.c > 0) P.lam = rng_word(R.seed, (u64)STREAM_RADE + (u64)STREAMS_PER_GRAPH * (u64)P.g, (u64)idx, 0);
     }
     P.noff = a.g.seg_noff[P.g];
@@ -1060,8 +1086,58 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
     P.elo = a.g.seg_eoff[P.g];
     P.ehi = a.g.seg_eoff[P.g + 1];
     P.level = (P.opt == OPT_SH || P.opt == OPT_SFM);
+    P.single = SINGLE;
 }
 
+// Distances from a single source after its forward sweep: every node the
+// sweep reached (other than the source; the forward lists them in
+// S.touched at their first arrival) adds one to the bin of its distance.
+// sh: fewest hops over all arrivals (the final hop state); fm, sfm and pfm:
+// the hops committed at the first arrival, which the forward keeps in N as
+// hops + 1 (N must be zero again for the next slot, so it is cleared here,
+// also when the sweep stopped at the hops limit and nothing is counted).
+constexpr int kDistBins = 2 * kFwN;  // u32 bins in LDS, over the reverse table's keys
+static_assert(kDistBins * 4 <= (int)sizeof(u64) * kFwN, "distance bins exceed the table");
+
+__device__ void distance_hist(const Pair &P, const Slab &S, const Hub &H, u32 *lh, int64_t nreached, bool count) {
+    const int l = lane_id();
+    const DevReq *R = P.req;
+    const u32 last = (u32)R->hist_len - 1u;
+    const bool first = P.opt != OPT_SH;
+    for (int i = l; i < kDistBins; i += kWave) lh[i] = 0u;
+    __syncthreads();
+    u32 dmax = 0;
+    for (int64_t i = l; i < nreached; i += kWave) {
+        const int32_t v = S.touched[i];
+        u32 d;
+        if (first) {
+            d = (u32)(S.N[v] - 1ull);
+            S.N[v] = 0ull;
+        } else {
+            d = v < H.K ? H.h[v] : (u32)(S.F[2 * (int64_t)v] >> 32) & 0xFFFFu;
+        }
+        if (count) {
+            const u32 b = d < last ? d : last;
+            if (b < (u32)kDistBins) atomicAdd(&lh[b], 1u);
+            else atomicAdd((unsigned long long *)&R->hist[b], 1ull);
+            dmax = d > dmax ? d : dmax;
+        }
+    }
+    __syncthreads();
+    if (!count) return;
+    for (u32 i = (u32)l; i < (u32)kDistBins && i <= last; i += kWave)
+        if (lh[i]) atomicAdd((unsigned long long *)&R->hist[i], (unsigned long long)lh[i]);
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const u32 x = (u32)__shfl_xor((int)dmax, o);
+        dmax = x > dmax ? x : dmax;
+    }
+    if (l == 0 && dmax) atomicMax((unsigned long long *)&R->hist[last + 1u], (unsigned long long)dmax);
+    __syncthreads();
+}
+
+// SINGLE: every slot is a single source (distances); a kernel of its own, so
+// that the pair sweep keeps its register allocation
+template <bool SINGLE>
 __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int l = lane_id();
@@ -1097,21 +1173,34 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
         const int64_t q = a.qbase + (int64_t)(u32)uni((int)qq);
         if (q >= np) break;
         Pair P;
-        resolve_pair(a, q, P);
+        resolve_pair<SINGLE>(a, q, P);
         serial += 1;
         if (serial == 0) serial = 1;  // tag 0 never valid (fresh slabs are zero)
         P.tag = serial;
         // window: first departure of s, last arrival at z, inside [t0, t1]
-        const int32_t gs_node = P.noff + P.s, gz_node = P.noff + P.z;
+        // (a single source: to the end of [t0, t1])
+        const int32_t gs_node = P.noff + P.s;
         int64_t o0 = a.g.out_off[gs_node], o1 = a.g.out_off[gs_node + 1];
-        int64_t i0 = a.g.in_off[gz_node], i1 = a.g.in_off[gz_node + 1];
         int64_t od = wave_lower_bound(a.g.out_t, o0, o1, P.t0);
-        int64_t id = wave_upper_bound(a.g.in_t, i0, i1, P.t1) - 1;
-        bool ok = od < o1 && id >= i0;
-        int32_t dep = ok ? a.g.out_t[od] : 0, lin = ok ? a.g.in_t[id] : 0;
-        ok = ok && dep <= P.t1 && lin >= P.t0 && lin >= dep;
+        bool ok;
+        int32_t dep, lin;
+        if (SINGLE) {
+            ok = od < o1;
+            dep = ok ? a.g.out_t[od] : 0;
+            lin = P.t1;
+            ok = ok && dep <= P.t1;
+        } else {
+            const int32_t gz_node = P.noff + P.z;
+            int64_t i0 = a.g.in_off[gz_node], i1 = a.g.in_off[gz_node + 1];
+            int64_t id = wave_upper_bound(a.g.in_t, i0, i1, P.t1) - 1;
+            ok = od < o1 && id >= i0;
+            dep = ok ? a.g.out_t[od] : 0;
+            lin = ok ? a.g.in_t[id] : 0;
+            ok = ok && dep <= P.t1 && lin >= P.t0 && lin >= dep;
+        }
         FwdOut fo;
         fo.reached = false; fo.zh = kHInf; fo.zS = 0; fo.t_arr = -1; fo.arcs = 0; fo.swept = 0; fo.flags = 0;
+        fo.reached_n = 0;
         if (ok) {
             P.lo = wave_lower_bound(a.g.T, P.elo, P.ehi, dep);
             P.hi = wave_upper_bound(a.g.T, P.lo, P.ehi, lin);
@@ -1127,8 +1216,10 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
                 if (a.lds_bitmap) bm[P.s >> 5] |= 1u << (P.s & 31);
             }
             __syncthreads();
-            forward(a, P, S, bm, H, tab.f, agstamp, fo);
+            forward<SINGLE>(a, P, S, bm, H, tab.f, agstamp, fo);
             __syncthreads();
+            if (SINGLE) distance_hist(P, S, H, reinterpret_cast<u32 *>(tab.r.tb_key), fo.reached_n,
+                                      !(fo.flags & REC_HOPS_LIMIT));
             // the reverse table reuses the forward's LDS: empty it
             for (int i = l; i < kFwN; i += kWave) { tab.r.tb_key[i] = 0; }
             stamp = 1;
@@ -1261,12 +1352,26 @@ __global__ void __launch_bounds__(256) k_pair_keys(LaunchArgs a, u32 *bucket, u6
     a.pq = nullptr;
     Pair P;
     resolve_pair(a, slot, P);
-    const int32_t gs = P.noff + P.s, gz = P.noff + P.z;
+    if (P.req->mode == MODE_DISTANCES) { P.single = true; P.z = -1; }
+    const int32_t gs = P.noff + P.s;
     const int64_t o0 = a.g.out_off[gs], o1 = a.g.out_off[gs + 1];
-    const int64_t i0 = a.g.in_off[gz], i1 = a.g.in_off[gz + 1];
     const int64_t od = lower_bound_1(a.g.out_t, o0, o1, P.t0);
-    const int64_t id = lower_bound_1(a.g.in_t, i0, i1, P.t1 == INT32_MAX ? P.t1 : P.t1 + 1) - 1;
     u64 est = 0;
+    if (P.single) {
+        // a single source: from its first departure to the window's end
+        if (od < o1 && a.g.out_t[od] <= P.t1) {
+            const int64_t lo = lower_bound_1(a.g.T, P.elo, P.ehi, a.g.out_t[od]);
+            const int64_t hi = lower_bound_1(a.g.T, lo, P.ehi, P.t1 == INT32_MAX ? P.t1 : P.t1 + 1);
+            est = (u64)(hi - lo);
+        }
+        const u32 b = order_bucket(est);
+        bucket[slot] = b;
+        atomicAdd((unsigned long long *)&hist[b], 1ull);
+        return;
+    }
+    const int32_t gz = P.noff + P.z;
+    const int64_t i0 = a.g.in_off[gz], i1 = a.g.in_off[gz + 1];
+    const int64_t id = lower_bound_1(a.g.in_t, i0, i1, P.t1 == INT32_MAX ? P.t1 : P.t1 + 1) - 1;
     if (od < o1 && id >= i0) {
         const int32_t dep = a.g.out_t[od], lin = a.g.in_t[id];
         if (dep <= P.t1 && lin >= P.t0 && lin >= dep) {
@@ -1358,7 +1463,12 @@ __global__ void k_fill_u64(u64 *p, u64 val, int64_t n) {
 
 extern "C" {
 hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(mantra::k_sweep, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    hipLaunchKernelGGL(mantra::k_sweep<false>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    return hipGetLastError();
+}
+// the single-source (distance) form of the sweep
+hipError_t mantra_launch_sweep_sources(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(mantra::k_sweep<true>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
     return hipGetLastError();
 }
 hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st) {
@@ -1396,7 +1506,7 @@ size_t mantra_tab_lds_bytes(void) { return sizeof(mantra::TabLds); }
 // resident sweep workgroups per CU for a given dynamic LDS size
 int mantra_sweep_occupancy(size_t lds_bytes) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mantra::k_sweep, 64, lds_bytes) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mantra::k_sweep<false>, 64, lds_bytes) != hipSuccess) return 0;
     return nb;
 }
 }
