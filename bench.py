@@ -1,7 +1,7 @@
 """Benchmark of the temporal-betweenness hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--slabs N]
-                    [--no-forms] [--no-serve] [--no-cpu-baseline]
+                    [--no-forms] [--no-serve] [--no-distances] [--no-cpu-baseline]
     python bench.py --calibrate-copy     (plain copy kernel for the traffic counters)
 
 Workload "mid-chunglu-n50k": directed Chung-Lu temporal graph (degree
@@ -23,6 +23,8 @@ Prints one JSON line (value: sampled pairs/s of the steps) with
    unbatched one-launch-per-pair form (timed on a fixed sample);
  - "serve": requests with Poisson arrivals (random windows, optimalities,
    eps in {0.01, 0.005}) through the serving scheduler: p50/p99 latency;
+ - "distances": Algorithm 2 (sampled temporal distance metrics) from 256
+   sources, the paper's seed count, for sh and pfm on the same graph;
  - "cpu_baseline": the oracle on the host's cores, on a bounded sample.
 """
 import argparse
@@ -50,9 +52,9 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip
 # counter bytes that the same counters give for a plain copy of known size),
 # valid for the kernel source with this SHA-256 only.
 TRAFFIC = {
-    "sweep_sha256": "e2a17b826b86e7114af1944797fa011711d8643aca6557a704400f07e8958e4e",
-    "fetch_bytes_per_launch": 4.915e11,   # 2.39982e8 KiB x 1.99994
-    "write_bytes_per_launch": 7.843e10,   # 7.65943e7 KiB x 1.00000
+    "sweep_sha256": "b13423949da4185e633a9377ab146c898e629056a76d8b1a4a492eb9619ec948",
+    "fetch_bytes_per_launch": 4.9195e+11,   # 2.40219e+08 KiB x 1.99995
+    "write_bytes_per_launch": 7.8473e+10,   # 7.66338e+07 KiB x 1.00000
 }
 
 
@@ -120,6 +122,22 @@ def forms(gg, torch, seed):
     return out
 
 
+def distances(gg, torch, seed, r=256):
+    """Algorithm 2 from r sources (sh and pfm, tau = 0.9), blocking calls."""
+    out = {}
+    for opt in ("sh", "pfm"):
+        gg.distances(opt, 16, seed=seed + 1)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, res = gg.distances(opt, r, seed=seed, tau=0.9)
+        wall = time.perf_counter() - t0
+        out[opt] = {"sources": r, "wall_ms": wall * 1e3, "gpu_ms": res["gpu_ms"],
+                    "temporal_edges_per_s": res["window_edges"] / (res["gpu_ms"] / 1e3),
+                    "d_lb": res["d_lb"], "d_tau": res["d_tau"], "zeta": res["zeta"], "psi": res["psi"],
+                    "rho": res["rho"]}
+    return out
+
+
 def serve(gg, G, torch, n_req=12, rate=50.0, seed=4002):
     """Poisson arrivals at `rate` req/s; each request a random window of
     5-100% of the span, a uniform optimality and eps in {0.01, 0.005}."""
@@ -183,6 +201,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-distances", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--slabs", type=int, default=0,
                     help="fixed number of persistent workgroups instead of the autotuner's pick "
@@ -256,12 +275,14 @@ def main():
         "launch": tuned,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "mantra::k_sweep", "algorithmic_bytes_per_launch": abytes},
+                     "kernel": "mantra::k_sweep<false>", "algorithmic_bytes_per_launch": abytes},
     }
     if not args.no_forms:
         out["forms"] = forms(gg, torch, args.seed)
     if not args.no_serve:
         out["serve"] = serve(gg, G, torch)
+    if not args.no_distances:
+        out["distances"] = distances(gg, torch, args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(G, args.seed)
     print(json.dumps(out), flush=True)
