@@ -138,7 +138,7 @@ def distances(gg, torch, seed, r=256):
     return out
 
 
-def serve(gg, G, torch, n_req=12, rate=50.0, seed=4002):
+def serve(gg, G, torch, n_req=12, rate=50.0, seed=4002, workload_name=WORKLOAD):
     """Poisson arrivals at `rate` req/s; each request a random window of
     5-100% of the span, a uniform optimality and eps in {0.01, 0.005}."""
     import numpy as np
@@ -151,14 +151,19 @@ def serve(gg, G, torch, n_req=12, rate=50.0, seed=4002):
     t_start = time.perf_counter()
 
     def waiter(i, tk):
+        ok = True
         try:
             res = tk.poll(timeout_ms=-1)
         except Exception as e:  # noqa: BLE001 - saturated fm counts are reported, not fatal
             res = tk.result
             errs.append(str(e))
+            ok = False
         if res is not None:
-            lat[i] = res["latency_ms"]
             pairs[i] = res["samples"] + res["s_boot"]
+            if ok:
+                lat[i] = res["latency_ms"]
+            print("request %d (%s) %s after %.0f ms, %d pairs" % (i, opts[reqs[i]["opt"]], "done" if ok else "failed",
+                                                               res["latency_ms"], pairs[i]), file=sys.stderr, flush=True)
 
     threads = []
     for i, rq in enumerate(reqs):
@@ -177,8 +182,10 @@ def serve(gg, G, torch, n_req=12, rate=50.0, seed=4002):
     L = np.array([x for x in lat if x is not None])
     return {"requests": n_req, "offered_req_per_s": rate, "completed": int(L.size), "wall_s": wall,
             "completed_req_per_s": L.size / wall, "pairs_per_s": sum(pairs) / wall,
-            "p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99)),
-            "overflowed": len(errs), "workload": WORKLOAD + " windows/optimalities/eps of the serving recipe"}
+            "p50_ms": float(np.percentile(L, 50)) if L.size else None,
+            "p99_ms": float(np.percentile(L, 99)) if L.size else None,
+            "latency_of": "completed requests", "overflowed": len(errs),
+            "workload": workload_name + ", windows/optimalities/eps of the serving recipe"}
 
 
 def calibrate_copy(torch):
@@ -202,6 +209,10 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-distances", action="store_true")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving measurement, on --serve-workload (prints {\"serve\": ...})")
+    ap.add_argument("--serve-workload", default=WORKLOAD)
+    ap.add_argument("--serve-requests", type=int, default=12)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--slabs", type=int, default=0,
                     help="fixed number of persistent workgroups instead of the autotuner's pick "
@@ -220,6 +231,15 @@ def main():
     import paper_2304_08356_amd as pk
     from synthgen import workload
 
+    if args.serve_only:
+        t0 = time.perf_counter()
+        G = workload(args.serve_workload)
+        gg = pk.Graph.of(G)
+        print("graph %s resident after %.1f s" % (args.serve_workload, time.perf_counter() - t0), file=sys.stderr,
+              flush=True)
+        print(json.dumps({"serve": serve(gg, G, torch, n_req=args.serve_requests,
+                                         workload_name=args.serve_workload)}), flush=True)
+        return
     G = workload(WORKLOAD)
     gg = pk.Graph.of(G)
     # launch configuration picked by the autotuner on a calibration sample
@@ -280,7 +300,7 @@ def main():
     if not args.no_forms:
         out["forms"] = forms(gg, torch, args.seed)
     if not args.no_serve:
-        out["serve"] = serve(gg, G, torch)
+        out["serve"] = serve(gg, G, torch, n_req=args.serve_requests)
     if not args.no_distances:
         out["distances"] = distances(gg, torch, args.seed)
     if not args.no_cpu_baseline:

@@ -69,11 +69,10 @@ struct DevReq {
 };
 
 struct DevSlabs {
-    u64 *F;           // [ns][nmax][2]  {tag | h<<32, S}
-    u64 *R;           // [ns][nmax][2]  {tag | lvl<<32, acc}
+    u64 *F;           // [ns][nmax][2]  forward {tag | h<<32, S}, then reverse {rtag | lvl<<32, acc}
     u64 *N;           // [ns][nmax]     zero between pairs
-    u64 *AG;          // [ns][nmax][2]  big-tick aggregation {~stamp<<32 | dmin, sum}
-    u32 *AGF;         // [ns][nmax]
+    u64 *AG;          // [ns][gmax][2]  big-tick aggregation per head run {~stamp<<32 | dmin, sum}
+    u32 *AGF;         // [ns][gmax]     big-tick commit stamp per head run
     int32_t *touched; // [ns][nmax]
     u64 *arcs;        // [ns][cap][4]   per slab: cap x {head | t<<32}, then cap x {k | u<<32, tail count, tl | hl<<16}
     u64 *XS;          // [ns][gmax][2]  big-tick scratch

@@ -190,6 +190,7 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
         run = same ? run + 1 : 1;
         if (run > gm) gm = run;
     }
+    if (gm >= ((int64_t)1 << 31)) return fail(MANTRA_E_INVALID, "a tick holds %lld edges (at most 2^31-1)", (long long)gm);
     g->gmax = gm;
     // CSR of out- and in-edge times per global node (ascending times)
     std::vector<int64_t> ooff((size_t)ntot + 1, 0), ioff((size_t)ntot + 1, 0);
@@ -261,10 +262,11 @@ static size_t lds_bytes(const mantra_graph *g) {
     return b;
 }
 
-// device bytes of one slab's per-node state (F, R, AG: 16 B; N: 8 B; AGF,
-// touched: 4 B) and its big-tick scratch
+// device bytes of one slab's per-node state (F: 16 B, shared by the forward
+// and the reverse; N: 8 B; touched: 4 B) and of its per-tick scratch (XS and
+// AG: 16 B, AGF: 4 B per edge of the longest tick)
 static size_t slab_state_bytes(const mantra_graph *g) {
-    return (size_t)g->nmax * 64 + (size_t)g->gmax * 16 + 16;
+    return (size_t)g->nmax * 28 + (size_t)g->gmax * 36 + 16;
 }
 
 // device memory and the share of it the slab pool (state and arc buffers)
@@ -301,9 +303,10 @@ int auto_slabs(const mantra_graph *g) {
         int by_lds = (int)((160 * 1024) / (lb ? lb : 1));
         per_cu = std::min(8, std::max(1, by_lds));
     }
-    // large graphs: the per-node state in half the pool budget bounds the
-    // number of pairs in flight
-    int64_t by_mem = (int64_t)(pool_budget(g) / 2 / slab_state_bytes(g));
+    // large graphs: the per-node state in a quarter of the pool budget bounds
+    // the number of pairs in flight; the rest holds their arc records, whose
+    // room decides how many pairs must be re-run with a full-window buffer
+    int64_t by_mem = (int64_t)(pool_budget(g) / 4 / slab_state_bytes(g));
     return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, by_mem));
 }
 
@@ -314,8 +317,8 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
     p.release();
     p.nmax = nmax; p.cap = cap; p.gmax = gmax;
     size_t ns = (size_t)nslabs;
-    if (dalloc(&p.F, ns * nmax * 2) || dalloc(&p.R, ns * nmax * 2) || dalloc(&p.N, ns * nmax) ||
-        dalloc(&p.AG, ns * nmax * 2) || dalloc(&p.AGF, ns * nmax) || dalloc(&p.touched, ns * nmax) ||
+    if (dalloc(&p.F, ns * nmax * 2) || dalloc(&p.N, ns * nmax) ||
+        dalloc(&p.AG, ns * (size_t)gmax * 2) || dalloc(&p.AGF, ns * (size_t)gmax) || dalloc(&p.touched, ns * nmax) ||
         dalloc(&p.arcs, ns * (size_t)cap * 4) || dalloc(&p.XS, ns * (size_t)gmax * 2) ||
         dalloc(&p.hdr, ns * 4)) {
         p.release();
@@ -324,10 +327,9 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
                     (long long)nmax, (long long)cap);
     }
     HIPCHK(hipMemsetAsync(p.F, 0, sizeof(u64) * ns * nmax * 2, g->st));
-    HIPCHK(hipMemsetAsync(p.R, 0, sizeof(u64) * ns * nmax * 2, g->st));
     HIPCHK(hipMemsetAsync(p.N, 0, sizeof(u64) * ns * nmax, g->st));
-    HIPCHK(hipMemsetAsync(p.AG, 0xFF, sizeof(u64) * ns * nmax * 2, g->st));
-    HIPCHK(hipMemsetAsync(p.AGF, 0, sizeof(u32) * ns * nmax, g->st));
+    HIPCHK(hipMemsetAsync(p.AG, 0xFF, sizeof(u64) * ns * gmax * 2, g->st));
+    HIPCHK(hipMemsetAsync(p.AGF, 0, sizeof(u32) * ns * gmax, g->st));
     HIPCHK(hipMemsetAsync(p.hdr, 0, sizeof(u32) * ns * 4, g->st));
     HIPCHK(hipStreamSynchronize(g->st));
     p.nslabs = nslabs;

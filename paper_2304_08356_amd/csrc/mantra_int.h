@@ -63,20 +63,20 @@ static inline hipError_t dalloc(T **p, size_t count) {
 struct SlabPool {
     int nslabs = 0;
     int64_t nmax = 0, cap = 0, gmax = 0;
-    u64 *F = nullptr, *R = nullptr, *N = nullptr, *AG = nullptr, *arcs = nullptr, *XS = nullptr;
+    u64 *F = nullptr, *N = nullptr, *AG = nullptr, *arcs = nullptr, *XS = nullptr;
     u32 *AGF = nullptr, *hdr = nullptr;
     int32_t *touched = nullptr;
     void release() {
-        hipFree(F); hipFree(R); hipFree(N); hipFree(AG); hipFree(arcs); hipFree(XS);
+        hipFree(F); hipFree(N); hipFree(AG); hipFree(arcs); hipFree(XS);
         hipFree(AGF); hipFree(hdr); hipFree(touched);
-        F = R = N = AG = arcs = XS = nullptr;
+        F = N = AG = arcs = XS = nullptr;
         AGF = hdr = nullptr;
         touched = nullptr;
         nslabs = 0;
     }
     DevSlabs view() const {
         DevSlabs s;
-        s.F = F; s.R = R; s.N = N; s.AG = AG; s.AGF = AGF; s.touched = touched; s.arcs = arcs;
+        s.F = F; s.N = N; s.AG = AG; s.AGF = AGF; s.touched = touched; s.arcs = arcs;
         s.XS = XS; s.hdr = hdr; s.nmax = nmax; s.cap = cap; s.gmax = gmax;
         return s;
     }

@@ -32,6 +32,7 @@ struct ServeState {
     size_t budget = 0, used = 0;
     int max_active = 64;
     bool stop = false;
+    bool trace = false;  // one stderr line per shared launch (MANTRA_SERVE_TRACE set)
     std::thread th;
 };
 
@@ -115,6 +116,11 @@ static void serve_loop(mantra_graph *g) {
                 SweepOut o;
                 int rc = run_sweep(g, sp, o);
                 const std::string launch_err = rc ? g_err : std::string();
+                if (S.trace)
+                    fprintf(stderr, "serve: launch of %lld pairs from %zu requests, %.1f ms (%d launches, %llu pairs "
+                                    "re-run for arc room), rc %d, %zu active\n",
+                            (long long)sp.npairs, in_launch.size(), o.ms, o.launches, (unsigned long long)o.st[5], rc,
+                            act.size());
                 for (auto &t : in_launch) {
                     t->run.R.gpu_ms += o.ms;
                     if (rc) { t->run.rc = rc; t->run.err = launch_err; continue; }
@@ -155,6 +161,7 @@ static int serve_start(mantra_graph *g) {
     if (g->serve) return MANTRA_OK;
     std::unique_ptr<ServeState> S(new ServeState());
     S->budget = default_budget(g);
+    S->trace = getenv("MANTRA_SERVE_TRACE") != nullptr;
     g->serve = S.release();
     try {
         g->serve->th = std::thread(serve_loop, g);

@@ -178,7 +178,8 @@ struct Pair {
     int64_t lo, hi;        // window
     u64 lam;
     const DevReq *req;
-    u32 tag;
+    u32 tag;               // forward state words of this pair carry it
+    u32 rtag;              // reverse state words (the same memory) carry this one
     bool level;            // sh / sfm: hop levels matter
     bool single;           // distances: one source, every node its target (z = -1, no arcs)
 };
@@ -264,11 +265,22 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
     const int32_t *U = a.g.U, *V = a.g.V;
     agstamp += 1;
     const u64 hi_key = (u64)(~agstamp) << 32;
+    const u64 le = (l == kWave - 1) ? kUMax : ((2ull << l) - 1ull);  // lanes <= l
+    // The tick's edges are sorted by head, so each head's edges form one run.
+    // A run is aggregated in the slab's scratch at the position of its first
+    // edge (k, counted from g0), not at its node: the scratch is as long as
+    // the longest tick, not the node count.
+    int64_t carry = g0;  // start of the run that continues into a sub-batch
     // pass A: tails, candidate minima, zero the sums
     for (int64_t sb = g0; sb < g1; sb += kWave) {
         int64_t idx = sb + l;
         bool act = idx < g1;
         int32_t u = act ? U[idx] : 0, v = act ? V[idx] : 0;
+        const bool rs = act && ((idx == g0) || V[idx - 1] != v);
+        const u64 rm = ballot(rs);
+        const u64 mine = rm & le;
+        const int64_t k = (mine ? sb + (63 - __clzll((long long)mine)) : carry) - g0;
+        if (rm) carry = sb + (63 - __clzll((long long)rm));
         bool rt = false;
         u32 hu = 0;
         u64 Su = 0;
@@ -283,13 +295,13 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
         }
         bool hl = false;
         if (act) {
-            S.XS[2 * (idx - g0)] = rt ? ((u64)hu | (1ull << 32)) : 0ull;
+            // {hops | reached << 32 | run position << 33, count} of the tail
+            S.XS[2 * (idx - g0)] = rt ? ((u64)hu | (1ull << 32) | ((u64)k << 33)) : 0ull;
             S.XS[2 * (idx - g0) + 1] = Su;
-            bool rs = (idx == g0) || V[idx - 1] != v;
-            if (rs) S.AG[2 * (int64_t)v + 1] = 0ull;
+            if (rs) S.AG[2 * k + 1] = 0ull;
             if (rt) {
                 if (hu + 1 >= kHInf) hl = true;
-                else atomicMin((unsigned long long *)&S.AG[2 * (int64_t)v], (unsigned long long)(hi_key | (hu + 1)));
+                else atomicMin((unsigned long long *)&S.AG[2 * k], (unsigned long long)(hi_key | (hu + 1)));
             }
         }
         if (ballot(hl)) o.flags |= REC_HOPS_LIMIT;
@@ -302,12 +314,12 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
         u64 x0 = S.XS[2 * (idx - g0)];
         if (!(x0 >> 32)) continue;
         u32 hu = (u32)x0;
+        const int64_t k = (int64_t)(x0 >> 33);
         u64 Su = S.XS[2 * (idx - g0) + 1];
-        int32_t v = V[idx];
-        u64 key = ld_agent(&S.AG[2 * (int64_t)v]);
+        u64 key = ld_agent(&S.AG[2 * k]);
         u32 d = (u32)key;
         bool tight = P.level ? (hu + 1 == d) : true;
-        if (tight) glb_sat_add(&S.AG[2 * (int64_t)v + 1], Su);
+        if (tight) glb_sat_add(&S.AG[2 * k + 1], Su);
     }
     __syncthreads();
     // pass C: one commit per head run
@@ -323,11 +335,12 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
         u32 nh = 0;
         u64 nS = 0;
         if (rs) {
-            u64 key = ld_agent(&S.AG[2 * (int64_t)v]);
+            const int64_t k = idx - g0;
+            u64 key = ld_agent(&S.AG[2 * k]);
             u32 ok = 0;
             if ((key & 0xFFFFFFFF00000000ull) == hi_key) {
                 u32 d = (u32)key;
-                u64 c = ld_agent(&S.AG[2 * (int64_t)v + 1]);
+                u64 c = ld_agent(&S.AG[2 * k + 1]);
                 bool rv = false;
                 u32 hv = 0;
                 u64 Sv = 0;
@@ -353,7 +366,7 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
                     zl = (v == P.z);
                 }
             }
-            S.AGF[v] = ok;
+            S.AGF[k] = ok;
         }
         if (SINGLE) {
             const u64 fm_ = ballot(fa);
@@ -387,9 +400,10 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
             u64 x0 = S.XS[2 * (idx - g0)];
             if (x0 >> 32) {
                 v = V[idx];
-                if (S.AGF[v] == agstamp) {
+                const int64_t k = (int64_t)(x0 >> 33);
+                if (S.AGF[k] == agstamp) {
                     hu = (u32)x0;
-                    d = (u32)ld_agent(&S.AG[2 * (int64_t)v]);
+                    d = (u32)ld_agent(&S.AG[2 * k]);
                     if ((!P.level || hu + 1 == d) && !SINGLE) {
                         rec = true;
                         u = U[idx];
@@ -826,7 +840,7 @@ __device__ void rev_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
             u64 acc = 0;
             if (v != P.z) {
                 u64 th = ld_agent(&S.R[2 * (int64_t)v]);
-                if ((u32)th == P.tag) { valid = true; lvl = (u32)(th >> 32) & 0xFFFFu; acc = ld_agent(&S.R[2 * (int64_t)v + 1]); }
+                if ((u32)th == P.rtag) { valid = true; lvl = (u32)(th >> 32) & 0xFFFFu; acc = ld_agent(&S.R[2 * (int64_t)v + 1]); }
             }
             B = head_B(P, X, v, hl, valid, lvl, acc);
         }
@@ -843,8 +857,8 @@ __device__ void rev_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
         u32 tl = (u32)S.arcx[3 * i + 2] & 0xFFFFu;
         u32 want = P.level ? tl : 0u;
         u64 th = ld_agent(&S.R[2 * (int64_t)u]);
-        if ((u32)th != P.tag || ((u32)(th >> 32) & 0xFFFFu) != want) {
-            S.R[2 * (int64_t)u] = (u64)P.tag | ((u64)want << 32);
+        if ((u32)th != P.rtag || ((u32)(th >> 32) & 0xFFFFu) != want) {
+            S.R[2 * (int64_t)u] = (u64)P.rtag | ((u64)want << 32);
             S.R[2 * (int64_t)u + 1] = 0;
         }
     }
@@ -946,11 +960,11 @@ __device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             tval[j] = false; tlvl[j] = 0; tacc[j] = 0;
             if (al[j] && vv[j] != P.z) {
                 u64 th = ld_agent(&S.R[2 * (int64_t)vv[j]]);
-                if ((u32)th == P.tag) { hval[j] = true; hlvl[j] = (u32)(th >> 32) & 0xFFFFu; hacc[j] = ld_agent(&S.R[2 * (int64_t)vv[j] + 1]); }
+                if ((u32)th == P.rtag) { hval[j] = true; hlvl[j] = (u32)(th >> 32) & 0xFFFFu; hacc[j] = ld_agent(&S.R[2 * (int64_t)vv[j] + 1]); }
             }
             if (in[j] && alive_test(a, bm, X, uu[j])) {
                 u64 th = ld_agent(&S.R[2 * (int64_t)uu[j]]);
-                if ((u32)th == P.tag) { tval[j] = true; tlvl[j] = (u32)(th >> 32) & 0xFFFFu; tacc[j] = ld_agent(&S.R[2 * (int64_t)uu[j] + 1]); }
+                if ((u32)th == P.rtag) { tval[j] = true; tlvl[j] = (u32)(th >> 32) & 0xFFFFu; tacc[j] = ld_agent(&S.R[2 * (int64_t)uu[j] + 1]); }
             }
         }
         stamp += 1;
@@ -1038,7 +1052,7 @@ __device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                 if ((u32)(key >> 32) != stamp) continue;
                 u32 node = (u32)key;
                 u32 x = L.tb_lvl[sl];
-                S.R[2 * (int64_t)node] = (u64)P.tag | ((u64)(x & 0xFFFFu) << 32);
+                S.R[2 * (int64_t)node] = (u64)P.rtag | ((u64)(x & 0xFFFFu) << 32);
                 S.R[2 * (int64_t)node + 1] = L.tb_acc[sl];
             }
         }
@@ -1144,10 +1158,10 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
     const int64_t slab = blockIdx.x;
     Slab S;
     S.F = a.sl.F + slab * a.sl.nmax * 2;
-    S.R = a.sl.R + slab * a.sl.nmax * 2;
+    S.R = S.F;  // the reverse state shares the forward's words (their tags differ)
     S.N = a.sl.N + slab * a.sl.nmax;
-    S.AG = a.sl.AG + slab * a.sl.nmax * 2;
-    S.AGF = a.sl.AGF + slab * a.sl.nmax;
+    S.AG = a.sl.AG + slab * a.sl.gmax * 2;
+    S.AGF = a.sl.AGF + slab * a.sl.gmax;
     S.touched = a.sl.touched + slab * a.sl.nmax;
     S.arcm = a.sl.arcs + slab * a.sl.cap * 4;
     S.arcx = S.arcm + a.sl.cap;
@@ -1174,9 +1188,11 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
         if (q >= np) break;
         Pair P;
         resolve_pair<SINGLE>(a, q, P);
-        serial += 1;
-        if (serial == 0) serial = 1;  // tag 0 never valid (fresh slabs are zero)
+        // two tags per pair; 0 and 1 never valid (fresh slabs are zero)
+        serial += 2;
+        if (serial < 2u) serial = 2u;
         P.tag = serial;
+        P.rtag = serial + 1u;
         // window: first departure of s, last arrival at z, inside [t0, t1]
         // (a single source: to the end of [t0, t1])
         const int32_t gs_node = P.noff + P.s;
@@ -1238,7 +1254,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
             // flow conservation at the origin: B(origin) must equal sigma
             u64 th = ld_agent(&S.R[2 * (int64_t)P.s]);
             u64 bo = 0;
-            if ((u32)th == P.tag && (!P.level || ((u32)(th >> 32) & 0xFFFFu) == 0u)) bo = ld_agent(&S.R[2 * (int64_t)P.s + 1]);
+            if ((u32)th == P.rtag && (!P.level || ((u32)(th >> 32) & 0xFFFFu) == 0u)) bo = ld_agent(&S.R[2 * (int64_t)P.s + 1]);
             if (bo != sigma) flags |= REC_SELFCHECK;
         }
         if (X.ovf) {
