@@ -1,7 +1,7 @@
 """Benchmark of the temporal-betweenness hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--slabs N]
-                    [--no-forms] [--no-serve] [--no-distances] [--no-cpu-baseline]
+                    [--no-forms] [--no-serve] [--no-trk] [--no-distances] [--no-cpu-baseline]
     python bench.py --calibrate-copy     (plain copy kernel for the traffic counters)
 
 Workload "mid-chunglu-n50k": directed Chung-Lu temporal graph (degree
@@ -23,6 +23,8 @@ Prints one JSON line (value: sampled pairs/s of the steps) with
    unbatched one-launch-per-pair form (timed on a fixed sample);
  - "serve": requests with Poisson arrivals (random windows, optimalities,
    eps in {0.01, 0.005}) through the serving scheduler: p50/p99 latency;
+ - "trk": the same step with the TRK estimator (one sampled optimal walk per
+   pair instead of the dependency sweep);
  - "distances": Algorithm 2 (sampled temporal distance metrics) from 256
    sources, the paper's seed count, for sh and pfm on the same graph;
  - "cpu_baseline": the oracle on the host's cores, on a bounded sample.
@@ -122,6 +124,22 @@ def forms(gg, torch, seed):
     return out
 
 
+def trk_step(gg, torch, seed, steps=3):
+    """The bench step (sfm, r = 20,000, c = 25, node + edge sums) with the
+    TRK estimator."""
+    gg.run(OPT, fixed_r=R_PER_STEP, seed=seed + 999, c=C, edges=True, trk=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = 0.0
+    for k in range(steps):
+        gg.run(OPT, fixed_r=R_PER_STEP, seed=seed + k, c=C, edges=True, trk=True)
+        ms += gg.last_timing()["sweep_ms"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"steps": steps, "pairs_per_s": R_PER_STEP * steps / wall, "ms_per_step": wall * 1e3 / steps,
+            "sweep_ms_per_launch": ms / steps}
+
+
 def distances(gg, torch, seed, r=256):
     """Algorithm 2 from r sources (sh and pfm, tau = 0.9), blocking calls."""
     out = {}
@@ -209,6 +227,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-distances", action="store_true")
+    ap.add_argument("--no-trk", action="store_true")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving measurement, on --serve-workload (prints {\"serve\": ...})")
     ap.add_argument("--serve-workload", default=WORKLOAD)
@@ -301,6 +320,8 @@ def main():
         out["forms"] = forms(gg, torch, args.seed)
     if not args.no_serve:
         out["serve"] = serve(gg, G, torch, n_req=args.serve_requests)
+    if not args.no_trk:
+        out["trk"] = trk_step(gg, torch, args.seed)
     if not args.no_distances:
         out["distances"] = distances(gg, torch, args.seed)
     if not args.no_cpu_baseline:

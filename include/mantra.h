@@ -109,6 +109,19 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
                        const int32_t *graph, const int32_t *s, const int32_t *z,
                        mantra_pair_record *out, double *node_f, double *edge_f);
 
+/* The TRK estimator's walks for r explicit pairs (arguments and outputs as
+ * mantra_count_pairs): one optimal walk per reachable pair, drawn backwards
+ * from z with probability 1/sigma_sz (the appendix's path sampler, Theorem on
+ * the path sampler).  Step j of pair q draws w = the SplitMix64 output
+ * (q * 2^16 + j + 1) of the generator started at the (2^20 + 1)-th output of
+ * the one started at seed, takes r = floor(w * W / 2^64) for the step's total
+ * weight W, and picks the first candidate arc, in the order (time, input
+ * head id, input tail id), whose running weight exceeds r.  node_f[q*n + v]
+ * gets the walk's internal visits of v, edge_f[q*m + e] its uses of e. */
+int mantra_sample_paths(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r,
+                        const int32_t *graph, const int32_t *s, const int32_t *z, uint64_t seed,
+                        mantra_pair_record *out, double *node_f, double *edge_f);
+
 /* One estimation request. */
 typedef struct {
     mantra_opt opt;
@@ -125,6 +138,13 @@ typedef struct {
 } mantra_request;
 
 #define MANTRA_F_EDGE_BC 1u /* also estimate temporal-edge betweenness */
+#define MANTRA_F_TRK 2u     /* the TRK estimator (appendix on other estimators):
+                               per sampled pair one optimal walk, drawn with
+                               probability 1/sigma_sz, and f(v) = its internal
+                               visits of v, f(e) = its uses of e, instead of
+                               the ob estimator's N(v)/sigma_sz.  Unbiased for
+                               the same betweenness; f in {0, 1} except for fm
+                               walks, which may revisit a node */
 
 typedef struct {
     int32_t status;        /* mantra_status of the request */

@@ -685,3 +685,116 @@ int orc_source_hops(const orc_graph *g, int32_t opt, int32_t t0, int32_t t1, int
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* the TRK estimator's path sampler (appendix on other estimators)          */
+
+/* draw j of pair i on a path stream: the SplitMix64 output (i * 2^16 + j + 1)
+   of the generator started at the (2^20 + stream + 1)-th output of the one
+   started at seed */
+uint64_t orc_trk_word(uint64_t seed, uint64_t stream, uint64_t i, uint64_t j) {
+    uint64_t key = orc_splitmix_nth(seed, ((uint64_t)1 << 20) + stream + 1);
+    return orc_splitmix_nth(key, (i << 16) + j + 1);
+}
+
+typedef struct { int64_t k; uint64_t w; } trk_cand;
+static const pws *g_trk_w;
+static int cmp_trk(const void *a, const void *b) { /* (time, head, tail) ascending; origin (k < 0) first */
+    int64_t x = ((const trk_cand *)a)->k, y = ((const trk_cand *)b)->k;
+    if (x < 0 || y < 0) return (x < 0) ? (y < 0 ? 0 : -1) : 1;
+    const pws *w = g_trk_w;
+    if (w->wt[x] != w->wt[y]) return w->wt[x] < w->wt[y] ? -1 : 1;
+    if (w->wv[x] != w->wv[y]) return w->wv[x] < w->wv[y] ? -1 : 1;
+    return w->wu[x] < w->wu[y] ? -1 : (w->wu[x] > w->wu[y]);
+}
+
+/*
+ * One optimal walk of the pair (s, z), drawn backwards with probability
+ * 1/sigma_sz: the terminal appearance (z, t_z) with probability
+ * sigma(z, t_z)/sigma_sz, then repeatedly a predecessor appearance (w, t_w)
+ * of the current one with probability sigma(w, t_w)/sigma(current).  The
+ * draws are arranged by edge: one draw picks an edge into the current
+ * node's candidate appearances with probability (its counted-tail sum) /
+ * (their total), which picks the appearance (with probability sigma(b) /
+ * total) and the edge into it (with probability (tail sum) / sigma(b)) at
+ * once.  Candidates are taken in the order (time, head id, tail id), the
+ * origin first where it is one, and the draw r = floor(word * W / 2^64)
+ * picks the first whose running total exceeds r.
+ * rec gets the pair's record (as orc_pair); nodeV[v] the walk's internal
+ * visits of v (v not s, z), edgeV[e] its uses of edge e (original ids).
+ * Returns 0; -1 on bad arguments; -2 if a step's total disagrees with the
+ * count it stands for or saturates (no walk then; the record is kept).
+ */
+int orc_trk_path(const orc_graph *g, int32_t opt, int32_t t0, int32_t t1, int32_t s, int32_t z, uint64_t seed,
+                 uint64_t stream, uint64_t i, orc_record *rec, uint64_t *nodeV, uint64_t *edgeV) {
+    int32_t n = g->n;
+    int rc = orc_pair(g, opt, t0, t1, s, z, 0, rec, NULL, NULL);
+    if (rc) return rc;
+    /* the walk needs sigma only: the record's saturation flag is sigma's
+       (orc_pair also flags an fm visit count N(v) that saturates) */
+    rec->flags &= ~REC_OVERFLOW;
+    if (rec->reachable && rec->sigma == U64MAX) rec->flags |= REC_OVERFLOW;
+    if (nodeV) memset(nodeV, 0, sizeof(uint64_t) * (size_t)n);
+    if (edgeV) memset(edgeV, 0, sizeof(uint64_t) * (size_t)g->m);
+    if (!rec->reachable || (rec->flags & REC_OVERFLOW)) return 0;
+    pws w;
+    memset(&w, 0, sizeof(w));
+    pws_build(g, t0, t1, &w);
+    forward_explicit(&w, s);
+    earliest(&w, n);
+    forward_pfm(&w, s);
+    /* terminal appearances of z */
+    uint8_t *cand_app = (uint8_t *)calloc((size_t)(w.A ? w.A : 1), 1);
+    if (opt == OPT_SH) {
+        for (int64_t a = w.app_off[z]; a < w.app_off[z + 1]; ++a)
+            if (w.reach[a] && w.dist[a] == rec->hops) cand_app[a] = 1;
+    } else {
+        cand_app[w.first_app[z]] = 1;
+    }
+    trk_cand *cs = (trk_cand *)malloc(sizeof(trk_cand) * (size_t)(w.W + 1));
+    uint64_t expect = rec->sigma;
+    int origin = 0;
+    int ret = 0;
+    for (uint64_t j = 0;; ++j) {
+        /* candidates: edges into the candidate appearances, weighted by their
+           counted-tail sums; the origin (weight 1) when it is one */
+        int64_t nc = 0;
+        if (origin) { cs[nc].k = -1; cs[nc].w = 1; nc++; }
+        for (int64_t k = 0; k < w.W; ++k) {
+            if (!cand_app[w.head[k]]) continue;
+            uint64_t ts = tail_sum_explicit(&w, opt, s, k);
+            if (ts) { cs[nc].k = k; cs[nc].w = ts; nc++; }
+        }
+        g_trk_w = &w; /* not re-entrant: walks are drawn one at a time */
+        qsort(cs, (size_t)nc, sizeof(trk_cand), cmp_trk);
+        uint64_t W = 0;
+        for (int64_t c = 0; c < nc; ++c) W = sadd(W, cs[c].w);
+        if (W != expect || W == 0 || W == U64MAX) { ret = -2; break; }
+        uint64_t r = mulhi(orc_trk_word(seed, stream, i, j), W);
+        uint64_t run = 0;
+        int64_t pick = -1;
+        for (int64_t c = 0; c < nc; ++c) {
+            run += cs[c].w;
+            if (run > r) { pick = c; break; }
+        }
+        int64_t k = cs[pick].k;
+        if (k < 0) break; /* the origin: the walk is complete */
+        int32_t x = w.wu[k], tk = w.wt[k];
+        int64_t hk = w.head[k];
+        if (x != s && x != z && nodeV) nodeV[x]++;
+        if (edgeV) edgeV[w.wid[k]]++;
+        expect = cs[pick].w;
+        if (x == s && opt != OPT_FM) break; /* the origin */
+        /* next candidates: the appearances of x counted as tails of k */
+        memset(cand_app, 0, (size_t)(w.A ? w.A : 1));
+        for (int64_t b = w.app_off[x]; b < w.app_off[x + 1] && w.app_time[b] < tk; ++b)
+            if (arc_counted(&w, opt, s, b, hk)) cand_app[b] = 1;
+        origin = (x == s) && arc_counted(&w, opt, s, -1, hk);
+    }
+    if (ret && nodeV) memset(nodeV, 0, sizeof(uint64_t) * (size_t)n);
+    if (ret && edgeV) memset(edgeV, 0, sizeof(uint64_t) * (size_t)g->m);
+    free(cs);
+    free(cand_app);
+    pws_free(&w);
+    return ret;
+}

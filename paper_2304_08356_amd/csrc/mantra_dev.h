@@ -26,7 +26,9 @@ constexpr u64 kUMax = ~0ull;
 
 enum { OPT_SH = 0, OPT_FM = 1, OPT_SFM = 2, OPT_PFM = 3 };
 enum { STREAM_PAIR = 0, STREAM_BOOT = 1, STREAM_RADE = 2, STREAM_SRC = 3, STREAMS_PER_GRAPH = 4 };
-enum { MODE_PAIRS = 0, MODE_DISTANCES = 1 };
+enum { MODE_PAIRS = 0, MODE_DISTANCES = 1, MODE_TRK = 2 };
+// path draws of the TRK estimator: stream kStreamTrk + (the pair's stream)
+constexpr u64 kStreamTrk = 1ull << 20;
 
 // record flags (public ones mirror mantra.h)
 enum : u32 {
@@ -62,7 +64,8 @@ struct DevReq {
     int64_t per_graph;   // graph = -1: index i is pair i % per_graph of graph i / per_graph
     double *Bsum, *Wsum, *Rsum, *Esum; // accumulators (device), may be null
     u64 *rstat;          // per-request counters: overflow, reachable, hops limit, window edges, arcs; may be null
-    int32_t mode;        // MODE_PAIRS, or MODE_DISTANCES: slot i is a source drawn from STREAM_SRC, swept
+    int32_t mode;        // MODE_PAIRS (f = N/sigma), MODE_TRK (f = visits of one sampled optimal path), or
+                         // MODE_DISTANCES: slot i is a source drawn from STREAM_SRC, swept
                          // to the window's end without a target; its distances go to hist
     int32_t hist_len;    // MODE_DISTANCES: bins of hist (the last one takes every larger distance)
     u64 *hist;           // [hist_len] sampled (source, node) pairs by distance; [hist_len]: largest distance

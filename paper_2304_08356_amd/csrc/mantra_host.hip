@@ -74,6 +74,8 @@ static int pick_device(int *dev) {
     return MANTRA_OK;
 }
 
+// an input edge with its graph's local INPUT node ids (the stream is ordered
+// by them, so that the order of a tick's edges is a function of the input)
 struct EdgeRec { int32_t g, t, v, u; int64_t idx; };
 
 static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge_off,
@@ -142,8 +144,7 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
             if (u == v) return fail(MANTRA_E_INVALID, "edge %lld: self-loop on %d", (long long)i, u);
             if (tt < 0 || tt == INT32_MAX)
                 return fail(MANTRA_E_INVALID, "edge %lld: time %d outside [0, 2^31-2]", (long long)i, tt);
-            int32_t b = g->seg_noff[gi];
-            E[(size_t)i] = EdgeRec{gi, tt, g->perm[(size_t)(b + v)] - b, g->perm[(size_t)(b + u)] - b, i};
+            E[(size_t)i] = EdgeRec{gi, tt, v, u, i};
         }
     }
     std::sort(E.begin(), E.end(), [](const EdgeRec &a, const EdgeRec &b) {
@@ -163,7 +164,10 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
         bool dup = i > 0 && E[i - 1].g == e.g && E[i - 1].t == e.t && E[i - 1].v == e.v && E[i - 1].u == e.u;
         if (!dup) {
             ++k;
-            U.push_back(e.u); V.push_back(e.v); T.push_back(e.t);
+            const int32_t b = g->seg_noff[e.g];
+            U.push_back(g->perm[(size_t)(b + e.u)] - b);
+            V.push_back(g->perm[(size_t)(b + e.v)] - b);
+            T.push_back(e.t);
             g->seg_eoff[e.g + 1] = k + 1;
         } else {
             g->ndup++;
@@ -368,18 +372,20 @@ void RoundGraph::release() {
 
 // the kernels of one launch: clear the counters, order the slots (longest
 // estimated window first), sweep; with rg, also the request's reduction
-static hipError_t launch_sweep(const LaunchArgs &a, bool sources, int ns, size_t lb, hipStream_t st) {
-    return sources ? mantra_launch_sweep_sources(&a, ns, lb, st) : mantra_launch_sweep(&a, ns, lb, st);
+static hipError_t launch_sweep(const LaunchArgs &a, int mode, int ns, size_t lb, hipStream_t st) {
+    if (mode == MODE_DISTANCES) return mantra_launch_sweep_sources(&a, ns, lb, st);
+    if (mode == MODE_TRK) return mantra_launch_sweep_trk(&a, ns, lb, st);
+    return mantra_launch_sweep(&a, ns, lb, st);
 }
 
-static int issue_kernels(mantra_graph *g, LaunchArgs &a, int ns, size_t lb, const RoundGraph *rg, bool sources) {
+static int issue_kernels(mantra_graph *g, LaunchArgs &a, int ns, size_t lb, const RoundGraph *rg, int mode) {
     HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, g->dstats, g->st));
     if (g->order_mode == MANTRA_ORDER_LONGEST_FIRST && a.npairs > ns) {
         HIPCHK(mantra_launch_order(&a, g->dbucket, g->dhist, g->dorder, g->st));
         a.pq = g->dorder;
     }
     if (!rg) HIPCHK(hipEventRecord(g->ev0, g->st));
-    HIPCHK(launch_sweep(a, sources, ns, lb, g->st));
+    HIPCHK(launch_sweep(a, mode, ns, lb, g->st));
     if (!rg) HIPCHK(hipEventRecord(g->ev1, g->st));
     if (rg) {
         ReduceArgs ra;
@@ -447,7 +453,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
             a.qbase = q;
             a.npairs = q + 1;
             HIPCHK(hipMemsetAsync(g->dwork, 0, sizeof(u32), g->st));
-            HIPCHK(launch_sweep(a, sp.sources, 1, lb, g->st));
+            HIPCHK(launch_sweep(a, sp.mode, 1, lb, g->st));
             o.launches += 1;
         }
         HIPCHK(hipEventRecord(g->ev1, g->st));
@@ -463,7 +469,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
             rg->ns = ns;
             memcpy(&rg->args, &a, sizeof a);
             HIPCHK(hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal));
-            int crc = issue_kernels(g, a, ns, lb, rg, sp.sources);
+            int crc = issue_kernels(g, a, ns, lb, rg, sp.mode);
             hipGraph_t gr = nullptr;
             hipError_t e = hipStreamEndCapture(g->st, &gr);
             if (crc) { if (gr) hipGraphDestroy(gr); return crc; }
@@ -477,7 +483,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         o.launches += 1;
         o.reduced = true;
     } else {
-        if ((rc = issue_kernels(g, a, ns, lb, nullptr, sp.sources))) return rc;
+        if ((rc = issue_kernels(g, a, ns, lb, nullptr, sp.mode))) return rc;
         o.launches += 1;
     }
     int32_t nretry = 0;
@@ -510,7 +516,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         a.qbase = 0;
         a.pq = dq;
         HIPCHK(hipEventRecord(g->ev0, g->st));
-        HIPCHK(launch_sweep(a, sp.sources, ns2, lb, g->st));
+        HIPCHK(launch_sweep(a, sp.mode, ns2, lb, g->st));
         HIPCHK(hipEventRecord(g->ev1, g->st));
         HIPCHK(hipStreamSynchronize(g->st));
         HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
@@ -626,6 +632,7 @@ static DevReq make_req(const mantra_request &rq, int stream, int64_t base, int64
     d.qoff = qoff;
     d.count = count;
     d.per_graph = count;
+    d.mode = (rq.flags & MANTRA_F_TRK) ? MODE_TRK : MODE_PAIRS;
     if (acc) {
         d.Bsum = acc->B;
         d.Wsum = acc->W;
@@ -843,6 +850,7 @@ static int run_request(mantra_graph *g, const mantra_request &rq, mantra_result 
         const int64_t cnt = req_pending(q);
         sp.reqs.push_back(req_slice(q, cnt, 0));
         sp.npairs = cnt;
+        sp.mode = sp.reqs[0].mode;
         // progressive rounds: one graph, captured for the largest round
         RoundGraph *rg = nullptr;
         if (g->graph_rounds && !g->per_pair && q.phase == ReqRun::ROUND && q.rq.fixed_r <= 0) {
@@ -1047,9 +1055,14 @@ int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launche
     return MANTRA_OK;
 }
 
-int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r,
-                       const int32_t *graph, const int32_t *s, const int32_t *z, mantra_pair_record *out,
-                       double *node_f, double *edge_f) {
+}  // extern "C"
+
+// explicit pairs (s[q], z[q]) in one launch: records and optional dense f;
+// mode MODE_PAIRS (f = N / sigma) or MODE_TRK (f = visits of the walk drawn
+// with seed)
+static int explicit_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r, const int32_t *graph,
+                          const int32_t *s, const int32_t *z, uint64_t seed, int mode, mantra_pair_record *out,
+                          double *node_f, double *edge_f) {
     if (!g) return fail(MANTRA_E_INVALID, "graph is NULL");
     if (r < 0 || (r > 0 && (!s || !z || !out))) return fail(MANTRA_E_INVALID, "bad pair arrays");
     if (opt < MANTRA_SH || opt > MANTRA_PFM) return fail(MANTRA_E_INVALID, "unknown optimality %d", (int)opt);
@@ -1096,10 +1109,12 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
     LaunchSpec sp;
     mantra_request rq;
     memset(&rq, 0, sizeof rq);
-    rq.opt = opt; rq.t0 = t0; rq.t1 = t1;
+    rq.opt = opt; rq.t0 = t0; rq.t1 = t1; rq.seed = seed;
+    if (mode == MODE_TRK) rq.flags |= MANTRA_F_TRK;
     norm_window(rq);
     sp.reqs.push_back(make_req(rq, STREAM_PAIR, 0, 0, r, nullptr, 0));
     sp.npairs = r;
+    sp.mode = mode;
     sp.dpg = dpg; sp.dps = dps; sp.dpz = dpz; sp.drec = drec; sp.dnode_f = dnf; sp.dedge_f = def;
     SweepOut so;
     rc = run_sweep(g, sp, so);
@@ -1127,6 +1142,20 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
     }
     cleanup();
     return rc;
+}
+
+extern "C" {
+
+int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r,
+                       const int32_t *graph, const int32_t *s, const int32_t *z, mantra_pair_record *out,
+                       double *node_f, double *edge_f) {
+    return explicit_pairs(g, opt, t0, t1, r, graph, s, z, 0, MODE_PAIRS, out, node_f, edge_f);
+}
+
+int mantra_sample_paths(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r, const int32_t *graph,
+                        const int32_t *s, const int32_t *z, uint64_t seed, mantra_pair_record *out, double *node_f,
+                        double *edge_f) {
+    return explicit_pairs(g, opt, t0, t1, r, graph, s, z, seed, MODE_TRK, out, node_f, edge_f);
 }
 
 int mantra_run(mantra_graph *g, const mantra_request *req, mantra_result *out) {
@@ -1177,7 +1206,7 @@ int mantra_distances(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, in
     d.rstat = drs;
     sp.reqs.push_back(d);
     sp.npairs = r;
-    sp.sources = true;
+    sp.mode = MODE_DISTANCES;
     SweepOut so;
     std::vector<u64> h((size_t)nb + 1);
     u64 rs[RS_N];

@@ -26,6 +26,7 @@
 extern "C" {
 hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
 hipError_t mantra_launch_sweep_sources(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
+hipError_t mantra_launch_sweep_trk(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
 hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st);
 hipError_t mantra_launch_fill(mantra::u64 *p, mantra::u64 val, int64_t n, hipStream_t st);
 hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u64 *stats, hipStream_t st);
@@ -150,7 +151,7 @@ struct LaunchSpec {
     const int32_t *dpg = nullptr, *dps = nullptr, *dpz = nullptr;
     void *drec = nullptr;
     double *dnode_f = nullptr, *dedge_f = nullptr;
-    bool sources = false;  // slots are single sources (the distance sweep)
+    int mode = MODE_PAIRS;  // the kernel: MODE_PAIRS, MODE_TRK (pairs) or MODE_DISTANCES (sources)
 };
 
 // what one call of run_sweep did: launch statistics (indices as in

@@ -100,28 +100,33 @@ static void serve_loop(mantra_graph *g) {
                 t->run.rc = req_begin(g, t->run);
                 if (t->run.rc) { t->run.err = g_err; finished.push_back(t); }
             }
-            // one launch over a slice of every active request
-            LaunchSpec sp;
-            std::vector<std::shared_ptr<Ticket>> in_launch;
+            // one launch over a slice of every active request (two when both
+            // estimators are active: each has a kernel of its own)
+            LaunchSpec sps[2];
+            std::vector<std::shared_ptr<Ticket>> ins[2];
             const int64_t quota = slice_quota(g, act.size());
             for (auto &t : act) {
                 if (t->run.rc || t->run.phase == ReqRun::DONE) continue;
                 const int64_t cnt = std::min(req_pending(t->run), quota);
                 if (cnt <= 0) continue;
-                sp.reqs.push_back(req_slice(t->run, cnt, sp.npairs));
-                sp.npairs += cnt;
-                in_launch.push_back(t);
+                const int mi = (t->run.rq.flags & MANTRA_F_TRK) ? 1 : 0;
+                sps[mi].reqs.push_back(req_slice(t->run, cnt, sps[mi].npairs));
+                sps[mi].npairs += cnt;
+                ins[mi].push_back(t);
             }
-            if (sp.npairs > 0) {
+            for (int mi = 0; mi < 2; ++mi) {
+                LaunchSpec &sp = sps[mi];
+                if (sp.npairs <= 0) continue;
+                sp.mode = mi ? MODE_TRK : MODE_PAIRS;
                 SweepOut o;
                 int rc = run_sweep(g, sp, o);
                 const std::string launch_err = rc ? g_err : std::string();
                 if (S.trace)
                     fprintf(stderr, "serve: launch of %lld pairs from %zu requests, %.1f ms (%d launches, %llu pairs "
                                     "re-run for arc room), rc %d, %zu active\n",
-                            (long long)sp.npairs, in_launch.size(), o.ms, o.launches, (unsigned long long)o.st[5], rc,
+                            (long long)sp.npairs, ins[mi].size(), o.ms, o.launches, (unsigned long long)o.st[5], rc,
                             act.size());
-                for (auto &t : in_launch) {
+                for (auto &t : ins[mi]) {
                     t->run.R.gpu_ms += o.ms;
                     if (rc) { t->run.rc = rc; t->run.err = launch_err; continue; }
                     t->run.rc = req_advance(g, t->run);

@@ -182,6 +182,8 @@ struct Pair {
     u32 rtag;              // reverse state words (the same memory) carry this one
     bool level;            // sh / sfm: hop levels matter
     bool single;           // distances: one source, every node its target (z = -1, no arcs)
+    u64 trk_key;           // TRK: key of the pair's path-draw stream
+    u64 trk_i;             // TRK: the pair's index in it
 };
 
 struct Slab {
@@ -1077,6 +1079,8 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
     P.qout = q;
     P.lam = 0;
     const int64_t i = q - R.qoff + R.base;
+    u64 pstream = (u64)R.stream;
+    P.trk_i = (u64)i;
     if (a.ps) {
         P.g = a.pg ? a.pg[q] : 0;
         P.s = a.ps[q];
@@ -1088,6 +1092,8 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
         int32_t noff = a.g.seg_noff[P.g];
         int32_t ng = a.g.seg_noff[P.g + 1] - noff;
         u64 st = (u64)R.stream + (u64)STREAMS_PER_GRAPH * (u64)P.g;
+        pstream = st;
+        P.trk_i = (u64)idx;
         u64 s = __umul64hi(rng_word(R.seed, st, (u64)idx, 0), (u64)ng);
         u64 zp = __umul64hi(rng_word(R.seed, st, (u64)idx, 1), (u64)(ng - 1));
         // pairs are drawn over input ids, then mapped to internal ids
@@ -1101,6 +1107,7 @@ __device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
     P.ehi = a.g.seg_eoff[P.g + 1];
     P.level = (P.opt == OPT_SH || P.opt == OPT_SFM);
     P.single = SINGLE;
+    P.trk_key = sm_mix(R.seed + (kStreamTrk + pstream + 1ull) * 0x9E3779B97F4A7C15ull);
 }
 
 // Distances from a single source after its forward sweep: every node the
@@ -1149,10 +1156,130 @@ __device__ void distance_hist(const Pair &P, const Slab &S, const Hub &H, u32 *l
     __syncthreads();
 }
 
-// SINGLE: every slot is a single source (distances); a kernel of its own, so
-// that the pair sweep keeps its register allocation
-template <bool SINGLE>
+// The TRK estimator (appendix on other estimators): one optimal walk of the
+// pair, drawn backwards from z with the probability 1/sigma_sz, and
+// f(v) = the number of its internal visits of v (v not s or z), f(e) = its
+// uses of e.  Each step draws one recorded arc, with the probability of its
+// tail count among the candidates:
+//  - first step: the arcs into z's terminal appearances (sh: those at z's
+//    fewest hops; fm, sfm, pfm: those at z's first arrival);
+//  - then, after an arc with tail x at level L and time t: the arcs into the
+//    appearances of x before t (sh, sfm: at level L; pfm: x's first
+//    arrival; fm: all of them), and for fm at x = s the origin (weight 1,
+//    first); for sh, sfm and pfm the walk ends at x = s.
+// An arc's tail count is the number of optimal prefixes of its tail node
+// that it extends, so the first step picks (z, t_z) with probability
+// sigma(z, t_z) / sigma_sz and each later step picks the predecessor
+// appearance and its arc together, as the paper's backward sampler does.
+// The draw of step j is r = floor(w * W / 2^64) with w the SplitMix64 output
+// (pair index * 2^16 + j + 1) of the pair's path stream and W the candidates'
+// total; the arc taken is the first, in arc order (time, then input head and
+// tail ids), whose running total exceeds r.  Each step's total must equal
+// the count it stands for (sigma_sz first, then the tail count of the arc
+// taken); returns false where it does not.
+__device__ bool trk_walk(const LaunchArgs &a, const Pair &P, const Slab &S, int64_t narcs, u32 zh, int32_t t_arr,
+                         u64 sigma, RevCtx &X) {
+    const int l = lane_id();
+    const DevReq *R = P.req;
+    int32_t node = P.z;
+    u32 lvl = zh;
+    int32_t tmax = INT32_MAX;
+    int64_t hi = narcs;
+    bool term = true;
+    u64 expect = sigma;
+    for (u32 step = 0;; ++step) {
+        const bool origin = !term && node == P.s;  // fm only: the walk may start here
+        // pass 1: total weight of the candidates
+        u64 part = 0;
+        for (int64_t b = 0; b < hi; b += kWave) {
+            const int64_t i = b + l;
+            if (i >= hi) continue;
+            const u64 mm = S.arcm[i];
+            if ((int32_t)(u32)mm != node) continue;
+            const int32_t ti = (int32_t)(mm >> 32);
+            const u32 hl = (u32)(S.arcx[3 * i + 2] >> 16) & 0xFFFFu;
+            bool c;
+            if (term) c = P.opt == OPT_SH ? hl == lvl : ti == t_arr;
+            else c = ti < tmax && (!P.level || hl == lvl);
+            if (c) part = sat_add(part, S.arcx[3 * i + 1]);
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) part = sat_add(part, shfl64(part, l ^ o));
+        u64 W = uni64(part);
+        if (origin) W = sat_add(W, 1ull);
+        if (W != expect || W == 0 || W == kUMax) return false;
+        const u64 w = sm_mix(P.trk_key + ((P.trk_i << 16) + (u64)step + 1ull) * 0x9E3779B97F4A7C15ull);
+        const u64 r = __umul64hi(w, W);
+        if (origin && r < 1ull) return true;  // the walk starts at the origin
+        // pass 2: the first candidate whose running total exceeds r
+        u64 carry = origin ? 1ull : 0ull;
+        int64_t pick = -1;
+        for (int64_t b = 0; b < hi && pick < 0; b += kWave) {
+            const int64_t i = b + l;
+            u64 wt = 0;
+            if (i < hi) {
+                const u64 mm = S.arcm[i];
+                if ((int32_t)(u32)mm == node) {
+                    const int32_t ti = (int32_t)(mm >> 32);
+                    const u32 hl = (u32)(S.arcx[3 * i + 2] >> 16) & 0xFFFFu;
+                    bool c;
+                    if (term) c = P.opt == OPT_SH ? hl == lvl : ti == t_arr;
+                    else c = ti < tmax && (!P.level || hl == lvl);
+                    if (c) wt = S.arcx[3 * i + 1];
+                }
+            }
+            // inclusive scan of the weights over the wave (no wrap: the
+            // total is below 2^64 - 1)
+            u64 x = wt;
+            for (int o = 1; o < kWave; o <<= 1) {
+                const u32 lo = (u32)__shfl_up((int)(u32)x, o), hi32 = (u32)__shfl_up((int)(u32)(x >> 32), o);
+                const u64 y = ((u64)hi32 << 32) | lo;
+                if (l >= o) x += y;
+            }
+            const u64 hit = ballot(wt != 0 && carry + x > r);
+            if (hit) pick = b + (__ffsll((long long)hit) - 1);
+            else carry += rl64(x, kWave - 1);
+        }
+        if (pick < 0) return false;
+        const u64 x0 = S.arcx[3 * pick];
+        const int32_t k = (int32_t)(u32)x0;           // stream index of the edge
+        const int32_t tail = (int32_t)(x0 >> 32);
+        const u32 tl = (u32)S.arcx[3 * pick + 2] & 0xFFFFu;
+        const int32_t tp = (int32_t)(S.arcm[pick] >> 32);
+        const u64 tcp = S.arcx[3 * pick + 1];
+        // visit counts in the slab's N (zero between pairs) and the list of
+        // the distinct internal nodes, as the reverse sweep leaves them
+        if (tail != P.s && tail != P.z) {
+            const u64 old = S.N[tail];  // every lane reads the same word
+            if (l == 0) {
+                S.N[tail] = old + 1ull;
+                if (old == 0ull) S.touched[X.touched_n] = tail;
+            }
+            if (old == 0ull) X.touched_n += 1;
+        }
+        if (l == 0) {
+            if (R->Esum) atomicAdd(&R->Esum[k], 1.0);
+            if (a.edge_f) a.edge_f[P.qout * a.g.m + (int64_t)(u32)k] += 1.0;
+        }
+        __syncthreads();  // the visit count is read again if the walk comes back
+        X.edges_n += 1;
+        if (tail == P.s && P.opt != OPT_FM) return true;  // the origin
+        node = tail;
+        lvl = tl;
+        tmax = tp;
+        hi = pick;
+        term = false;
+        expect = tcp;
+    }
+}
+
+// MODE_PAIRS: pairs, f = N / sigma from the reverse sweep; MODE_DISTANCES:
+// every slot is a single source; MODE_TRK: pairs, f = visits of one sampled
+// optimal walk.  Each mode is a kernel of its own, so that the pair sweep
+// keeps its register allocation.
+template <int MODE>
 __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
+    constexpr bool SINGLE = MODE == MODE_DISTANCES;
+    constexpr bool TRK = MODE == MODE_TRK;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int l = lane_id();
     const int64_t slab = blockIdx.x;
@@ -1248,7 +1375,11 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
         bool do_rev = reach && !(flags & REC_OVERFLOW);
         RevCtx X;
         X.sigma = sigma; X.dsh = fo.zh; X.touched_n = 0; X.edges_n = 0; X.ovf = false; X.alive_all = false;
-        if (do_rev) {
+        if (TRK && do_rev) {
+            // the walk checks the forward's counts at every step: a failure
+            // is a broken invariant
+            if (!trk_walk(a, P, S, fo.arcs, fo.zh, fo.t_arr, sigma, X)) flags |= REC_SELFCHECK;
+        } else if (do_rev) {
             reverse(a, P, S, bm, bmw, tab.r, stamp, fo.arcs, X);
             __syncthreads();
             // flow conservation at the origin: B(origin) must equal sigma
@@ -1273,7 +1404,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
             int32_t v = S.touched[i];
             u64 nv = atomicExch((unsigned long long *)&S.N[v], 0ull);
             if (!accum) continue;
-            double f = (double)nv / (double)sigma;
+            double f = TRK ? (double)nv : (double)nv / (double)sigma;
             int64_t gv = (int64_t)P.noff + v;
             if (R->Bsum) atomicAdd(&R->Bsum[gv], f);
             if (R->Wsum) { double f2 = f * f; atomicAdd(&R->Wsum[gv], f2); }
@@ -1479,12 +1610,17 @@ __global__ void k_fill_u64(u64 *p, u64 val, int64_t n) {
 
 extern "C" {
 hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(mantra::k_sweep<false>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_PAIRS>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
     return hipGetLastError();
 }
 // the single-source (distance) form of the sweep
 hipError_t mantra_launch_sweep_sources(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(mantra::k_sweep<true>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_DISTANCES>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    return hipGetLastError();
+}
+// the sweep with the TRK estimator (one sampled optimal walk per pair)
+hipError_t mantra_launch_sweep_trk(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_TRK>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
     return hipGetLastError();
 }
 hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st) {
@@ -1522,7 +1658,9 @@ size_t mantra_tab_lds_bytes(void) { return sizeof(mantra::TabLds); }
 // resident sweep workgroups per CU for a given dynamic LDS size
 int mantra_sweep_occupancy(size_t lds_bytes) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mantra::k_sweep<false>, 64, lds_bytes) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mantra::k_sweep<mantra::MODE_PAIRS>, 64, lds_bytes) !=
+        hipSuccess)
+        return 0;
     return nb;
 }
 }
