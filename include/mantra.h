@@ -122,6 +122,18 @@ int mantra_sample_paths(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1,
                         const int32_t *graph, const int32_t *s, const int32_t *z, uint64_t seed,
                         mantra_pair_record *out, double *node_f, double *edge_f);
 
+/* The RTB estimator's f for r explicit sources s[q] (node ids local to
+ * graph[q], or graph 0 when graph is NULL): node_f[q*n + v] =
+ * (1/(n-1)) sum_{z != s} sigma_sz(v)/sigma_sz and edge_f[q*m + e] likewise,
+ * computed in double precision from one forward sweep of s to the end of
+ * [t0, t1] and one reverse sweep over all targets.  out[q]: reachable = 1 if
+ * s reaches any node, sigma = the number of nodes it reaches, t_arr = hops =
+ * -1; MANTRA_REC_OVERFLOW if a count on the way saturated (f rows are then
+ * zero). */
+int mantra_source_dependencies(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r,
+                               const int32_t *graph, const int32_t *s, mantra_pair_record *out,
+                               double *node_f, double *edge_f);
+
 /* One estimation request. */
 typedef struct {
     mantra_opt opt;
@@ -145,6 +157,12 @@ typedef struct {
                                the ob estimator's N(v)/sigma_sz.  Unbiased for
                                the same betweenness; f in {0, 1} except for fm
                                walks, which may revisit a node */
+#define MANTRA_F_RTB 4u     /* the RTB estimator (appendix on other estimators):
+                               each sample is a source s (uniform over the
+                               nodes), swept to the window's end, with
+                               f(v) = (1/(n-1)) sum over targets z != s of
+                               sigma_sz(v)/sigma_sz and f(e) likewise; the
+                               sample sizes count sources */
 
 typedef struct {
     int32_t status;        /* mantra_status of the request */

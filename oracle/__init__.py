@@ -22,6 +22,12 @@ Parity status per function (the tests that pin each one are named there):
 * ``mantra.estimate`` (Algorithm 1): pinned through its parts and by the
   statistical guarantee of Theorem 5; fm has no guarantee ("parity unpinned"
   beyond its counts).
+* ``distances`` (Algorithm 2): per-source distances pinned by brute force,
+  the closing formulas by closed forms and the all-sources definitions.
+* ``trk`` (the TRK estimator's path sampler): pinned by brute-force optimal
+  walks, the 1/sigma distribution of the drawn walks and unbiasedness.
+* ``rtb`` (the RTB estimator): pinned by brute force, the line's closed form
+  and the mean over all sources.
 """
 from __future__ import annotations
 

@@ -798,3 +798,69 @@ int orc_trk_path(const orc_graph *g, int32_t opt, int32_t t0, int32_t t1, int32_
     pws_free(&w);
     return ret;
 }
+
+/* ------------------------------------------------------------------------ */
+/* the RTB estimator (appendix on other estimators)                          */
+
+/*
+ * One source: nodeF[v] = (1/(n-1)) * sum over targets z != s of f(v|s,z)
+ * (orc_pair's N(v)/sigma_sz, unreachable targets adding 0), edgeF[e] (original
+ * edge ids) likewise; the sums over targets are double-double.  *reached
+ * gets the number of targets s reaches.  Returns 0; 1 if some target's
+ * counts saturated (the source is void: rows zero); -1 on bad arguments.
+ */
+int orc_rtb(const orc_graph *g, int32_t opt, int32_t t0, int32_t t1, int32_t s, int32_t mode, double *nodeF,
+            double *edgeF, int64_t *reached, int32_t nthreads) {
+    int32_t n = g->n;
+    int64_t m = g->m;
+    if (s < 0 || s >= n || opt < 0 || opt > 3) return -1;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    double *hi = (double *)calloc((size_t)nt * (size_t)(n + m), sizeof(double));
+    double *lo = (double *)calloc((size_t)nt * (size_t)(n + m), sizeof(double));
+    int64_t nreach = 0, nsat = 0;
+#pragma omp parallel num_threads(nt) reduction(+ : nreach, nsat)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *h = hi + (size_t)tid * (size_t)(n + m), *l = lo + (size_t)tid * (size_t)(n + m);
+        uint64_t *nN = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+        uint64_t *eN = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(m ? m : 1));
+#pragma omp for schedule(static)
+        for (int32_t z = 0; z < n; ++z) {
+            if (z == s) continue;
+            orc_record rec;
+            orc_pair(g, opt, t0, t1, s, z, mode, &rec, nN, eN);
+            if (!rec.reachable) continue;
+            nreach++;
+            if (rec.flags & REC_OVERFLOW) { nsat++; continue; }
+            double sg = (double)rec.sigma;
+            for (int32_t v = 0; v < n; ++v)
+                if (nN[v]) dd_add(&h[v], &l[v], (double)nN[v] / sg);
+            for (int64_t e = 0; e < m; ++e)
+                if (eN[e]) dd_add(&h[n + e], &l[n + e], (double)eN[e] / sg);
+        }
+        free(nN);
+        free(eN);
+    }
+    /* threads' sums in thread order, then the 1/(n-1) */
+    for (int64_t x = 0; x < n + m; ++x) {
+        double H = 0, L = 0;
+        for (int t = 0; t < nt; ++t) {
+            dd_add(&H, &L, hi[(size_t)t * (size_t)(n + m) + (size_t)x]);
+            dd_add(&H, &L, lo[(size_t)t * (size_t)(n + m) + (size_t)x]);
+        }
+        double f = (H + L) / (double)(n - 1);
+        if (nsat) f = 0.0;
+        if (x < n) { if (nodeF) nodeF[x] = f; }
+        else if (edgeF) edgeF[x - n] = f;
+    }
+    free(hi);
+    free(lo);
+    if (reached) *reached = nreach;
+    return nsat ? 1 : 0;
+}

@@ -11,7 +11,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (OPT, F_EDGE_BC, F_TRK, MantraError, PairRecord, Request, Result,  # noqa: F401
+from ._lib import (OPT, F_EDGE_BC, F_RTB, F_TRK, MantraError, PairRecord, Request, Result,  # noqa: F401
                    REC_OVERFLOW, REC_HOPS_LIMIT, RES_NO_GUARANTEE, RES_STOP_OMEGA, RES_STOP_XI)
 
 REC_DTYPE = np.dtype([("reachable", np.int32), ("t_arr", np.int32), ("hops", np.int32),
@@ -145,22 +145,36 @@ class Graph:
                                                  int(seed), _p(rec), _p(nf), _p(ef)))
         return rec, nf, ef
 
-    def _request(self, opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges, trk=False):
+    def source_dependencies(self, opt, s, t0=0, t1=T_MAX, graph=None, node_f=True, edge_f=True):
+        """The RTB estimator's f of explicit sources: records, and per source
+        f(v|s) per node and f(e|s) per input edge."""
+        s = np.ascontiguousarray(s, dtype=np.int32)
+        r = int(s.shape[0])
+        g = None if graph is None else np.ascontiguousarray(graph, dtype=np.int32)
+        rec = np.zeros(r, dtype=REC_DTYPE)
+        nf = np.zeros((r, self.n), dtype=np.float64) if node_f else None
+        ef = np.zeros((r, self.m_input), dtype=np.float64) if edge_f else None
+        _lib.check(_lib._lib.mantra_source_dependencies(self._h, _opt(opt), int(t0), int(t1), r, _p(g), _p(s),
+                                                        _p(rec), _p(nf), _p(ef)))
+        return rec, nf, ef
+
+    def _request(self, opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges, trk=False, rtb=False):
         node_bc = np.zeros(self.n, dtype=np.float64)
         edge_bc = np.zeros(self.m_input, dtype=np.float64) if edges else None
-        flags = (F_EDGE_BC if edges else 0) | (F_TRK if trk else 0)
+        flags = (F_EDGE_BC if edges else 0) | (F_TRK if trk else 0) | (F_RTB if rtb else 0)
         rq = Request(opt=_opt(opt), t0=int(t0), t1=int(t1), eps=float(eps), delta=float(delta),
                      seed=int(seed), c=int(c), s1=int(s1), max_samples=int(max_samples), fixed_r=int(fixed_r),
                      flags=flags, node_bc=_p(node_bc), edge_bc=_p(edge_bc))
         return rq, node_bc, edge_bc
 
     def run(self, opt, eps=0.01, delta=0.1, seed=0, c=25, t0=0, t1=T_MAX, s1=0, max_samples=0, fixed_r=0,
-            edges=False, raise_on_error=True, trk=False):
+            edges=False, raise_on_error=True, trk=False, rtb=False):
         """Algorithm 1 (or a fixed sample of ``fixed_r`` pairs), with the ob
-        estimator or (trk=True) the TRK estimator: returns (node_bc, edge_bc
-        or None, result dict)."""
+        estimator, the TRK estimator (trk=True) or the RTB estimator
+        (rtb=True, samples are sources): returns (node_bc, edge_bc or None,
+        result dict)."""
         rq, node_bc, edge_bc = self._request(opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges,
-                                             trk)
+                                             trk, rtb)
         res = Result()
         rc = _lib._lib.mantra_run(self._h, ctypes.byref(rq), ctypes.byref(res))
         if raise_on_error:
@@ -191,9 +205,9 @@ class Graph:
         _lib.check(_lib._lib.mantra_serve_config(self._h, int(mem_budget_bytes), int(max_active)))
 
     def submit(self, opt, eps=0.01, delta=0.1, seed=0, c=25, t0=0, t1=T_MAX, s1=0, max_samples=0, fixed_r=0,
-               edges=False, trk=False):
+               edges=False, trk=False, rtb=False):
         rq, node_bc, edge_bc = self._request(opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges,
-                                             trk)
+                                             trk, rtb)
         tk = ctypes.c_uint64()
         _lib.check(_lib._lib.mantra_submit(self._h, ctypes.byref(rq), ctypes.byref(tk)))
         return Ticket(tk.value, node_bc, edge_bc)

@@ -26,6 +26,7 @@ REC_OVERFLOW = 1
 REC_HOPS_LIMIT = 4
 F_EDGE_BC = 1
 F_TRK = 2
+F_RTB = 4
 RES_NO_GUARANTEE = 1
 RES_STOP_XI = 2
 RES_STOP_OMEGA = 4
@@ -78,6 +79,7 @@ SIGNATURES = {
     "mantra_graph_info": (I32, [P, P, P, P, P, P, P]),
     "mantra_count_pairs": (I32, [P, I32, I32, I32, I64, P, P, P, P, P, P]),
     "mantra_sample_paths": (I32, [P, I32, I32, I32, I64, P, P, P, U64, P, P, P]),
+    "mantra_source_dependencies": (I32, [P, I32, I32, I32, I64, P, P, P, P, P]),
     "mantra_estimate": (I32, [P, I32, F64, F64, U64, P, P]),
     "mantra_run": (I32, [P, P, P]),
     "mantra_distances": (I32, [P, I32, I32, I32, I64, U64, F64, P, I32, P]),

@@ -26,7 +26,7 @@ constexpr u64 kUMax = ~0ull;
 
 enum { OPT_SH = 0, OPT_FM = 1, OPT_SFM = 2, OPT_PFM = 3 };
 enum { STREAM_PAIR = 0, STREAM_BOOT = 1, STREAM_RADE = 2, STREAM_SRC = 3, STREAMS_PER_GRAPH = 4 };
-enum { MODE_PAIRS = 0, MODE_DISTANCES = 1, MODE_TRK = 2 };
+enum { MODE_PAIRS = 0, MODE_DISTANCES = 1, MODE_TRK = 2, MODE_RTB = 3 };
 // path draws of the TRK estimator: stream kStreamTrk + (the pair's stream)
 constexpr u64 kStreamTrk = 1ull << 20;
 
@@ -64,7 +64,8 @@ struct DevReq {
     int64_t per_graph;   // graph = -1: index i is pair i % per_graph of graph i / per_graph
     double *Bsum, *Wsum, *Rsum, *Esum; // accumulators (device), may be null
     u64 *rstat;          // per-request counters: overflow, reachable, hops limit, window edges, arcs; may be null
-    int32_t mode;        // MODE_PAIRS (f = N/sigma), MODE_TRK (f = visits of one sampled optimal path), or
+    int32_t mode;        // MODE_PAIRS (f = N/sigma), MODE_TRK (f = visits of one sampled optimal path),
+                         // MODE_RTB (slot i is a source s, f = mean over targets z of N_z/sigma_sz), or
                          // MODE_DISTANCES: slot i is a source drawn from STREAM_SRC, swept
                          // to the window's end without a target; its distances go to hist
     int32_t hist_len;    // MODE_DISTANCES: bins of hist (the last one takes every larger distance)
@@ -79,6 +80,7 @@ struct DevSlabs {
     int32_t *touched; // [ns][nmax]
     u64 *arcs;        // [ns][cap][4]   per slab: cap x {head | t<<32}, then cap x {k | u<<32, tail count, tl | hl<<16}
     u64 *XS;          // [ns][gmax][2]  big-tick scratch
+    u64 *T;           // [ns][nmax][2]  RTB sources: first arrival of each reached node (allocated for them)
     u32 *hdr;         // [ns][4]        pair serial, tick stamp
     int64_t nmax, cap, gmax;
 };

@@ -340,6 +340,16 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
     return MANTRA_OK;
 }
 
+// the RTB kernel's per-node first arrivals (16 B per node per slab), on first use
+static int pool_need_T(mantra_graph *g, SlabPool &p) {
+    if (p.T || !p.nslabs) return MANTRA_OK;
+    if (dalloc(&p.T, (size_t)p.nslabs * (size_t)p.nmax * 2)) {
+        (void)hipGetLastError();
+        return fail(MANTRA_E_OOM, "RTB state of %d slabs x %lld nodes", p.nslabs, (long long)p.nmax);
+    }
+    return MANTRA_OK;
+}
+
 // arc records (32 B each) per slab: the rest of the pool budget, at most
 // one per edge of the graph
 static int64_t auto_cap(const mantra_graph *g, int nslabs) {
@@ -375,6 +385,7 @@ void RoundGraph::release() {
 static hipError_t launch_sweep(const LaunchArgs &a, int mode, int ns, size_t lb, hipStream_t st) {
     if (mode == MODE_DISTANCES) return mantra_launch_sweep_sources(&a, ns, lb, st);
     if (mode == MODE_TRK) return mantra_launch_sweep_trk(&a, ns, lb, st);
+    if (mode == MODE_RTB) return mantra_launch_sweep_rtb(&a, ns, lb, st);
     return mantra_launch_sweep(&a, ns, lb, st);
 }
 
@@ -414,6 +425,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     int64_t cap = auto_cap(g, auto_slabs(g));
     int rc = pool_ensure(g, g->pool, std::max(ns, g->pool.nslabs), std::max(cap, g->pool.cap));
     if (rc) return rc;
+    if (sp.mode == MODE_RTB && (rc = pool_need_T(g, g->pool))) return rc;
     int64_t rcap = g->dreq_cap;
     if ((rc = grow(&g->dreqs, rcap, (int64_t)sp.reqs.size(), 64))) return rc;
     g->dreq_cap = (int)rcap;
@@ -504,6 +516,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         int ns2 = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int>(nretry, 64), fit));
         rc = pool_ensure(g, g->pool_big, ns2, cap2);
         if (rc) return rc;
+        if (sp.mode == MODE_RTB && (rc = pool_need_T(g, g->pool_big))) return rc;
         std::vector<int32_t> q((size_t)nretry + 1);
         HIPCHK(hipMemcpy(q.data(), g->dretry, sizeof(int32_t) * (nretry + 1), hipMemcpyDeviceToHost));
         int32_t *dq = nullptr;
@@ -632,7 +645,7 @@ static DevReq make_req(const mantra_request &rq, int stream, int64_t base, int64
     d.qoff = qoff;
     d.count = count;
     d.per_graph = count;
-    d.mode = (rq.flags & MANTRA_F_TRK) ? MODE_TRK : MODE_PAIRS;
+    d.mode = (rq.flags & MANTRA_F_RTB) ? MODE_RTB : (rq.flags & MANTRA_F_TRK) ? MODE_TRK : MODE_PAIRS;
     if (acc) {
         d.Bsum = acc->B;
         d.Wsum = acc->W;
@@ -647,6 +660,8 @@ int check_request(const mantra_graph *g, const mantra_request &rq) {
     if (!rq.node_bc) return fail(MANTRA_E_INVALID, "node_bc is NULL");
     int c = rq.c ? rq.c : 25;
     if (c < 1 || c > 64) return fail(MANTRA_E_INVALID, "c = %d outside 1..64", c);
+    if ((rq.flags & MANTRA_F_TRK) && (rq.flags & MANTRA_F_RTB))
+        return fail(MANTRA_E_INVALID, "MANTRA_F_TRK and MANTRA_F_RTB are two estimators: pick one");
     if (rq.fixed_r <= 0) {
         if (!(rq.eps > 0 && rq.eps < 1)) return fail(MANTRA_E_INVALID, "eps must be in (0, 1)");
         if (!(rq.delta > 0 && rq.delta < 1)) return fail(MANTRA_E_INVALID, "delta must be in (0, 1)");
@@ -1072,6 +1087,11 @@ static int explicit_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t
         int32_t gi = graph ? graph[q] : 0;
         if (gi < 0 || gi >= g->G) return fail(MANTRA_E_INVALID, "pair %lld: graph %d", (long long)q, gi);
         int32_t ng = g->seg_noff[gi + 1] - g->seg_noff[gi];
+        if (mode == MODE_RTB) {
+            if (s[q] < 0 || s[q] >= ng) return fail(MANTRA_E_INVALID, "source %lld: %d not a node of graph %d",
+                                                    (long long)q, s[q], gi);
+            continue;
+        }
         if (s[q] < 0 || s[q] >= ng || z[q] < 0 || z[q] >= ng || s[q] == z[q])
             return fail(MANTRA_E_INVALID, "pair %lld: (%d, %d) not two distinct nodes of graph %d", (long long)q,
                         s[q], z[q], gi);
@@ -1098,7 +1118,7 @@ static int explicit_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t
         for (int64_t q = 0; q < r; ++q) {
             int32_t b = g->seg_noff[graph ? graph[q] : 0];
             si[(size_t)q] = g->perm[(size_t)(b + s[q])] - b;
-            zi[(size_t)q] = g->perm[(size_t)(b + z[q])] - b;
+            zi[(size_t)q] = mode == MODE_RTB ? 0 : g->perm[(size_t)(b + z[q])] - b;
         }
         hipMemcpy(dps, si.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice);
         hipMemcpy(dpz, zi.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice);
@@ -1111,6 +1131,7 @@ static int explicit_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t
     memset(&rq, 0, sizeof rq);
     rq.opt = opt; rq.t0 = t0; rq.t1 = t1; rq.seed = seed;
     if (mode == MODE_TRK) rq.flags |= MANTRA_F_TRK;
+    if (mode == MODE_RTB) rq.flags |= MANTRA_F_RTB;
     norm_window(rq);
     sp.reqs.push_back(make_req(rq, STREAM_PAIR, 0, 0, r, nullptr, 0));
     sp.npairs = r;
@@ -1156,6 +1177,12 @@ int mantra_sample_paths(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1,
                         const int32_t *s, const int32_t *z, uint64_t seed, mantra_pair_record *out, double *node_f,
                         double *edge_f) {
     return explicit_pairs(g, opt, t0, t1, r, graph, s, z, seed, MODE_TRK, out, node_f, edge_f);
+}
+
+int mantra_source_dependencies(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r,
+                               const int32_t *graph, const int32_t *s, mantra_pair_record *out, double *node_f,
+                               double *edge_f) {
+    return explicit_pairs(g, opt, t0, t1, r, graph, s, s, 0, MODE_RTB, out, node_f, edge_f);
 }
 
 int mantra_run(mantra_graph *g, const mantra_request *req, mantra_result *out) {

@@ -27,6 +27,7 @@ extern "C" {
 hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
 hipError_t mantra_launch_sweep_sources(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
 hipError_t mantra_launch_sweep_trk(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
+hipError_t mantra_launch_sweep_rtb(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
 hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st);
 hipError_t mantra_launch_fill(mantra::u64 *p, mantra::u64 val, int64_t n, hipStream_t st);
 hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u64 *stats, hipStream_t st);
@@ -65,19 +66,20 @@ struct SlabPool {
     int nslabs = 0;
     int64_t nmax = 0, cap = 0, gmax = 0;
     u64 *F = nullptr, *N = nullptr, *AG = nullptr, *arcs = nullptr, *XS = nullptr;
+    u64 *T = nullptr;  // RTB launches only: first arrivals, [nslabs][nmax][2]
     u32 *AGF = nullptr, *hdr = nullptr;
     int32_t *touched = nullptr;
     void release() {
-        hipFree(F); hipFree(N); hipFree(AG); hipFree(arcs); hipFree(XS);
+        hipFree(F); hipFree(N); hipFree(AG); hipFree(arcs); hipFree(XS); hipFree(T);
         hipFree(AGF); hipFree(hdr); hipFree(touched);
-        F = N = AG = arcs = XS = nullptr;
+        F = N = AG = arcs = XS = T = nullptr;
         AGF = hdr = nullptr;
         touched = nullptr;
         nslabs = 0;
     }
     DevSlabs view() const {
         DevSlabs s;
-        s.F = F; s.N = N; s.AG = AG; s.AGF = AGF; s.touched = touched; s.arcs = arcs;
+        s.F = F; s.N = N; s.T = T; s.AG = AG; s.AGF = AGF; s.touched = touched; s.arcs = arcs;
         s.XS = XS; s.hdr = hdr; s.nmax = nmax; s.cap = cap; s.gmax = gmax;
         return s;
     }
@@ -151,7 +153,7 @@ struct LaunchSpec {
     const int32_t *dpg = nullptr, *dps = nullptr, *dpz = nullptr;
     void *drec = nullptr;
     double *dnode_f = nullptr, *dedge_f = nullptr;
-    int mode = MODE_PAIRS;  // the kernel: MODE_PAIRS, MODE_TRK (pairs) or MODE_DISTANCES (sources)
+    int mode = MODE_PAIRS;  // the kernel: MODE_PAIRS, MODE_TRK (pairs), MODE_DISTANCES or MODE_RTB (sources)
 };
 
 // what one call of run_sweep did: launch statistics (indices as in

@@ -100,24 +100,24 @@ static void serve_loop(mantra_graph *g) {
                 t->run.rc = req_begin(g, t->run);
                 if (t->run.rc) { t->run.err = g_err; finished.push_back(t); }
             }
-            // one launch over a slice of every active request (two when both
-            // estimators are active: each has a kernel of its own)
-            LaunchSpec sps[2];
-            std::vector<std::shared_ptr<Ticket>> ins[2];
+            // one launch over a slice of every active request (one per
+            // estimator in use: each has a kernel of its own)
+            LaunchSpec sps[3];
+            std::vector<std::shared_ptr<Ticket>> ins[3];
             const int64_t quota = slice_quota(g, act.size());
             for (auto &t : act) {
                 if (t->run.rc || t->run.phase == ReqRun::DONE) continue;
                 const int64_t cnt = std::min(req_pending(t->run), quota);
                 if (cnt <= 0) continue;
-                const int mi = (t->run.rq.flags & MANTRA_F_TRK) ? 1 : 0;
+                const int mi = (t->run.rq.flags & MANTRA_F_RTB) ? 2 : (t->run.rq.flags & MANTRA_F_TRK) ? 1 : 0;
                 sps[mi].reqs.push_back(req_slice(t->run, cnt, sps[mi].npairs));
                 sps[mi].npairs += cnt;
                 ins[mi].push_back(t);
             }
-            for (int mi = 0; mi < 2; ++mi) {
+            for (int mi = 0; mi < 3; ++mi) {
                 LaunchSpec &sp = sps[mi];
                 if (sp.npairs <= 0) continue;
-                sp.mode = mi ? MODE_TRK : MODE_PAIRS;
+                sp.mode = mi == 2 ? MODE_RTB : mi == 1 ? MODE_TRK : MODE_PAIRS;
                 SweepOut o;
                 int rc = run_sweep(g, sp, o);
                 const std::string launch_err = rc ? g_err : std::string();

@@ -188,6 +188,7 @@ struct Pair {
 
 struct Slab {
     u64 *F, *R, *N, *AG, *XS;
+    u64 *T;                // RTB: [nmax][2] first arrival {time | hops << 32, count} of each reached node
     u64 *arcm;             // [cap] head | time << 32
     u64 *arcx;             // [cap][3] edge | tail << 32, tail count, tl | hl << 16
     u32 *AGF, *hdr;
@@ -259,10 +260,16 @@ __device__ __forceinline__ bool head_commit(int opt, bool rv, u32 hv, u64 Sv, u3
 // slab's global per-node scratch (AG), four passes, commits after all reads.
 // Such a tick always forms a batch of its own.
 
-template <bool SINGLE>
+// forward modes: a pair (arcs, stop at z); a source's distances (no arcs,
+// first-arrival hops in N); a source for the RTB estimator (arcs, and each
+// node's first arrival {time | hops << 32, count} in T)
+enum { FWD_PAIR = 0, FWD_DIST = 1, FWD_RTB = 2 };
+
+template <int FM>
 __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
                               int64_t g0, int64_t g1, int32_t t, u32 &agstamp, FwdOut &o,
                               u32 &zh, u64 &zS, bool &zhit) {
+    constexpr bool SINGLE = FM != FWD_PAIR;
     const int l = lane_id();
     const int32_t *U = a.g.U, *V = a.g.V;
     agstamp += 1;
@@ -356,7 +363,11 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
                 if (head_commit(P.opt, rv, hv, Sv, d, c, v, P.z, zh, &nh, &nS)) {
                     ok = agstamp;
                     if (SINGLE && !rv) {  // first arrival: list of reached nodes, hops (fm / sfm / pfm)
-                        if (P.opt != OPT_SH) S.N[v] = (u64)nh + 1ull;
+                        if (FM == FWD_DIST && P.opt != OPT_SH) S.N[v] = (u64)nh + 1ull;
+                        if (FM == FWD_RTB) {
+                            S.T[2 * (int64_t)v] = (u64)(u32)t | ((u64)nh << 32);
+                            S.T[2 * (int64_t)v + 1] = nS;
+                        }
                         fa = true;
                     }
                     if (v < H.K) { H.h[v] = nh; H.s[v] = nS; }
@@ -406,7 +417,7 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
                 if (S.AGF[k] == agstamp) {
                     hu = (u32)x0;
                     d = (u32)ld_agent(&S.AG[2 * k]);
-                    if ((!P.level || hu + 1 == d) && !SINGLE) {
+                    if ((!P.level || hu + 1 == d) && FM != FWD_DIST) {
                         rec = true;
                         u = U[idx];
                         su = S.XS[2 * (idx - g0) + 1];
@@ -445,9 +456,10 @@ __device__ __forceinline__ void load_batch(const LaunchArgs &a, const Pair &P, i
 // from the slab) or the commit of an earlier tick of the same batch, passed
 // from the committing lane's registers.  Maximal runs of ticks that read no
 // commit made inside the run ("segments") are processed together.
-template <bool SINGLE>
+template <int FM>
 __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H, FwdLds &L,
                         u32 &agstamp, FwdOut &o) {
+    constexpr bool SINGLE = FM != FWD_PAIR;
     static_assert(kE == 1, "the forward sweep is written for one edge per lane");
     const int l = lane_id();
     const int opt = P.opt;
@@ -481,7 +493,7 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                         if (m) { g1 = i + (__ffsll((long long)m) - 1); break; }
                     }
                     __syncthreads();
-                    fwd_long_tick<SINGLE>(a, P, S, bm, H, b0, g1, tlast, agstamp, o, zh, zS, zhit);
+                    fwd_long_tick<FM>(a, P, S, bm, H, b0, g1, tlast, agstamp, o, zh, zS, zhit);
                     o.swept = g1 - P.lo;
                     b0 = g1;
                     if (o.flags & REC_HOPS_LIMIT) return;
@@ -693,7 +705,11 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
                 const bool fa = ok && cur_h == kHInf;
                 const u64 fm_ = ballot(fa);
                 if (fa) {
-                    if (opt != OPT_SH) S.N[v] = (u64)nh2 + 1ull;
+                    if (FM == FWD_DIST && opt != OPT_SH) S.N[v] = (u64)nh2 + 1ull;
+                    if (FM == FWD_RTB) {
+                        S.T[2 * (int64_t)v] = (u64)(u32)t | ((u64)nh2 << 32);
+                        S.T[2 * (int64_t)v + 1] = nS;
+                    }
                     S.touched[o.reached_n + mbcnt(fm_)] = v;
                 }
                 o.reached_n += __popcll(fm_);
@@ -712,7 +728,7 @@ __device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
             }
             // arcs of the segment
             const bool okr = single ? ok : (__shfl((int)ok, rsl) != 0);
-            const bool rec = tight && okr && keep && !SINGLE;
+            const bool rec = tight && okr && keep && FM != FWD_DIST;
             const u64 m = ballot(rec);
             if (m) {
                 if (rec) put_arc(S, a.sl.cap, o.arcs + mbcnt(m), v, t, (u32)(b0 + l), u, s_u, h_u, d);
@@ -1272,13 +1288,119 @@ __device__ bool trk_walk(const LaunchArgs &a, const Pair &P, const Slab &S, int6
     }
 }
 
+// The RTB estimator (appendix on other estimators): for a sampled source s,
+// f(v|s) = (1/(n-1)) * sum over targets z != s of sigma_sz(v) / sigma_sz.
+// After a forward sweep of s to the window's end with its arcs recorded, the
+// reverse walks the arcs newest first, one tick at a time, in double
+// precision: the value of a head appearance (v, t) is
+//   C(v, t) = (continuations of (v, t), the tail state of v at its level)
+//           + 1 / sigma_sv if (v, t) is one of v's terminal appearances
+// (sh: those at v's fewest hops; fm, sfm, pfm: its first arrival), i.e. the
+// sum over targets z of (optimal suffixes from (v, t) to z) / sigma_sz.
+// N(v) gains (tail count) * (continuations only: v as the target is not an
+// internal node), f(e) = (tail count) * C(head) / (n - 1), and C(head) flows
+// into the tail's state; level resets as in the pair reverse.  The origin's
+// value must come out as the number of reached targets.  Returns false if
+// a count on the way saturated.
+__device__ bool rev_rtb(const LaunchArgs &a, const Pair &P, const Slab &S, int64_t narcs, RevCtx &X) {
+    const int l = lane_id();
+    const DevReq *R = P.req;
+    const double n1 = (double)(P.ng - 1);
+    bool bad = false;
+    int64_t ac = narcs;
+    while (ac > 0) {
+        // the tick [a0, ac) of the newest arcs left
+        const int32_t th = (int32_t)(S.arcm[ac - 1] >> 32);
+        int64_t a0 = 0;
+        for (int64_t i0 = ac - kWave;; i0 -= kWave) {
+            const int64_t i = i0 + l;
+            const bool diff = i >= 0 && i < ac && (int32_t)(S.arcm[i] >> 32) != th;
+            const u64 m = ballot(diff);
+            if (m) { a0 = i0 + (63 - __clzll((long long)m)) + 1; break; }
+            if (i0 <= 0) { a0 = 0; break; }
+        }
+        // heads: their values (state older than the tick), N(v), f(e)
+        for (int64_t sb = a0; sb < ac; sb += kWave) {
+            const int64_t i = sb + l;
+            bool first = false, nz = false;
+            int32_t v = 0;
+            if (i < ac) {
+                const u64 mm = S.arcm[i];
+                v = (int32_t)(u32)mm;
+                const int32_t t = (int32_t)(mm >> 32);
+                const u64 x0 = S.arcx[3 * i];
+                const u32 k = (u32)x0;
+                const u64 tc = S.arcx[3 * i + 1];
+                const u32 hl = (u32)(S.arcx[3 * i + 2] >> 16) & 0xFFFFu;
+                if (tc == kUMax) bad = true;
+                double thru = 0.0;
+                const u64 tw = ld_agent(&S.R[2 * (int64_t)v]);
+                if ((u32)tw == P.rtag && (!P.level || ((u32)(tw >> 32) & 0xFFFFu) == hl))
+                    thru = __longlong_as_double((long long)ld_agent(&S.R[2 * (int64_t)v + 1]));
+                double C = thru;
+                if (v != P.s) {
+                    const u64 fa = S.T[2 * (int64_t)v];
+                    const bool term = P.opt == OPT_SH ? ((u32)(fa >> 32) & 0xFFFFu) == hl : (int32_t)(u32)fa == t;
+                    if (term) {
+                        const u64 sg = S.T[2 * (int64_t)v + 1];
+                        if (sg == kUMax) bad = true;
+                        C += 1.0 / (double)sg;
+                    }
+                }
+                S.XS[i - a0] = (u64)__double_as_longlong(C);
+                if (v != P.s && thru != 0.0) {
+                    const double old = atomicAdd(reinterpret_cast<double *>(&S.N[v]), (double)tc * thru);
+                    first = old == 0.0;
+                }
+                nz = C != 0.0;
+                if (nz) {
+                    const double fe = (double)tc * C / n1;
+                    if (R->Esum) atomicAdd(&R->Esum[k], fe);
+                    if (a.edge_f) a.edge_f[P.qout * a.g.m + k] = fe;
+                }
+            }
+            X.edges_n += __popcll(ballot(nz));
+            const u64 m = ballot(first);
+            if (first) S.touched[X.touched_n + mbcnt(m)] = v;
+            X.touched_n += __popcll(m);
+        }
+        __syncthreads();
+        // tails: level resets, then the additions
+        for (int64_t sb = a0; sb < ac; sb += kWave) {
+            const int64_t i = sb + l;
+            if (i >= ac) continue;
+            if (S.XS[i - a0] == 0ull) continue;
+            const int32_t u = (int32_t)(S.arcx[3 * i] >> 32);
+            const u32 want = P.level ? ((u32)S.arcx[3 * i + 2] & 0xFFFFu) : 0u;
+            const u64 tw = ld_agent(&S.R[2 * (int64_t)u]);
+            if ((u32)tw != P.rtag || ((u32)(tw >> 32) & 0xFFFFu) != want) {
+                S.R[2 * (int64_t)u] = (u64)P.rtag | ((u64)want << 32);
+                S.R[2 * (int64_t)u + 1] = 0ull;
+            }
+        }
+        __syncthreads();
+        for (int64_t sb = a0; sb < ac; sb += kWave) {
+            const int64_t i = sb + l;
+            if (i >= ac) continue;
+            const u64 cb = S.XS[i - a0];
+            if (cb == 0ull) continue;
+            const int32_t u = (int32_t)(S.arcx[3 * i] >> 32);
+            atomicAdd(reinterpret_cast<double *>(&S.R[2 * (int64_t)u + 1]), __longlong_as_double((long long)cb));
+        }
+        __syncthreads();
+        ac = a0;
+    }
+    return !ballot(bad);
+}
+
 // MODE_PAIRS: pairs, f = N / sigma from the reverse sweep; MODE_DISTANCES:
 // every slot is a single source; MODE_TRK: pairs, f = visits of one sampled
 // optimal walk.  Each mode is a kernel of its own, so that the pair sweep
 // keeps its register allocation.
 template <int MODE>
 __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
-    constexpr bool SINGLE = MODE == MODE_DISTANCES;
+    constexpr bool RTB = MODE == MODE_RTB;
+    constexpr bool SINGLE = MODE == MODE_DISTANCES || RTB;
     constexpr bool TRK = MODE == MODE_TRK;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int l = lane_id();
@@ -1293,6 +1415,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
     S.arcm = a.sl.arcs + slab * a.sl.cap * 4;
     S.arcx = S.arcm + a.sl.cap;
     S.XS = a.sl.XS + slab * a.sl.gmax * 2;
+    S.T = a.sl.T ? a.sl.T + slab * a.sl.nmax * 2 : nullptr;
     S.hdr = a.sl.hdr + slab * 4;
     TabLds &tab = *reinterpret_cast<TabLds *>(lds_raw);
     u32 *bm = reinterpret_cast<u32 *>(lds_raw + sizeof(TabLds));
@@ -1359,10 +1482,23 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
                 if (a.lds_bitmap) bm[P.s >> 5] |= 1u << (P.s & 31);
             }
             __syncthreads();
-            forward<SINGLE>(a, P, S, bm, H, tab.f, agstamp, fo);
+            forward<SINGLE ? (RTB ? FWD_RTB : FWD_DIST) : FWD_PAIR>(a, P, S, bm, H, tab.f, agstamp, fo);
             __syncthreads();
-            if (SINGLE) distance_hist(P, S, H, reinterpret_cast<u32 *>(tab.r.tb_key), fo.reached_n,
-                                      !(fo.flags & REC_HOPS_LIMIT));
+            if (MODE == MODE_DISTANCES)
+                distance_hist(P, S, H, reinterpret_cast<u32 *>(tab.r.tb_key), fo.reached_n,
+                              !(fo.flags & REC_HOPS_LIMIT));
+            if (RTB) {
+                // sh: the terminal level and sigma are the final state
+                for (int64_t i = l; i < fo.reached_n; i += kWave) {
+                    const int32_t v = S.touched[i];
+                    const u32 h = v < H.K ? H.h[v] : (u32)(S.F[2 * (int64_t)v] >> 32) & 0xFFFFu;
+                    const u64 sg = v < H.K ? H.s[v] : S.F[2 * (int64_t)v + 1];
+                    if (P.opt == OPT_SH) {
+                        S.T[2 * (int64_t)v] = (u64)h << 32;
+                        S.T[2 * (int64_t)v + 1] = sg;
+                    }
+                }
+            }
             // the reverse table reuses the forward's LDS: empty it
             for (int i = l; i < kFwN; i += kWave) { tab.r.tb_key[i] = 0; }
             stamp = 1;
@@ -1372,10 +1508,31 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
         bool reach = ok && fo.reached && !(flags & (REC_HOPS_LIMIT | REC_ARCS_LIMIT));
         u64 sigma = reach ? fo.zS : 0;
         if (reach && sigma == kUMax) flags |= REC_OVERFLOW;
+        if (RTB) {
+            // a source: sigma counts the targets it reaches
+            reach = ok && fo.reached_n > 0 && !(flags & (REC_HOPS_LIMIT | REC_ARCS_LIMIT));
+            sigma = reach ? (u64)fo.reached_n : 0;
+        }
         bool do_rev = reach && !(flags & REC_OVERFLOW);
         RevCtx X;
         X.sigma = sigma; X.dsh = fo.zh; X.touched_n = 0; X.edges_n = 0; X.ovf = false; X.alive_all = false;
-        if (TRK && do_rev) {
+        if (RTB && do_rev) {
+            if (!rev_rtb(a, P, S, fo.arcs, X)) {
+                // a saturated count: the source is void, its f(e) rows cleared
+                flags |= REC_OVERFLOW;
+                if (a.edge_f)
+                    for (int64_t i = l; i < fo.arcs; i += kWave)
+                        a.edge_f[P.qout * a.g.m + (int64_t)(u32)S.arcx[3 * i]] = 0.0;
+            } else {
+                // every reached target contributes exactly one to the origin
+                const u64 tw = ld_agent(&S.R[2 * (int64_t)P.s]);
+                double bo = 0.0;
+                if ((u32)tw == P.rtag && (!P.level || ((u32)(tw >> 32) & 0xFFFFu) == 0u))
+                    bo = __longlong_as_double((long long)ld_agent(&S.R[2 * (int64_t)P.s + 1]));
+                const double want = (double)fo.reached_n;
+                if (!(fabs(bo - want) <= 1e-9 * want)) flags |= REC_SELFCHECK;
+            }
+        } else if (TRK && do_rev) {
             // the walk checks the forward's counts at every step: a failure
             // is a broken invariant
             if (!trk_walk(a, P, S, fo.arcs, fo.zh, fo.t_arr, sigma, X)) flags |= REC_SELFCHECK;
@@ -1404,7 +1561,8 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
             int32_t v = S.touched[i];
             u64 nv = atomicExch((unsigned long long *)&S.N[v], 0ull);
             if (!accum) continue;
-            double f = TRK ? (double)nv : (double)nv / (double)sigma;
+            double f = TRK ? (double)nv
+                           : RTB ? __longlong_as_double((long long)nv) / (double)(P.ng - 1) : (double)nv / (double)sigma;
             int64_t gv = (int64_t)P.noff + v;
             if (R->Bsum) atomicAdd(&R->Bsum[gv], f);
             if (R->Wsum) { double f2 = f * f; atomicAdd(&R->Wsum[gv], f2); }
@@ -1422,7 +1580,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
                 bool rch = reach;
                 rr[0] = rch ? 1 : 0;
                 rr[1] = rch ? fo.t_arr : -1;
-                rr[2] = rch ? (int32_t)fo.zh : -1;
+                rr[2] = (rch && !RTB) ? (int32_t)fo.zh : -1;
                 rr[3] = (int32_t)flags;
                 *reinterpret_cast<u64 *>(rr + 4) = sigma;
             }
@@ -1499,7 +1657,7 @@ __global__ void __launch_bounds__(256) k_pair_keys(LaunchArgs a, u32 *bucket, u6
     a.pq = nullptr;
     Pair P;
     resolve_pair(a, slot, P);
-    if (P.req->mode == MODE_DISTANCES) { P.single = true; P.z = -1; }
+    if (P.req->mode == MODE_DISTANCES || P.req->mode == MODE_RTB) { P.single = true; P.z = -1; }
     const int32_t gs = P.noff + P.s;
     const int64_t o0 = a.g.out_off[gs], o1 = a.g.out_off[gs + 1];
     const int64_t od = lower_bound_1(a.g.out_t, o0, o1, P.t0);
@@ -1616,6 +1774,11 @@ hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t l
 // the single-source (distance) form of the sweep
 hipError_t mantra_launch_sweep_sources(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
     hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_DISTANCES>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    return hipGetLastError();
+}
+// the sweep with the RTB estimator (sources, all targets; needs the slabs' T)
+hipError_t mantra_launch_sweep_rtb(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_RTB>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
     return hipGetLastError();
 }
 // the sweep with the TRK estimator (one sampled optimal walk per pair)
