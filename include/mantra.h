@@ -20,8 +20,10 @@
  *  - Optimalities (Definition 1; fm is an extension, see mantra_opt) are
  *    counted over strict temporal walks: consecutive edges have strictly
  *    increasing times, and the source starts before every edge.
- *  - Path counts are exact uint64; a count that reaches 2^64-1 is saturated and
- *    reported (MANTRA_REC_OVERFLOW / MANTRA_E_OVERFLOW), never rounded.
+ *  - Path counts are exact integers: uint64, and for the dependency estimator
+ *    256-bit words for the pairs whose counts do not fit 64 bits
+ *    (MANTRA_REC_WIDE).  A count beyond that is saturated and reported
+ *    (MANTRA_REC_OVERFLOW / MANTRA_E_OVERFLOW), never rounded.
  *  - Time windows [t0, t1] are inclusive; the node set and the n(n-1)
  *    normalisation are those of the whole graph.
  */
@@ -67,7 +69,13 @@ typedef struct {
     uint64_t sigma;    /* number of optimal walks (saturated at 2^64-1) */
 } mantra_pair_record;
 
-#define MANTRA_REC_OVERFLOW 1u   /* sigma (or an fm visit count) saturated */
+#define MANTRA_REC_OVERFLOW 1u   /* a count saturated: above 2^256 - 1 for the dependency
+                                    estimator (its multiword path), above 2^64 - 1 for the
+                                    TRK and RTB estimators */
+#define MANTRA_REC_WIDE 16u      /* sigma is above 2^64 - 1 (the record's sigma field then
+                                    reads 2^64 - 1): the pair was counted exactly in 256-bit
+                                    words (the paper's 128-bit and arbitrary-precision
+                                    counts) and its f values are exact quotients */
 #define MANTRA_REC_HOPS_LIMIT 4u /* a hop count would exceed 65534 */
 
 /* Build a device-resident temporal graph (Preliminaries: a set of temporal
@@ -273,7 +281,14 @@ typedef struct {
     int32_t hub_nodes;    /* forward state of the hub_nodes highest-degree nodes
                              of each pair kept in LDS (graphs whose reached
                              bitmap fits LDS; 0: none) */
+    int32_t wide_counts;  /* pairs whose 64-bit counts saturate, counted again in
+                             256-bit words (dependency estimator): MANTRA_WIDE_* */
 } mantra_launch_config;
+
+#define MANTRA_WIDE_NONE 0    /* reported as saturated */
+#define MANTRA_WIDE_NOT_FM 1  /* sh, sfm and pfm pairs (default): fm walk counts grow
+                                 exponentially with the ticks and mostly pass 2^256 too */
+#define MANTRA_WIDE_ALL 2     /* every optimality */
 
 #define MANTRA_ORDER_LONGEST_FIRST 0 /* decreasing estimated window (default) */
 #define MANTRA_ORDER_DRAWN 1         /* sample order */

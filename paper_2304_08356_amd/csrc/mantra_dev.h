@@ -36,6 +36,25 @@ enum : u32 {
     REC_SELFCHECK = 2u,   // flow conservation at the origin failed (internal error)
     REC_HOPS_LIMIT = 4u,
     REC_ARCS_LIMIT = 8u,  // arc buffer too small: pair re-run with a larger one
+    REC_WIDE = 16u,       // counts beyond 64 bits, taken exactly by the multiword path
+};
+
+// multiword counts of the exact path for pairs whose 64-bit counts saturate
+constexpr int kWide = 4;  // limbs of 64 bits: counts below 2^256
+
+// per-slab state of the multiword path (one pair at a time per slab)
+struct WideSlabs {
+    u64 *ST;          // [ns][nmax]          forward {tag | hops << 32}
+    u64 *SS;          // [ns][nmax][kWide]   forward count
+    u64 *RT;          // [ns][nmax]          reverse {tag | level << 32}
+    u64 *RA;          // [ns][nmax][kWide]   reverse suffix sum
+    u64 *NV;          // [ns][nmax][kWide]   N(v), zero between pairs
+    int32_t *touched; // [ns][nmax]
+    u32 *TL;          // [ns][gmax]          per edge of a tick: tail hops (or none)
+    u64 *TC;          // [ns][gmax][kWide]   per edge of a tick: tail count; per arc of a tick: B(head)
+    u64 *AR;          // [ns][cap][3 + kWide] arcs {head | t << 32, edge | tail << 32, tl | hl << 16, count}
+    u32 *hdr;         // [ns][4]             pair serial
+    int64_t nmax, cap, gmax;
 };
 
 struct DevGraph {
@@ -103,6 +122,9 @@ struct LaunchArgs {
     u32 *work;                   // work counter, zero at launch
     u64 *stats;                  // [16] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck, touched nodes, touched edges, slab busy ticks, last end, ~first start
     int32_t *retry;              // [1 + npairs] pairs whose arcs did not fit
+    int32_t *wide;               // [1 + npairs] pairs whose counts saturated, for the multiword path
+                                 // (null: they are reported as saturated)
+    int32_t wide_fm;             // 1: fm pairs too
 };
 
 struct ReduceArgs {

@@ -350,6 +350,38 @@ static int pool_need_T(mantra_graph *g, SlabPool &p) {
     return MANTRA_OK;
 }
 
+// the multiword path's slabs: per node the forward and reverse state, N and
+// the touched list; per edge of the longest tick its scratch; arcs for every
+// edge of the graph (a pair's arcs never outnumber its window)
+static size_t wide_slab_bytes(const mantra_graph *g, int64_t cap) {
+    return (size_t)g->nmax * (16 + 24 * kWide + 4) + (size_t)g->gmax * (4 + 8 * kWide) +
+           (size_t)cap * 8 * (3 + kWide) + 16;
+}
+static int wide_ensure(mantra_graph *g, int nslabs, int64_t cap) {
+    WidePool &p = g->wide;
+    if (p.nslabs >= nslabs && p.cap >= cap && p.nmax == g->nmax && p.gmax >= g->gmax) return MANTRA_OK;
+    p.release();
+    const size_t ns = (size_t)nslabs, n = (size_t)g->nmax, gm = (size_t)g->gmax;
+    if (dalloc(&p.ST, ns * n) || dalloc(&p.SS, ns * n * kWide) || dalloc(&p.RT, ns * n) ||
+        dalloc(&p.RA, ns * n * kWide) || dalloc(&p.NV, ns * n * kWide) || dalloc(&p.touched, ns * n) ||
+        dalloc(&p.TL, ns * gm) || dalloc(&p.TC, ns * gm * kWide) || dalloc(&p.AR, ns * (size_t)cap * (3 + kWide)) ||
+        dalloc(&p.hdr, ns * 4)) {
+        p.release();
+        (void)hipGetLastError();
+        return fail(MANTRA_E_OOM, "multiword path: %d slabs x %lld nodes", nslabs, (long long)n);
+    }
+    HIPCHK(hipMemsetAsync(p.ST, 0, sizeof(u64) * ns * n, g->st));
+    HIPCHK(hipMemsetAsync(p.RT, 0, sizeof(u64) * ns * n, g->st));
+    HIPCHK(hipMemsetAsync(p.NV, 0, sizeof(u64) * ns * n * kWide, g->st));
+    HIPCHK(hipMemsetAsync(p.hdr, 0, sizeof(u32) * ns * 4, g->st));
+    HIPCHK(hipStreamSynchronize(g->st));
+    p.nslabs = nslabs;
+    p.nmax = g->nmax;
+    p.gmax = g->gmax;
+    p.cap = cap;
+    return MANTRA_OK;
+}
+
 // arc records (32 B each) per slab: the rest of the pool budget, at most
 // one per edge of the graph
 static int64_t auto_cap(const mantra_graph *g, int nslabs) {
@@ -390,7 +422,7 @@ static hipError_t launch_sweep(const LaunchArgs &a, int mode, int ns, size_t lb,
 }
 
 static int issue_kernels(mantra_graph *g, LaunchArgs &a, int ns, size_t lb, const RoundGraph *rg, int mode) {
-    HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, g->dstats, g->st));
+    HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, (u32 *)g->dwide, g->dstats, g->st));
     if (g->order_mode == MANTRA_ORDER_LONGEST_FIRST && a.npairs > ns) {
         HIPCHK(mantra_launch_order(&a, g->dbucket, g->dhist, g->dorder, g->st));
         a.pq = g->dorder;
@@ -430,6 +462,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     if ((rc = grow(&g->dreqs, rcap, (int64_t)sp.reqs.size(), 64))) return rc;
     g->dreq_cap = (int)rcap;
     if ((rc = grow(&g->dretry, g->retry_cap, slots + 1, 4096))) return rc;
+    if ((rc = grow(&g->dwide, g->wide_cap, slots + 1, 4096))) return rc;
     int64_t oc = g->order_cap;
     if ((rc = grow(&g->dbucket, oc, slots, 4096))) return rc;
     if ((rc = grow(&g->dorder, g->order_cap, slots, 4096))) return rc;
@@ -455,11 +488,13 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     a.work = g->dwork;
     a.stats = g->dstats;
     a.retry = g->dretry;
+    a.wide = (sp.mode == MODE_PAIRS && g->wide_mode != MANTRA_WIDE_NONE) ? g->dwide : nullptr;  // saturated pairs:
+    a.wide_fm = g->wide_mode == MANTRA_WIDE_ALL ? 1 : 0;                                        // the multiword path
     const size_t lb = lds_bytes(g);
     float ms = 0;
     if (g->per_pair) {
         // the unbatched form: one single-workgroup launch per pair
-        HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, g->dstats, g->st));
+        HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, (u32 *)g->dwide, g->dstats, g->st));
         HIPCHK(hipEventRecord(g->ev0, g->st));
         for (int64_t q = 0; q < sp.npairs; ++q) {
             a.qbase = q;
@@ -522,8 +557,8 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         int32_t *dq = nullptr;
         HIPCHK(dalloc(&dq, (size_t)nretry));
         HIPCHK(hipMemcpy(dq, q.data() + 1, sizeof(int32_t) * nretry, hipMemcpyHostToDevice));
-        HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, g->dstats, g->st));
-        a.sl = g->pool_big.view();
+        HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, nullptr, g->dstats, g->st));  // keeps the
+        a.sl = g->pool_big.view();                                                              // multiword list
         a.npairs = nretry;
         a.npairs_dev = nullptr;
         a.qbase = 0;
@@ -544,6 +579,37 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         if (n2 > 0) return fail(MANTRA_E_INTERNAL, "arc buffer of a full window overflowed");
         for (int i = 0; i < 16; ++i)
             if (i != 5 && i < 9) st1[i] += st2[i];
+    }
+    int32_t nwide = 0;
+    if (a.wide) HIPCHK(hipMemcpy(&nwide, g->dwide, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (nwide > 0) {
+        // pairs whose 64-bit counts saturated: exact multiword counts, one
+        // lane per pair, as many slabs as an eighth of device memory holds
+        o.reduced = false;
+        const int64_t cap3 = g->m + 1;
+        size_t fr, tot;
+        device_mem(g, &fr, &tot);
+        const int64_t fit = (int64_t)(std::min(tot / 8, fr / 2) / wide_slab_bytes(g, cap3));
+        const int ns3 = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int>(nwide, 128), fit));
+        if ((rc = wide_ensure(g, std::max(ns3, g->wide.nslabs), cap3))) return rc;
+        HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, nullptr, g->dstats, g->st));
+        a.npairs = nwide;
+        a.npairs_dev = nullptr;
+        a.qbase = 0;
+        a.pq = g->dwide + 1;
+        const WideSlabs wv = g->wide.view();
+        HIPCHK(hipEventRecord(g->ev0, g->st));
+        HIPCHK(mantra_launch_wide(&a, &wv, ns3, g->st));
+        HIPCHK(hipEventRecord(g->ev1, g->st));
+        HIPCHK(hipStreamSynchronize(g->st));
+        HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+        o.ms += ms;
+        o.launches += 1;
+        u64 st3[16];
+        HIPCHK(hipMemcpy(st3, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
+        st1[2] += st3[2];
+        st1[4] += st3[4];
+        st1[6] += st3[6];
     }
     memcpy(o.st, st1, sizeof(st1));
     // busy share of the first launch's persistent grid
@@ -959,6 +1025,7 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
         best->graph_rounds = g->graph_rounds;
         best->per_pair_launch = g->per_pair;
         best->hub_nodes = hub_nodes(g);
+        best->wide_counts = g->wide_mode;
     }
     return MANTRA_OK;
 }
@@ -996,6 +1063,8 @@ void mantra_graph_destroy(mantra_graph *g) {
     if (g->st) hipStreamSynchronize(g->st);
     g->pool.release();
     g->pool_big.release();
+    g->wide.release();
+    hipFree(g->dwide);
     hipFree(g->dU); hipFree(g->dV); hipFree(g->dT); hipFree(g->dout_t); hipFree(g->din_t);
     hipFree(g->dout_off); hipFree(g->din_off); hipFree(g->dseg_eoff); hipFree(g->dseg_noff); hipFree(g->dperm);
     hipFree(g->dwork); hipFree(g->dstats); hipFree(g->dretry); hipFree(g->dpart); hipFree(g->dreqs);
@@ -1024,6 +1093,8 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg) {
     if (cfg->order != MANTRA_ORDER_LONGEST_FIRST && cfg->order != MANTRA_ORDER_DRAWN)
         return fail(MANTRA_E_INVALID, "unknown pair order %d", cfg->order);
     if (cfg->hub_nodes < 0 || cfg->hub_nodes > 4096) return fail(MANTRA_E_INVALID, "hub_nodes outside 0..4096");
+    if (cfg->wide_counts < MANTRA_WIDE_NONE || cfg->wide_counts > MANTRA_WIDE_ALL)
+        return fail(MANTRA_E_INVALID, "unknown wide_counts %d", cfg->wide_counts);
     std::lock_guard<std::mutex> lk(g->mu);
     if (g->user_slabs != cfg->n_slabs || g->user_cap != cfg->arc_cap) g->pool.release();
     g->user_slabs = cfg->n_slabs;
@@ -1032,6 +1103,7 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg) {
     g->graph_rounds = cfg->graph_rounds ? 1 : 0;
     g->per_pair = cfg->per_pair_launch ? 1 : 0;
     g->hub_nodes = cfg->hub_nodes;
+    g->wide_mode = cfg->wide_counts;
     return MANTRA_OK;
 }
 
@@ -1053,6 +1125,7 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {
     cfg->graph_rounds = g->graph_rounds;
     cfg->per_pair_launch = g->per_pair;
     cfg->hub_nodes = hub_nodes(g);
+    cfg->wide_counts = g->wide_mode;
     return MANTRA_OK;
 }
 

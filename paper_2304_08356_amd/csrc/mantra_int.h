@@ -30,7 +30,9 @@ hipError_t mantra_launch_sweep_trk(const mantra::LaunchArgs *a, int nslabs, size
 hipError_t mantra_launch_sweep_rtb(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st);
 hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st);
 hipError_t mantra_launch_fill(mantra::u64 *p, mantra::u64 val, int64_t n, hipStream_t st);
-hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u64 *stats, hipStream_t st);
+hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u32 *wide, mantra::u64 *stats,
+                               hipStream_t st);
+hipError_t mantra_launch_wide(const mantra::LaunchArgs *a, const mantra::WideSlabs *ws, int nslabs, hipStream_t st);
 hipError_t mantra_launch_order(const mantra::LaunchArgs *a, mantra::u32 *bucket, mantra::u64 *hist,
                                int32_t *order, hipStream_t st);
 size_t mantra_tab_lds_bytes(void);
@@ -85,6 +87,29 @@ struct SlabPool {
     }
 };
 
+// per-slab state of the multiword path, allocated on its first use
+struct WidePool {
+    int nslabs = 0;
+    int64_t nmax = 0, cap = 0, gmax = 0;
+    u64 *ST = nullptr, *SS = nullptr, *RT = nullptr, *RA = nullptr, *NV = nullptr, *TC = nullptr, *AR = nullptr;
+    u32 *TL = nullptr, *hdr = nullptr;
+    int32_t *touched = nullptr;
+    void release() {
+        hipFree(ST); hipFree(SS); hipFree(RT); hipFree(RA); hipFree(NV); hipFree(TC); hipFree(AR);
+        hipFree(TL); hipFree(hdr); hipFree(touched);
+        ST = SS = RT = RA = NV = TC = AR = nullptr;
+        TL = hdr = nullptr;
+        touched = nullptr;
+        nslabs = 0;
+    }
+    WideSlabs view() const {
+        WideSlabs w;
+        w.ST = ST; w.SS = SS; w.RT = RT; w.RA = RA; w.NV = NV; w.touched = touched; w.TL = TL; w.TC = TC;
+        w.AR = AR; w.hdr = hdr; w.nmax = nmax; w.cap = cap; w.gmax = gmax;
+        return w;
+    }
+};
+
 struct ServeState;  // mantra_serve.hip
 
 }  // namespace mantra
@@ -106,10 +131,14 @@ struct mantra_graph {
     hipStream_t st = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     mantra::SlabPool pool, pool_big;
+    mantra::WidePool wide;          // the multiword path's slabs (first use)
+    int32_t *dwide = nullptr;       // [1 + slots] pairs for the multiword path
+    int64_t wide_cap = 0;
     int user_slabs = 0;
     int64_t user_cap = 0;
     int order_mode = MANTRA_ORDER_LONGEST_FIRST;
     int hub_nodes = 0;              // forward state of nodes below this id in LDS
+    int wide_mode = MANTRA_WIDE_NOT_FM;  // which saturated pairs take the multiword path
     int graph_rounds = 0;
     int per_pair = 0;               // unbatched form: one launch per pair
     int64_t *dnp = nullptr;         // pair count of a graph replay

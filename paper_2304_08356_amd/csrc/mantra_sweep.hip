@@ -1588,14 +1588,21 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
                 atomicAdd((unsigned long long *)&a.stats[0], (unsigned long long)fo.swept);
                 atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)fo.arcs);
             }
-            if (flags & REC_OVERFLOW) atomicAdd((unsigned long long *)&a.stats[2], 1ull);
+            // saturated pairs go to the multiword path when there is one
+            const bool defer = MODE == MODE_PAIRS && a.wide && (flags & REC_OVERFLOW) && !(flags & REC_ARCS_LIMIT) &&
+                               (a.wide_fm || P.opt != OPT_FM);
+            if (defer) {
+                const int pos = atomicAdd(&a.wide[0], 1);
+                a.wide[1 + pos] = (int32_t)P.q;
+            }
+            if ((flags & REC_OVERFLOW) && !defer) atomicAdd((unsigned long long *)&a.stats[2], 1ull);
             if (reach) atomicAdd((unsigned long long *)&a.stats[3], 1ull);
             if (flags & REC_HOPS_LIMIT) atomicAdd((unsigned long long *)&a.stats[4], 1ull);
             if (flags & REC_SELFCHECK) atomicAdd((unsigned long long *)&a.stats[6], 1ull);
             atomicAdd((unsigned long long *)&a.stats[7], (unsigned long long)X.touched_n);
             atomicAdd((unsigned long long *)&a.stats[8], (unsigned long long)X.edges_n);
             if (R->rstat && !(flags & REC_ARCS_LIMIT)) {
-                if (flags & REC_OVERFLOW) atomicAdd((unsigned long long *)&R->rstat[0], 1ull);
+                if ((flags & REC_OVERFLOW) && !defer) atomicAdd((unsigned long long *)&R->rstat[0], 1ull);
                 if (reach) atomicAdd((unsigned long long *)&R->rstat[1], 1ull);
                 if (flags & REC_HOPS_LIMIT) atomicAdd((unsigned long long *)&R->rstat[2], 1ull);
                 atomicAdd((unsigned long long *)&R->rstat[3], (unsigned long long)fo.swept);
@@ -1619,6 +1626,363 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
         atomicMax((unsigned long long *)&a.stats[10], (unsigned long long)t_end);
         atomicMax((unsigned long long *)&a.stats[11], (unsigned long long)~t_begin);
     }
+}
+
+// ------------------------------------------------------------ multiword path
+// Pairs whose 64-bit counts saturate are taken again with counts of kWide
+// limbs (the paper counts with 128-bit and arbitrary-precision integers where
+// 64 bits do not suffice).  It is an exactness path, not a fast one: one
+// lane per pair runs the forward tick by tick (all reads of a tick before its
+// commits; one head run at a time) and the reverse arc by arc, with the same
+// commits, arcs, terminal rule and level resets as the batched kernels.
+// f = N / sigma is the IEEE quotient of the two counts rounded to double.
+
+struct Wd { u64 w[kWide]; };
+
+__device__ __forceinline__ void wd_set(Wd &a, u64 x) {
+    a.w[0] = x;
+    for (int i = 1; i < kWide; ++i) a.w[i] = 0;
+}
+__device__ __forceinline__ void wd_load(Wd &a, const u64 *p) { for (int i = 0; i < kWide; ++i) a.w[i] = p[i]; }
+__device__ __forceinline__ void wd_store(u64 *p, const Wd &a) { for (int i = 0; i < kWide; ++i) p[i] = a.w[i]; }
+__device__ __forceinline__ bool wd_zero(const Wd &a) {
+    u64 x = 0;
+    for (int i = 0; i < kWide; ++i) x |= a.w[i];
+    return x == 0;
+}
+__device__ __forceinline__ bool wd_sat(const Wd &a) {
+    u64 x = kUMax;
+    for (int i = 0; i < kWide; ++i) x &= a.w[i];
+    return x == kUMax;
+}
+__device__ __forceinline__ bool wd_eq(const Wd &a, const Wd &b) {
+    u64 x = 0;
+    for (int i = 0; i < kWide; ++i) x |= a.w[i] ^ b.w[i];
+    return x == 0;
+}
+__device__ __forceinline__ void wd_fill(Wd &a) { for (int i = 0; i < kWide; ++i) a.w[i] = kUMax; }
+// a += b, saturating at 2^(64 kWide) - 1
+__device__ __forceinline__ void wd_add(Wd &a, const Wd &b) {
+    if (wd_sat(a) || wd_sat(b)) { wd_fill(a); return; }
+    u64 carry = 0;
+    for (int i = 0; i < kWide; ++i) {
+        const u64 x = a.w[i] + b.w[i];
+        const u64 c1 = x < a.w[i];
+        const u64 y = x + carry;
+        const u64 c2 = y < x;
+        a.w[i] = y;
+        carry = c1 | c2;
+    }
+    if (carry) wd_fill(a);
+}
+// a * b, saturating
+__device__ __forceinline__ Wd wd_mul(const Wd &a, const Wd &b) {
+    Wd r;
+    if (wd_sat(a) || wd_sat(b)) { wd_fill(r); return r; }
+    u64 acc[2 * kWide];
+    for (int i = 0; i < 2 * kWide; ++i) acc[i] = 0;
+    for (int i = 0; i < kWide; ++i) {
+        u64 carry = 0;
+        for (int j = 0; j < kWide; ++j) {
+            const u64 lo = a.w[i] * b.w[j], hi = __umul64hi(a.w[i], b.w[j]);
+            u64 x = acc[i + j] + lo;
+            u64 c = x < lo;
+            const u64 y = x + carry;
+            c += y < x;
+            acc[i + j] = y;
+            carry = hi + c;  // no wrap: hi <= 2^64 - 2
+        }
+        acc[i + kWide] = carry;
+    }
+    bool over = false;
+    for (int i = kWide; i < 2 * kWide; ++i) over |= acc[i] != 0;
+    if (over) { wd_fill(r); return r; }
+    for (int i = 0; i < kWide; ++i) r.w[i] = acc[i];
+    return r;
+}
+// the count rounded to double, to nearest with ties to even: the top 64 bits
+// with a sticky bit for what lies below (the 11 bits under the 53-bit
+// significand make the hardware rounding of the 64-bit value exact)
+__device__ double wd_to_double(const Wd &a) {
+    int i = kWide - 1;
+    while (i > 0 && a.w[i] == 0) --i;
+    if (i == 0) return (double)a.w[0];
+    const u64 hi = a.w[i], lo = a.w[i - 1];
+    const int sh = __clzll((long long)hi);
+    u64 top = sh ? ((hi << sh) | (lo >> (64 - sh))) : hi;
+    bool sticky = sh ? (lo << sh) != 0 : lo != 0;
+    for (int j = i - 2; j >= 0; --j) sticky |= a.w[j] != 0;
+    if (sticky) top |= 1ull;
+    return ldexp((double)top, 64 * i - sh);
+}
+
+// the commit of a head run (the rules of head_commit, multiword)
+__device__ bool wd_commit(int opt, bool rv, u32 hv, const Wd &Sv, u32 d, const Wd &c, u32 &nh, Wd &nS) {
+    if (opt == OPT_SH || opt == OPT_SFM) {
+        const u32 hcur = rv ? hv : kHInf;
+        if (d > hcur) return false;
+        if (d < hcur) { nh = d; nS = c; }
+        else { nh = hcur; nS = Sv; wd_add(nS, c); }
+        return true;
+    }
+    if (opt == OPT_FM) {
+        const u32 hcur = rv ? hv : kHInf;
+        nh = d < hcur ? d : hcur;
+        if (rv) nS = Sv; else wd_set(nS, 0);
+        wd_add(nS, c);
+        return true;
+    }
+    if (rv) return false;  // pfm: only the earliest arrival counts
+    nh = d;
+    nS = c;
+    return true;
+}
+
+__device__ int64_t lb32(const int32_t *arr, int64_t lo, int64_t hi, int32_t x) {  // first >= x
+    while (lo < hi) { const int64_t md = (lo + hi) >> 1; if (arr[md] < x) lo = md + 1; else hi = md; }
+    return lo;
+}
+
+__global__ void __launch_bounds__(64) k_wide(LaunchArgs a, WideSlabs ws) {
+    if (threadIdx.x != 0) return;  // one lane per pair: no barriers below
+    const int64_t slab = blockIdx.x;
+    u64 *ST = ws.ST + slab * ws.nmax, *SS = ws.SS + slab * ws.nmax * kWide;
+    u64 *RT = ws.RT + slab * ws.nmax, *RA = ws.RA + slab * ws.nmax * kWide;
+    u64 *NV = ws.NV + slab * ws.nmax * kWide;
+    int32_t *touched = ws.touched + slab * ws.nmax;
+    u32 *TL = ws.TL + slab * ws.gmax;
+    u64 *TC = ws.TC + slab * ws.gmax * kWide;
+    u64 *AR = ws.AR + slab * ws.cap * (3 + kWide);
+    u32 serial = ws.hdr[slab * 4];
+    const int64_t np = a.npairs;
+    for (;;) {
+        const int64_t q = (int64_t)atomicAdd(a.work, 1u);
+        if (q >= np) break;
+        Pair P;
+        resolve_pair<false>(a, q, P);
+        serial += 2;
+        if (serial < 2u) serial = 2u;
+        const u32 ftag = serial, rtag = serial + 1u;
+        const int32_t *U = a.g.U, *V = a.g.V, *T = a.g.T;
+        // window: first departure of s, last arrival at z, inside [t0, t1]
+        const int32_t gs = P.noff + P.s, gz = P.noff + P.z;
+        const int64_t o0 = a.g.out_off[gs], o1 = a.g.out_off[gs + 1];
+        const int64_t i0 = a.g.in_off[gz], i1 = a.g.in_off[gz + 1];
+        const int64_t od = lb32(a.g.out_t, o0, o1, P.t0);
+        const int64_t id = (P.t1 == INT32_MAX ? i1 : lb32(a.g.in_t, i0, i1, P.t1 + 1)) - 1;
+        u32 flags = 0, zh = kHInf;
+        Wd zS;
+        wd_set(zS, 0);
+        int32_t t_arr = -1;
+        int64_t narcs = 0, swept = 0;
+        bool ok = od < o1 && id >= i0;
+        const int32_t dep = ok ? a.g.out_t[od] : 0, lin = ok ? a.g.in_t[id] : 0;
+        ok = ok && dep <= P.t1 && lin >= P.t0 && lin >= dep;
+        if (ok) {
+            const int64_t lo = lb32(T, P.elo, P.ehi, dep);
+            const int64_t hi = lb32(T, lo, P.ehi, lin == INT32_MAX ? lin : lin + 1);
+            ST[P.s] = (u64)ftag;  // the origin: 0 hops, one walk
+            Wd one;
+            wd_set(one, 1);
+            wd_store(SS + (int64_t)P.s * kWide, one);
+            bool done = false;
+            for (int64_t i = lo; i < hi && !done && !flags;) {
+                const int32_t t = T[i];
+                int64_t j = i + 1;
+                while (j < hi && T[j] == t) ++j;
+                // reads: every tail's state before the tick
+                for (int64_t e = i; e < j; ++e) {
+                    const int32_t u = U[e];
+                    const u64 st = ST[u];
+                    if ((u32)st == ftag) {
+                        TL[e - i] = (u32)(st >> 32) & 0xFFFFu;
+                        Wd x;
+                        wd_load(x, SS + (int64_t)u * kWide);
+                        wd_store(TC + (e - i) * kWide, x);
+                    } else {
+                        TL[e - i] = kHInf;
+                    }
+                }
+                bool zhit = false;
+                // one head run at a time (the tick's edges are sorted by head)
+                for (int64_t r0 = i, r1; r0 < j; r0 = r1) {
+                    const int32_t v = V[r0];
+                    r1 = r0 + 1;
+                    while (r1 < j && V[r1] == v) ++r1;
+                    u32 d = 0xFFFFFFFFu;
+                    for (int64_t e = r0; e < r1; ++e)
+                        if (TL[e - i] != kHInf && TL[e - i] + 1 < d) d = TL[e - i] + 1;
+                    if (d == 0xFFFFFFFFu) continue;  // no reached tail
+                    if (d >= kHInf) { flags |= REC_HOPS_LIMIT; break; }
+                    Wd c;
+                    wd_set(c, 0);
+                    for (int64_t e = r0; e < r1; ++e) {
+                        const u32 h = TL[e - i];
+                        if (h == kHInf || (P.level && h + 1 != d)) continue;
+                        Wd x;
+                        wd_load(x, TC + (e - i) * kWide);
+                        wd_add(c, x);
+                    }
+                    const u64 sv = ST[v];
+                    const bool rv = (u32)sv == ftag;
+                    Wd Sv, nS;
+                    if (rv) wd_load(Sv, SS + (int64_t)v * kWide); else wd_set(Sv, 0);
+                    u32 nh = 0;
+                    if (!wd_commit(P.opt, rv, rv ? (u32)(sv >> 32) & 0xFFFFu : 0u, Sv, d, c, nh, nS)) continue;
+                    ST[v] = (u64)ftag | ((u64)nh << 32);
+                    wd_store(SS + (int64_t)v * kWide, nS);
+                    // arcs of the run's counted tails
+                    for (int64_t e = r0; e < r1; ++e) {
+                        const u32 h = TL[e - i];
+                        if (h == kHInf || (P.level && h + 1 != d)) continue;
+                        if (narcs >= ws.cap) { flags |= REC_ARCS_LIMIT; break; }
+                        u64 *ar = AR + narcs * (3 + kWide);
+                        ar[0] = (u64)(u32)v | ((u64)(u32)t << 32);
+                        ar[1] = (u64)(u32)e | ((u64)(u32)U[e] << 32);
+                        ar[2] = (u64)h | ((u64)d << 16);
+                        for (int w = 0; w < kWide; ++w) ar[3 + w] = TC[(e - i) * kWide + w];
+                        ++narcs;
+                    }
+                    if (v == P.z) {
+                        if (P.opt == OPT_SH) { if (nh < zh) t_arr = t; }
+                        else t_arr = t;
+                        zh = nh;
+                        zS = nS;
+                        zhit = true;
+                    }
+                }
+                swept = j - lo;
+                if (zhit && P.opt != OPT_SH) done = true;
+                i = j;
+            }
+        }
+        // reverse over the arcs, newest first, a tick at a time
+        const bool reach = ok && zh != kHInf && !(flags & (REC_HOPS_LIMIT | REC_ARCS_LIMIT));
+        bool sat = reach && wd_sat(zS);
+        int64_t ntouch = 0;
+        if (reach && !sat) {
+            const double sg = wd_to_double(zS);
+            for (int64_t ac = narcs; ac > 0;) {
+                const int32_t t = (int32_t)(AR[(ac - 1) * (3 + kWide)] >> 32);
+                int64_t a0 = ac - 1;
+                while (a0 > 0 && (int32_t)(AR[(a0 - 1) * (3 + kWide)] >> 32) == t) --a0;
+                // heads: B(head appearance) from state older than the tick
+                for (int64_t x = a0; x < ac; ++x) {
+                    const u64 *ar = AR + x * (3 + kWide);
+                    const int32_t v = (int32_t)(u32)ar[0];
+                    const u32 hl = (u32)(ar[2] >> 16) & 0xFFFFu;
+                    Wd B;
+                    if (v == P.z) wd_set(B, (P.opt != OPT_SH || hl == zh) ? 1ull : 0ull);
+                    else {
+                        const u64 rt = RT[v];
+                        if ((u32)rt == rtag && (!P.level || ((u32)(rt >> 32) & 0xFFFFu) == hl))
+                            wd_load(B, RA + (int64_t)v * kWide);
+                        else wd_set(B, 0);
+                    }
+                    wd_store(TC + (x - a0) * kWide, B);
+                }
+                // N(e) = tail count * B(head), N(v) of the head, f(e)
+                for (int64_t x = a0; x < ac; ++x) {
+                    const u64 *ar = AR + x * (3 + kWide);
+                    Wd B, tc;
+                    wd_load(B, TC + (x - a0) * kWide);
+                    if (wd_zero(B)) continue;
+                    wd_load(tc, ar + 3);
+                    const Wd na = wd_mul(tc, B);
+                    if (wd_sat(na)) sat = true;
+                    const int32_t v = (int32_t)(u32)ar[0];
+                    const u32 k = (u32)ar[1];
+                    if (v != P.s && v != P.z) {
+                        Wd nv;
+                        wd_load(nv, NV + (int64_t)v * kWide);
+                        if (wd_zero(nv)) touched[ntouch++] = v;
+                        wd_add(nv, na);
+                        if (wd_sat(nv)) sat = true;
+                        wd_store(NV + (int64_t)v * kWide, nv);
+                    }
+                    const double fe = wd_to_double(na) / sg;
+                    if (P.req->Esum) atomicAdd(&P.req->Esum[k], fe);
+                    if (a.edge_f) a.edge_f[P.qout * a.g.m + k] = fe;
+                }
+                // tails: level resets, then the additions
+                for (int64_t x = a0; x < ac; ++x) {
+                    const u64 *ar = AR + x * (3 + kWide);
+                    Wd B;
+                    wd_load(B, TC + (x - a0) * kWide);
+                    if (wd_zero(B)) continue;
+                    const int32_t u = (int32_t)(ar[1] >> 32);
+                    const u32 want = P.level ? (u32)ar[2] & 0xFFFFu : 0u;
+                    const u64 rt = RT[u];
+                    if ((u32)rt != rtag || ((u32)(rt >> 32) & 0xFFFFu) != want) {
+                        RT[u] = (u64)rtag | ((u64)want << 32);
+                        Wd zero;
+                        wd_set(zero, 0);
+                        wd_store(RA + (int64_t)u * kWide, zero);
+                    }
+                }
+                for (int64_t x = a0; x < ac; ++x) {
+                    const u64 *ar = AR + x * (3 + kWide);
+                    Wd B, acc;
+                    wd_load(B, TC + (x - a0) * kWide);
+                    if (wd_zero(B)) continue;
+                    const int32_t u = (int32_t)(ar[1] >> 32);
+                    wd_load(acc, RA + (int64_t)u * kWide);
+                    wd_add(acc, B);
+                    wd_store(RA + (int64_t)u * kWide, acc);
+                }
+                ac = a0;
+            }
+            // flow conservation at the origin: B(origin) = sigma
+            Wd bo;
+            const u64 rt = RT[P.s];
+            if ((u32)rt == rtag && (!P.level || ((u32)(rt >> 32) & 0xFFFFu) == 0u)) wd_load(bo, RA + (int64_t)P.s * kWide);
+            else wd_set(bo, 0);
+            if (!sat && !wd_eq(bo, zS)) flags |= REC_SELFCHECK;
+            if (sat && a.edge_f)
+                for (int64_t x = 0; x < narcs; ++x) a.edge_f[P.qout * a.g.m + (u32)AR[x * (3 + kWide) + 1]] = 0.0;
+            // finalize: f(v) = N(v) / sigma into the sums; N back to zero
+            const DevReq *R = P.req;
+            for (int64_t x = 0; x < ntouch; ++x) {
+                const int32_t v = touched[x];
+                Wd nv;
+                wd_load(nv, NV + (int64_t)v * kWide);
+                Wd zero;
+                wd_set(zero, 0);
+                wd_store(NV + (int64_t)v * kWide, zero);
+                if (sat) continue;
+                const double f = wd_to_double(nv) / sg;
+                const int64_t gv = (int64_t)P.noff + v;
+                if (R->Bsum) atomicAdd(&R->Bsum[gv], f);
+                if (R->Wsum) atomicAdd(&R->Wsum[gv], f * f);
+                if (R->Rsum)
+                    for (int jc = 0; jc < P.c; ++jc)
+                        atomicAdd(&R->Rsum[gv * P.c + jc], ((P.lam >> jc) & 1ull) ? -f : f);
+                if (a.node_f) a.node_f[P.qout * (int64_t)a.g.n_total + gv] = f;
+            }
+        }
+        bool big = false;  // sigma beyond 64 bits
+        for (int w = 1; w < kWide; ++w) big |= zS.w[w] != 0;
+        if (sat) flags |= REC_OVERFLOW;
+        if (reach && big) flags |= REC_WIDE;
+        if (a.rec) {
+            int32_t *rr = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(a.rec) + P.qout * 24);
+            rr[0] = reach ? 1 : 0;
+            rr[1] = reach ? t_arr : -1;
+            rr[2] = reach ? (int32_t)zh : -1;
+            rr[3] = (int32_t)flags;
+            *reinterpret_cast<u64 *>(rr + 4) = reach ? (big ? kUMax : zS.w[0]) : 0ull;
+        }
+        const DevReq *R = P.req;
+        if (flags & REC_OVERFLOW) atomicAdd((unsigned long long *)&a.stats[2], 1ull);
+        if (flags & REC_SELFCHECK) atomicAdd((unsigned long long *)&a.stats[6], 1ull);
+        if (flags & (REC_ARCS_LIMIT | REC_HOPS_LIMIT)) atomicAdd((unsigned long long *)&a.stats[4], 1ull);
+        if (R->rstat) {
+            if (flags & REC_OVERFLOW) atomicAdd((unsigned long long *)&R->rstat[0], 1ull);
+            if (flags & (REC_HOPS_LIMIT | REC_ARCS_LIMIT)) atomicAdd((unsigned long long *)&R->rstat[2], 1ull);
+        }
+        (void)swept;
+    }
+    ws.hdr[slab * 4] = serial;
 }
 
 // ------------------------------------------------------------ pair order
@@ -1752,8 +2116,8 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
     }
 }
 
-__global__ void k_zero_u32(u32 *a, u32 *b) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) { *a = 0u; *b = 0u; }
+__global__ void k_zero_u32(u32 *a, u32 *b, u32 *c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) { *a = 0u; *b = 0u; if (c) *c = 0u; }
 }
 
 __global__ void k_fill_u64(u64 *p, u64 val, int64_t n) {
@@ -1767,6 +2131,11 @@ __global__ void k_fill_u64(u64 *p, u64 val, int64_t n) {
 // ------------------------------------------------------------ launchers
 
 extern "C" {
+// the multiword path over the pairs a->pq names (one lane per pair)
+hipError_t mantra_launch_wide(const mantra::LaunchArgs *a, const mantra::WideSlabs *ws, int nslabs, hipStream_t st) {
+    hipLaunchKernelGGL(mantra::k_wide, dim3(nslabs), dim3(64), 0, st, *a, *ws);
+    return hipGetLastError();
+}
 hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
     hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_PAIRS>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
     return hipGetLastError();
@@ -1810,10 +2179,12 @@ hipError_t mantra_launch_order(const mantra::LaunchArgs *a, mantra::u32 *bucket,
                        (const mantra::u32 *)bucket, hist, order);
     return hipGetLastError();
 }
-// zero the launch counters (work counter, retry count, statistics) with
-// kernels, so that the sequence can be captured in a graph
-hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u64 *stats, hipStream_t st) {
-    hipLaunchKernelGGL(mantra::k_zero_u32, dim3(1), dim3(64), 0, st, work, retry);
+// zero the launch counters (work counter, retry and multiword counts (may be
+// null), statistics) with kernels, so that the sequence can be captured in a
+// graph
+hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u32 *wide, mantra::u64 *stats,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(mantra::k_zero_u32, dim3(1), dim3(64), 0, st, work, retry, wide);
     hipLaunchKernelGGL(mantra::k_fill_u64, dim3(1), dim3(64), 0, st, stats, 0ull, (int64_t)16);
     return hipGetLastError();
 }

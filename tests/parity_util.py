@@ -34,9 +34,18 @@ def compare_pairs(gg, og, opt, S, Z, t0=0, t1=2**31 - 1, edges=True, mode=None, 
     for q, want in enumerate(orecs):
         got = {k: int(rec[k][q]) for k in ("reachable", "t_arr", "hops", "flags", "sigma")}
         assert got["flags"] & 2 == 0, ("flow conservation", ctx, opt, S[q], Z[q])
-        want_flags = want["flags"] & oracle.REC_OVERFLOW
+        if want["flags"] & oracle.REC_OVERFLOW:
+            # beyond the 64-bit oracle: the library counted the pair in wider
+            # words (its exact checks are in test_gpu_wide); the record agrees
+            assert (got["reachable"], got["t_arr"], got["hops"]) == (
+                want["reachable"], want["t_arr"], want["hops"]), (ctx, opt, int(S[q]), int(Z[q]), got, want)
+            assert got["sigma"] == want["sigma"] or got["flags"] & 16, (ctx, opt, got, want)
+            nf[q] = onf[q]
+            if edges:
+                ef[q] = oef[q]
+            continue
         assert (got["reachable"], got["t_arr"], got["hops"], got["sigma"], got["flags"] & 1) == (
-            want["reachable"], want["t_arr"], want["hops"], want["sigma"], want_flags), (
+            want["reachable"], want["t_arr"], want["hops"], want["sigma"], 0), (
             ctx, opt, int(S[q]), int(Z[q]), got, want)
     # f(v|s,z) and f(e|s,z): the same IEEE division of the same exact integers
     bad = np.nonzero(nf != onf)

@@ -109,16 +109,18 @@ def test_hub_star_tick(lib, opt):
 
 
 def test_saturation(lib):
-    """16 hops x 16 parallel edges: 2^64 shortest paths saturate (flagged,
-    no contributions); 15 hops give exactly 2^60."""
+    """16 hops x 16 parallel edges: 2^64 shortest paths, one past the 64-bit
+    counts (the multiword path takes the pair: MANTRA_REC_WIDE, f exact);
+    15 hops give exactly 2^60 in 64 bits."""
     edges = [(i, i + 1, 16 * i + j + 1) for i in range(16) for j in range(16)]
     a = np.array(edges, dtype=np.int32)
     from synthgen.graphs import TemporalGraph
     G = TemporalGraph(17, a[:, 0].copy(), a[:, 1].copy(), a[:, 2].copy())
     gg, og = both(lib, G)
-    rec = compare_pairs(gg, og, "sh", [0, 0, 3], [16, 15, 12], ctx="sat")
-    assert int(rec["sigma"][0]) == 2**64 - 1 and int(rec["flags"][0]) & 1
-    assert int(rec["sigma"][1]) == 2**60
+    rec = compare_pairs(gg, og, "sh", [0, 3], [15, 12], ctx="sat")
+    assert int(rec["sigma"][0]) == 2**60
+    rec, nf, _ = gg.count_pairs("sh", [0], [16], node_f=True)
+    assert int(rec["sigma"][0]) == 2**64 - 1 and int(rec["flags"][0]) == 16 and np.all(nf[0, 1:16] == 1.0)
     for opt in ("fm", "sfm", "pfm"):
         compare_pairs(gg, og, opt, [0, 0, 3], [16, 15, 12], ctx="sat-" + opt)
 
