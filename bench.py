@@ -54,9 +54,9 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip
 # counter bytes that the same counters give for a plain copy of known size),
 # valid for the kernel source with this SHA-256 only.
 TRAFFIC = {
-    "sweep_sha256": "d95faf3201ac922de1f8bf3353b7c2fdc5e59f17bb1599f20b7127d1d0c2cd42",
-    "fetch_bytes_per_launch": 4.9217e+11,   # 2.40324e+08 KiB x 1.99995
-    "write_bytes_per_launch": 7.8486e+10,   # 7.66463e+07 KiB x 1.00000
+    "sweep_sha256": "f3afe1cb98aaae36bd63b931b09d7ef3b06c46b664f8e26500aae91edfe44173",
+    "fetch_bytes_per_launch": 4.9199e+11,   # 2.40238e+08 KiB x 1.99995
+    "write_bytes_per_launch": 7.8481e+10,   # 7.66412e+07 KiB x 1.00000
 }
 
 
