@@ -1,8 +1,11 @@
 """Benchmark of the temporal-betweenness hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--slabs N]
-                    [--no-forms] [--no-serve] [--no-trk] [--no-distances] [--no-cpu-baseline]
+                    [--no-forms] [--no-serve] [--no-trk] [--no-rtb] [--no-distances]
+                    [--no-cpu-baseline]
     python bench.py --calibrate-copy     (plain copy kernel for the traffic counters)
+    python bench.py --batching           (n = 10^6 Algorithm 1 and the 256 packed graphs)
+    python bench.py --serve-only [--serve-workload NAME] [--serve-requests K]
 
 Workload "mid-chunglu-n50k": directed Chung-Lu temporal graph (degree
 exponent 2.3, n = 50,000, |E| = 2,000,000, bursty Pareto(1.5) renewal
@@ -25,6 +28,7 @@ Prints one JSON line (value: sampled pairs/s of the steps) with
    eps in {0.01, 0.005}) through the serving scheduler: p50/p99 latency;
  - "trk": the same step with the TRK estimator (one sampled optimal walk per
    pair instead of the dependency sweep);
+ - "rtb": the RTB estimator (sampled sources, all targets) on the same graph;
  - "distances": Algorithm 2 (sampled temporal distance metrics) from 256
    sources, the paper's seed count, for sh and pfm on the same graph;
  - "cpu_baseline": the oracle on the host's cores, on a bounded sample.
@@ -129,15 +133,47 @@ def trk_step(gg, torch, seed, steps=3):
     TRK estimator."""
     gg.run(OPT, fixed_r=R_PER_STEP, seed=seed + 999, c=C, edges=True, trk=True)
     torch.cuda.synchronize()
+    tot = {"sweep_ms": 0.0, "launches": 0, "window_edges": 0, "arcs": 0, "touched_nodes": 0, "touched_edges": 0}
     t0 = time.perf_counter()
-    ms = 0.0
     for k in range(steps):
         gg.run(OPT, fixed_r=R_PER_STEP, seed=seed + k, c=C, edges=True, trk=True)
-        ms += gg.last_timing()["sweep_ms"]
+        t = gg.last_timing()
+        for key in tot:
+            tot[key] += t[key]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return {"steps": steps, "pairs_per_s": R_PER_STEP * steps / wall, "ms_per_step": wall * 1e3 / steps,
-            "sweep_ms_per_launch": ms / steps}
+            "sweep_ms_per_launch": tot["sweep_ms"] / max(1, tot["launches"]), "hbm_frac": hbm_frac(tot, C),
+            "kernel": "mantra::k_sweep<2>"}
+
+
+def rtb_step(gg, torch, seed, r=2000, steps=2):
+    """The bench step's settings (sfm, c = 25, node + edge sums) with the RTB
+    estimator: r sampled sources per step, each swept to the end of the span
+    with the dependencies of every reached target."""
+    gg.run(OPT, fixed_r=256, seed=seed + 999, c=C, edges=True, rtb=True)
+    torch.cuda.synchronize()
+    tot = {"sweep_ms": 0.0, "launches": 0, "window_edges": 0, "arcs": 0, "touched_nodes": 0, "touched_edges": 0}
+    t0 = time.perf_counter()
+    for k in range(steps):
+        gg.run(OPT, fixed_r=r, seed=seed + k, c=C, edges=True, rtb=True)
+        t = gg.last_timing()
+        for key in tot:
+            tot[key] += t[key]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"steps": steps, "sources_per_step": r, "sources_per_s": r * steps / wall,
+            "ms_per_step": wall * 1e3 / steps, "sweep_ms_per_launch": tot["sweep_ms"] / max(1, tot["launches"]),
+            "temporal_edges_per_s": tot["window_edges"] / (tot["sweep_ms"] / 1e3),
+            "hbm_frac": hbm_frac(tot, C), "kernel": "mantra::k_sweep<3>"}
+
+
+def hbm_frac(t, c):
+    """Algorithmic bytes of a call's sweep launches over their summed HIP-event
+    duration, as a fraction of the HBM peak."""
+    if t["sweep_ms"] <= 0:
+        return None
+    return algorithmic_bytes(t, c) / (t["sweep_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
 
 
 def distances(gg, torch, seed, r=256):
@@ -151,6 +187,8 @@ def distances(gg, torch, seed, r=256):
         wall = time.perf_counter() - t0
         out[opt] = {"sources": r, "wall_ms": wall * 1e3, "gpu_ms": res["gpu_ms"],
                     "temporal_edges_per_s": res["window_edges"] / (res["gpu_ms"] / 1e3),
+                    # 12 B per swept edge, and the list of reached nodes written and read back
+                    "hbm_frac": (12 * res["window_edges"] + 8 * res["reached_pairs"]) / (res["gpu_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
                     "d_lb": res["d_lb"], "d_tau": res["d_tau"], "zeta": res["zeta"], "psi": res["psi"],
                     "rho": res["rho"]}
     return out
@@ -206,6 +244,70 @@ def serve(gg, G, torch, n_req=12, rate=50.0, seed=4002, workload_name=WORKLOAD):
             "workload": workload_name + ", windows/optimalities/eps of the serving recipe"}
 
 
+def batching(pk, torch, seed):
+    """The batching workloads, outside the default run (minutes of graph
+    generation): one launch of r = 2,000 sh pairs per graph over the 256
+    graphs of packed-256; Algorithm 1 at eps = 0.005, delta = 0.1, c = 16,
+    s1 = 4,096 on big-chunglu-n1m for pfm, each round one replayed HIP graph
+    at the autotuned grid; fm on the same graph as a fixed sample of one
+    first round (4,096 pairs) at that grid, since its walk counts pass 2^64
+    (and 2^256) and Algorithm 1 then stops with MANTRA_E_OVERFLOW."""
+    from synthgen import workload
+    out = {}
+
+    def note(key, d):
+        out[key] = d
+        print("%s: %s" % (key, json.dumps(d)), file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    gs = workload("packed-256")
+    pg = pk.Graph.packed(gs)
+    print("packed-256 resident after %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    r = 2000
+    pg.run("sh", fixed_r=64, seed=seed + 99, c=C)
+    for k in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, res = pg.run("sh", fixed_r=r, seed=seed + k, c=C, raise_on_error=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        t = pg.last_timing()
+        note("packed_sh", {
+            "workload": "packed-256", "graphs": len(gs), "edges": int(sum(g.m for g in gs)), "pairs_per_graph": r,
+            "pairs": r * len(gs), "rc": res["rc"], "n_overflow": res["n_overflow"], "wall_s": wall,
+            "pairs_per_s": r * len(gs) / wall, "sweep_ms": t["sweep_ms"], "launches": t["launches"],
+            "temporal_edges_per_s": t["window_edges"] / max(t["sweep_ms"] / 1e3, 1e-9),
+            "hbm_frac": hbm_frac(t, C), "grid_balance": t["balance"], "launch": pg.get_launch()})
+    del pg, gs
+    t0 = time.perf_counter()
+    G = workload("big-chunglu-n1m")
+    gg = pk.Graph.of(G)
+    print("big-chunglu-n1m resident after %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    gg.set_launch(graph_rounds=True)
+    t0 = time.perf_counter()
+    tuned = gg.autotune("pfm", sample_pairs=2048, seed=seed + 7)
+    print("autotuned in %.1f s: %s" % (time.perf_counter() - t0, json.dumps(tuned)), file=sys.stderr, flush=True)
+
+    def timed(opt, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, res = gg.run(opt, c=16, raise_on_error=False, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        t = gg.last_timing()
+        pairs = res["samples"] + res["s_boot"]
+        return {"workload": "big-chunglu-n1m", "optimality": opt, "c": 16, "rc": res["rc"],
+                "rounds": res["rounds"], "samples": res["samples"], "s_boot": res["s_boot"], "omega": res["omega"],
+                "xi": res["xi"], "n_overflow": res["n_overflow"], "wall_s": wall, "pairs_per_s": pairs / wall,
+                "sweep_ms": t["sweep_ms"], "launches": t["launches"],
+                "temporal_edges_per_s": t["window_edges"] / max(t["sweep_ms"] / 1e3, 1e-9),
+                "hbm_frac": hbm_frac(t, 16), "grid_balance": t["balance"], "launch": tuned}
+
+    note("n1m_pfm", dict(timed("pfm", eps=0.005, delta=0.1, seed=seed, s1=4096), eps=0.005, delta=0.1, s1=4096))
+    note("n1m_fm_first_round", dict(timed("fm", fixed_r=4096, seed=seed), fixed_r=4096))
+    return out
+
+
 def calibrate_copy(torch):
     """A plain device-to-device copy of known size, for scaling the traffic
     counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
@@ -233,6 +335,9 @@ def main():
     ap.add_argument("--serve-workload", default=WORKLOAD)
     ap.add_argument("--serve-requests", type=int, default=12)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--batching", action="store_true",
+                    help="only the batching workloads (n = 10^6 Algorithm 1, packed-256; prints {\"batching\": ...})")
+    ap.add_argument("--no-rtb", action="store_true")
     ap.add_argument("--slabs", type=int, default=0,
                     help="fixed number of persistent workgroups instead of the autotuner's pick "
                          "(profiling runs: every sweep launch of the run is then alike)")
@@ -250,6 +355,9 @@ def main():
     import paper_2304_08356_amd as pk
     from synthgen import workload
 
+    if args.batching:
+        print(json.dumps({"batching": batching(pk, torch, args.seed)}), flush=True)
+        return
     if args.serve_only:
         t0 = time.perf_counter()
         G = workload(args.serve_workload)
@@ -322,6 +430,8 @@ def main():
         out["serve"] = serve(gg, G, torch, n_req=args.serve_requests)
     if not args.no_trk:
         out["trk"] = trk_step(gg, torch, args.seed)
+    if not args.no_rtb:
+        out["rtb"] = rtb_step(gg, torch, args.seed)
     if not args.no_distances:
         out["distances"] = distances(gg, torch, args.seed)
     if not args.no_cpu_baseline:

@@ -37,6 +37,20 @@ namespace mantra {
 
 // ---------------------------------------------------------------- helpers
 
+// The kernels' one by-value argument sits at offset 0 of the kernel-argument
+// segment (constant memory).  The sweep reads its fields there, where they
+// are used, through a copy of the segment pointer that the compiler cannot
+// see through, taken once per pair: each field is then loaded per pair
+// (scalar loads) instead of all 84 dwords being kept live across the sweep
+// loops, which spilled scalar registers into vector-register lanes inside
+// the hot loops.
+typedef const __attribute__((address_space(4))) LaunchArgs KArgs;
+__device__ __forceinline__ KArgs &launch_args() {
+    KArgs *p = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *p;
+}
+
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 __device__ __forceinline__ u64 ballot(bool p) { return (u64)__ballot(p ? 1 : 0); }
 __device__ __forceinline__ int mbcnt(u64 m) {
@@ -266,7 +280,7 @@ __device__ __forceinline__ bool head_commit(int opt, bool rv, u32 hv, u64 Sv, u3
 enum { FWD_PAIR = 0, FWD_DIST = 1, FWD_RTB = 2 };
 
 template <int FM>
-__device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
+__device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
                               int64_t g0, int64_t g1, int32_t t, u32 &agstamp, FwdOut &o,
                               u32 &zh, u64 &zS, bool &zhit) {
     constexpr bool SINGLE = FM != FWD_PAIR;
@@ -438,7 +452,7 @@ __device__ void fwd_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
 
 // edges of the batch at b: lane l holds edge b + l (past the window: time
 // INT32_MAX, head -1); tnext = time of edge b + 64, INT32_MAX past the window
-__device__ __forceinline__ void load_batch(const LaunchArgs &a, const Pair &P, int64_t b, int32_t &t, int32_t &u,
+__device__ __forceinline__ void load_batch(KArgs &a, const Pair &P, int64_t b, int32_t &t, int32_t &u,
                                            int32_t &v, int32_t &tnext) {
     const int l = lane_id();
     const int64_t i = b + l;
@@ -457,7 +471,7 @@ __device__ __forceinline__ void load_batch(const LaunchArgs &a, const Pair &P, i
 // from the committing lane's registers.  Maximal runs of ticks that read no
 // commit made inside the run ("segments") are processed together.
 template <int FM>
-__device__ void forward(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H, FwdLds &L,
+__device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H, FwdLds &L,
                         u32 &agstamp, FwdOut &o) {
     constexpr bool SINGLE = FM != FWD_PAIR;
     static_assert(kE == 1, "the forward sweep is written for one edge per lane");
@@ -772,7 +786,7 @@ struct RevCtx {
 };
 
 // alive set: nodes with a non-zero dependency accumulator for this pair
-__device__ __forceinline__ bool alive_test(const LaunchArgs &a, const u32 *bm, const RevCtx &X, int32_t v) {
+__device__ __forceinline__ bool alive_test(KArgs &a, const u32 *bm, const RevCtx &X, int32_t v) {
     if (a.lds_bitmap) return bm_test(bm, v);
     if (X.alive_all) return true;
     u32 sl = (((u32)v) * 2654435761u) >> (32 - 9);
@@ -784,7 +798,7 @@ __device__ __forceinline__ bool alive_test(const LaunchArgs &a, const u32 *bm, c
     }
     return false;
 }
-__device__ __forceinline__ bool alive_set(const LaunchArgs &a, u32 *bm, int32_t v) {
+__device__ __forceinline__ bool alive_set(KArgs &a, u32 *bm, int32_t v) {
     if (a.lds_bitmap) { atomicOr(&bm[v >> 5], 1u << (v & 31)); return true; }
     u32 sl = (((u32)v) * 2654435761u) >> (32 - 9);
     for (int it = 0; it < kAliveN / 2; ++it) {
@@ -800,7 +814,7 @@ __device__ __forceinline__ bool alive_set(const LaunchArgs &a, u32 *bm, int32_t 
     return false;  // too full: the caller switches to "everything alive"
 }
 
-__device__ __forceinline__ void rev_contrib(const LaunchArgs &a, const Pair &P, const Slab &S,
+__device__ __forceinline__ void rev_contrib(KArgs &a, const Pair &P, const Slab &S,
                                             RevCtx &X, bool act, u64 B, u64 tc, int32_t v, u32 k) {
     // N(arc) = tail count * B(head); N(v) += N(arc); f(e) = N(arc) / sigma
     bool first = false, wrap = false;
@@ -837,7 +851,7 @@ __device__ __forceinline__ u64 head_B(const Pair &P, const RevCtx &X, int32_t v,
 
 // a tick with more arcs than one batch: heads first (all read state older
 // than the tick), then level resets and additions at the tails
-__device__ void rev_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, RevCtx &X,
+__device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, RevCtx &X,
                               int64_t a0, int64_t a1) {
     const int l = lane_id();
     for (int64_t sb = a0; sb < a1; sb += kWave) {
@@ -895,7 +909,7 @@ __device__ void rev_long_tick(const LaunchArgs &a, const Pair &P, const Slab &S,
     __syncthreads();
 }
 
-__device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t bmw, RevLds &L,
+__device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t bmw, RevLds &L,
                         u32 &stamp, int64_t narcs, RevCtx &X) {
     const int l = lane_id();
     // the alive set starts empty
@@ -1082,8 +1096,8 @@ __device__ void reverse(const LaunchArgs &a, const Pair &P, const Slab &S, u32 *
 // ------------------------------------------------------------ the kernel
 
 // SINGLE (the distance kernel): slots are single sources, no target
-template <bool SINGLE = false>
-__device__ void resolve_pair(const LaunchArgs &a, int64_t slot, Pair &P) {
+template <bool SINGLE = false, class A>
+__device__ void resolve_pair(A &a, int64_t slot, Pair &P) {
     // a retry launch names the original launch slots through pq
     const int64_t q = a.pq ? (int64_t)a.pq[slot] : slot;
     int r = 0;
@@ -1193,7 +1207,7 @@ __device__ void distance_hist(const Pair &P, const Slab &S, const Hub &H, u32 *l
 // tail ids), whose running total exceeds r.  Each step's total must equal
 // the count it stands for (sigma_sz first, then the tail count of the arc
 // taken); returns false where it does not.
-__device__ bool trk_walk(const LaunchArgs &a, const Pair &P, const Slab &S, int64_t narcs, u32 zh, int32_t t_arr,
+__device__ bool trk_walk(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, u32 zh, int32_t t_arr,
                          u64 sigma, RevCtx &X) {
     const int l = lane_id();
     const DevReq *R = P.req;
@@ -1302,7 +1316,7 @@ __device__ bool trk_walk(const LaunchArgs &a, const Pair &P, const Slab &S, int6
 // into the tail's state; level resets as in the pair reverse.  The origin's
 // value must come out as the number of reached targets.  Returns false if
 // a count on the way saturated.
-__device__ bool rev_rtb(const LaunchArgs &a, const Pair &P, const Slab &S, int64_t narcs, RevCtx &X) {
+__device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, RevCtx &X) {
     const int l = lane_id();
     const DevReq *R = P.req;
     const double n1 = (double)(P.ng - 1);
@@ -1397,14 +1411,7 @@ __device__ bool rev_rtb(const LaunchArgs &a, const Pair &P, const Slab &S, int64
 // every slot is a single source; MODE_TRK: pairs, f = visits of one sampled
 // optimal walk.  Each mode is a kernel of its own, so that the pair sweep
 // keeps its register allocation.
-template <int MODE>
-__global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
-    constexpr bool RTB = MODE == MODE_RTB;
-    constexpr bool SINGLE = MODE == MODE_DISTANCES || RTB;
-    constexpr bool TRK = MODE == MODE_TRK;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int l = lane_id();
-    const int64_t slab = blockIdx.x;
+__device__ __forceinline__ Slab slab_of(KArgs &a, int64_t slab) {
     Slab S;
     S.F = a.sl.F + slab * a.sl.nmax * 2;
     S.R = S.F;  // the reverse state shares the forward's words (their tags differ)
@@ -1417,21 +1424,41 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
     S.XS = a.sl.XS + slab * a.sl.gmax * 2;
     S.T = a.sl.T ? a.sl.T + slab * a.sl.nmax * 2 : nullptr;
     S.hdr = a.sl.hdr + slab * 4;
+    return S;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg) {
+    constexpr bool RTB = MODE == MODE_RTB;
+    constexpr bool SINGLE = MODE == MODE_DISTANCES || RTB;
+    constexpr bool TRK = MODE == MODE_TRK;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int l = lane_id();
+    const int64_t slab = blockIdx.x;
+    (void)a_arg;
     TabLds &tab = *reinterpret_cast<TabLds *>(lds_raw);
     u32 *bm = reinterpret_cast<u32 *>(lds_raw + sizeof(TabLds));
-    const int64_t bmw = a.lds_bitmap ? (a.sl.nmax + 31) / 32 : 0;
-    Hub H;
-    H.K = a.lds_bitmap ? a.hub_nodes : 0;
-    H.s = reinterpret_cast<u64 *>(lds_raw + sizeof(TabLds) + ((bmw * 4 + 7) & ~7ll));
-    H.h = reinterpret_cast<u32 *>(H.s + H.K);
     for (int i = l; i < kFwN; i += kWave) { tab.r.tb_key[i] = 0; }
-    u32 serial = S.hdr[0];
-    u32 agstamp = S.hdr[1];
+    u32 serial, agstamp;
+    int64_t np;
+    {
+        KArgs &a = launch_args();
+        const u32 *hdr = a.sl.hdr + slab * 4;
+        serial = hdr[0];
+        agstamp = hdr[1];
+        np = a.npairs_dev ? *a.npairs_dev : a.npairs;
+    }
     u32 stamp = 1;  // reverse table stamps (0 = empty)
     const u64 t_begin = wall_clock64();
     __syncthreads();
-    const int64_t np = a.npairs_dev ? *a.npairs_dev : a.npairs;
     for (;;) {
+        KArgs &a = launch_args();
+        const Slab S = slab_of(a, slab);
+        const int64_t bmw = a.lds_bitmap ? (a.sl.nmax + 31) / 32 : 0;
+        Hub H;
+        H.K = a.lds_bitmap ? a.hub_nodes : 0;
+        H.s = reinterpret_cast<u64 *>(lds_raw + sizeof(TabLds) + ((bmw * 4 + 7) & ~7ll));
+        H.h = reinterpret_cast<u32 *>(H.s + H.K);
         u32 qq = 0;
         if (l == 0) qq = atomicAdd(a.work, 1u);
         const int64_t q = a.qbase + (int64_t)(u32)uni((int)qq);
@@ -1616,9 +1643,11 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a) {
         }
         __syncthreads();
     }
+    KArgs &a = launch_args();
     if (l == 0) {
-        S.hdr[0] = serial;
-        S.hdr[1] = agstamp;
+        u32 *hdr = a.sl.hdr + slab * 4;
+        hdr[0] = serial;
+        hdr[1] = agstamp;
         // load balance of the persistent grid: busy time of this slab, the
         // last finish and the first start (constant-rate wall clock)
         const u64 t_end = wall_clock64();
@@ -1743,7 +1772,9 @@ __device__ int64_t lb32(const int32_t *arr, int64_t lo, int64_t hi, int32_t x) {
     return lo;
 }
 
-__global__ void __launch_bounds__(64) k_wide(LaunchArgs a, WideSlabs ws) {
+__global__ void __launch_bounds__(64) k_wide(LaunchArgs a_arg, WideSlabs ws) {
+    (void)a_arg;
+    KArgs &a = launch_args();
     if (threadIdx.x != 0) return;  // one lane per pair: no barriers below
     const int64_t slab = blockIdx.x;
     u64 *ST = ws.ST + slab * ws.nmax, *SS = ws.SS + slab * ws.nmax * kWide;
