@@ -58,9 +58,9 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip
 # counter bytes that the same counters give for a plain copy of known size),
 # valid for the kernel source with this SHA-256 only.
 TRAFFIC = {
-    "sweep_sha256": "f3afe1cb98aaae36bd63b931b09d7ef3b06c46b664f8e26500aae91edfe44173",
-    "fetch_bytes_per_launch": 4.9199e+11,   # 2.40238e+08 KiB x 1.99995
-    "write_bytes_per_launch": 7.8481e+10,   # 7.66412e+07 KiB x 1.00000
+    "sweep_sha256": "a67e4431b25d0edfa880a551c0bc9657cf95bcc31eb000ac9cc62522fbd7ba2c",
+    "fetch_bytes_per_launch": 4.9179e+11,   # 2.4014e+08 KiB x 1.99995
+    "write_bytes_per_launch": 7.8463e+10,   # 7.6624e+07 KiB x 1.00000
 }
 
 
