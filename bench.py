@@ -285,7 +285,7 @@ def batching(pk, torch, seed):
     print("big-chunglu-n1m resident after %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
     gg.set_launch(graph_rounds=True)
     t0 = time.perf_counter()
-    tuned = gg.autotune("pfm", sample_pairs=2048, seed=seed + 7)
+    tuned = gg.autotune("pfm", seed=seed + 7)
     print("autotuned in %.1f s: %s" % (time.perf_counter() - t0, json.dumps(tuned)), file=sys.stderr, flush=True)
 
     def timed(opt, **kw):

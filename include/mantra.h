@@ -298,12 +298,14 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg);
 int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg);
 
 /* Autotuner: times the sweep on a calibration sample of sample_pairs pairs
- * (0: twice the automatic grid) drawn for optimality opt from the bootstrap
- * stream of seed, under candidate grid sizes (all, 7/8, 3/4, 5/8 and 1/2 of
- * the resident workgroups) and both pair orders, then with 256 hub nodes in
- * LDS at the best of those, then keeps the fastest as the
- * graph's launch configuration and writes it to *best (may be NULL).
- * Blocking; results of later calls do not depend on the choice. */
+ * (0: four times the largest candidate grid) drawn for optimality opt from
+ * the bootstrap stream of seed, under candidate grid sizes (1, 7/8, 3/4, 5/8
+ * and 1/2 of the automatic grid; where device memory, not residency, bounds
+ * that grid, also 3/2 and 2 times it, up to the resident workgroups, with
+ * smaller arc buffers) and both pair orders, then with 256 hub nodes in LDS
+ * at the best of those, then keeps the fastest as the graph's launch
+ * configuration and writes it to *best (may be NULL).  Blocking; results of
+ * later calls do not depend on the choice. */
 int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint64_t seed,
                     mantra_launch_config *best);
 

@@ -3,6 +3,8 @@
 // sampling driver of Algorithm 1 (blocking calls and the serving scheduler
 // share the per-request state machine defined here).
 
+#include <functional>
+
 #include "mantra_int.h"
 
 namespace mantra {
@@ -295,23 +297,28 @@ static size_t pool_budget(const mantra_graph *g) {
     return (size_t)std::min(0.45 * (double)tot, 0.7 * (double)(fr + own));
 }
 
-int auto_slabs(const mantra_graph *g) {
-    if (g->user_slabs > 0) return g->user_slabs;
+// sweep workgroups the device holds at once (registers and LDS, as the
+// runtime reports them)
+static int resident_slabs(const mantra_graph *g) {
     hipDeviceProp_t pr;
     hipGetDeviceProperties(&pr, g->device);
     int cus = pr.multiProcessorCount > 0 ? pr.multiProcessorCount : 256;
-    // resident workgroups per CU (registers and LDS), as the runtime reports
     size_t lb = lds_bytes(g);
     int per_cu = mantra_sweep_occupancy(lb);
     if (per_cu <= 0) {
         int by_lds = (int)((160 * 1024) / (lb ? lb : 1));
         per_cu = std::min(8, std::max(1, by_lds));
     }
+    return cus * per_cu;
+}
+
+int auto_slabs(const mantra_graph *g) {
+    if (g->user_slabs > 0) return g->user_slabs;
     // large graphs: the per-node state in a quarter of the pool budget bounds
     // the number of pairs in flight; the rest holds their arc records, whose
     // room decides how many pairs must be re-run with a full-window buffer
     int64_t by_mem = (int64_t)(pool_budget(g) / 4 / slab_state_bytes(g));
-    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, by_mem));
+    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)resident_slabs(g), by_mem));
 }
 
 static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
@@ -455,7 +462,18 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     if ((int64_t)ns > slots) ns = (int)slots;
     if (g->per_pair) ns = 1;
     int64_t cap = auto_cap(g, auto_slabs(g));
-    int rc = pool_ensure(g, g->pool, std::max(ns, g->pool.nslabs), std::max(cap, g->pool.cap));
+    // the pool grows to cover every grid used so far, unless the union of
+    // the largest grid and the largest arc buffer exceeds the budget (grids
+    // that trade pairs in flight for arc room, as the autotuner's): then it
+    // is sized for this launch alone
+    int want_ns = std::max(ns, g->pool.nslabs);
+    int64_t want_cap = std::max(cap, g->pool.cap);
+    if ((g->pool.nslabs < ns || g->pool.cap < cap) &&
+        (double)want_ns * ((double)slab_state_bytes(g) + (double)want_cap * 32.0) > (double)pool_budget(g)) {
+        want_ns = ns;
+        want_cap = cap;
+    }
+    int rc = pool_ensure(g, g->pool, want_ns, want_cap);
     if (rc) return rc;
     if (sp.mode == MODE_RTB && (rc = pool_need_T(g, g->pool))) return rc;
     int64_t rcap = g->dreq_cap;
@@ -963,16 +981,28 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
     g->user_cap = 0;
     g->hub_nodes = 0;
     const int full = auto_slabs(g);
-    if (sample <= 0) sample = std::max<int64_t>(2 * (int64_t)full, 256);
+    std::vector<int> slabs;
+    // a grid bounded by memory (large graphs) is also tried with up to twice
+    // the pairs in flight: their state then takes up to half of the pool
+    // budget and their arc buffers are smaller (pairs that overflow them are
+    // re-run after the launch, inside the timed call)
+    const int res = resident_slabs(g);
+    if (full < res) {
+        slabs.push_back(std::min(res, 2 * full));
+        slabs.push_back(std::min(res, (3 * full) / 2));
+    }
+    for (int x : {full, (7 * full) / 8, (3 * full) / 4, (5 * full) / 8, full / 2}) slabs.push_back(std::max(1, x));
+    std::sort(slabs.begin(), slabs.end(), std::greater<int>());
+    slabs.erase(std::unique(slabs.begin(), slabs.end()), slabs.end());
+    // several pairs per workgroup at the largest grid, so that the timing is
+    // not only the longest pair's
+    if (sample <= 0) sample = std::max<int64_t>(4 * (int64_t)slabs.front(), 256);
     mantra_request rq;
     memset(&rq, 0, sizeof rq);
     rq.opt = opt;
     rq.t0 = 0;
     rq.t1 = INT32_MAX;
     rq.seed = seed;
-    std::vector<int> slabs = {full, std::max(1, (7 * full) / 8), std::max(1, (3 * full) / 4),
-                              std::max(1, (5 * full) / 8), std::max(1, full / 2)};
-    slabs.erase(std::unique(slabs.begin(), slabs.end()), slabs.end());
     double best_ms = INFINITY;
     int best_slabs = full, best_order = MANTRA_ORDER_LONGEST_FIRST, best_hub = 0;
     int rc = MANTRA_OK;
