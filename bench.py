@@ -59,8 +59,8 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip
 # valid for the kernel source with this SHA-256 only.
 TRAFFIC = {
     "sweep_sha256": "a67e4431b25d0edfa880a551c0bc9657cf95bcc31eb000ac9cc62522fbd7ba2c",
-    "fetch_bytes_per_launch": 4.9179e+11,   # 2.4014e+08 KiB x 1.99995
-    "write_bytes_per_launch": 7.8463e+10,   # 7.6624e+07 KiB x 1.00000
+    "fetch_bytes_per_launch": 4.9185e+11,   # 2.40167e+08 KiB x 1.99995
+    "write_bytes_per_launch": 7.8464e+10,   # 7.66249e+07 KiB x 1.00000
 }
 
 
