@@ -30,7 +30,8 @@ Prints one JSON line (value: sampled pairs/s of the steps) with
    pair instead of the dependency sweep);
  - "rtb": the RTB estimator (sampled sources, all targets) on the same graph;
  - "distances": Algorithm 2 (sampled temporal distance metrics) from 256
-   sources, the paper's seed count, for sh and pfm on the same graph;
+   sources, the paper's seed count, for sh and pfm on the same graph, with
+   the oracle's per-source distances timed beside it on 32 sources;
  - "cpu_baseline": the oracle on the host's cores, on a bounded sample.
 """
 import argparse
@@ -142,9 +143,10 @@ def trk_step(gg, torch, seed, steps=3):
             tot[key] += t[key]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return {"steps": steps, "pairs_per_s": R_PER_STEP * steps / wall, "ms_per_step": wall * 1e3 / steps,
-            "sweep_ms_per_launch": tot["sweep_ms"] / max(1, tot["launches"]), "hbm_frac": hbm_frac(tot, C),
-            "kernel": "mantra::k_sweep<2>"}
+    out = {"steps": steps, "pairs_per_s": R_PER_STEP * steps / wall, "ms_per_step": wall * 1e3 / steps,
+           "sweep_ms_per_launch": tot["sweep_ms"] / max(1, tot["launches"]), "hbm_frac": hbm_frac(tot, C),
+           "kernel": "mantra::k_sweep<2>"}
+    return out
 
 
 def rtb_step(gg, torch, seed, r=2000, steps=2):
@@ -176,8 +178,9 @@ def hbm_frac(t, c):
     return algorithmic_bytes(t, c) / (t["sweep_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
 
 
-def distances(gg, torch, seed, r=256):
-    """Algorithm 2 from r sources (sh and pfm, tau = 0.9), blocking calls."""
+def distances(gg, torch, seed, r=256, og=None):
+    """Algorithm 2 from r sources (sh and pfm, tau = 0.9), blocking calls;
+    beside it the oracle's per-source distances on a bounded sample."""
     out = {}
     for opt in ("sh", "pfm"):
         gg.distances(opt, 16, seed=seed + 1)  # warm
@@ -191,6 +194,16 @@ def distances(gg, torch, seed, r=256):
                     "hbm_frac": (12 * res["window_edges"] + 8 * res["reached_pairs"]) / (res["gpu_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
                     "d_lb": res["d_lb"], "d_tau": res["d_tau"], "zeta": res["zeta"], "psi": res["psi"],
                     "rho": res["rho"]}
+        if og is not None:
+            from oracle import distances as odist
+            threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+            S = odist.draw_sources(seed, og.n, 32)
+            t0 = time.perf_counter()
+            odist.source_hops(og, opt, S, nthreads=threads)
+            dt = time.perf_counter() - t0
+            out[opt]["cpu_baseline"] = {"value": len(S) / dt, "unit": "sources/s", "cores": threads,
+                                        "kind": "oracle",
+                                        "sample": "first %d sources of the same source stream, %.1f s" % (len(S), dt)}
     return out
 
 
@@ -428,12 +441,16 @@ def main():
         out["forms"] = forms(gg, torch, args.seed)
     if not args.no_serve:
         out["serve"] = serve(gg, G, torch, n_req=args.serve_requests)
+    og = None
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Graph.of(G)
     if not args.no_trk:
         out["trk"] = trk_step(gg, torch, args.seed)
     if not args.no_rtb:
         out["rtb"] = rtb_step(gg, torch, args.seed)
     if not args.no_distances:
-        out["distances"] = distances(gg, torch, args.seed)
+        out["distances"] = distances(gg, torch, args.seed, og=og)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(G, args.seed)
     print(json.dumps(out), flush=True)
