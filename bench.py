@@ -149,10 +149,14 @@ def trk_step(gg, torch, seed, steps=3):
     return out
 
 
-def rtb_step(gg, torch, seed, r=2000, steps=2):
+def rtb_step(gg, torch, seed, r=0, steps=2):
     """The bench step's settings (sfm, c = 25, node + edge sums) with the RTB
-    estimator: r sampled sources per step, each swept to the end of the span
+    estimator: r sampled sources per step (default: two per workgroup of the
+    grid, since each source's sweep runs to the end of the span and a launch
+    lasts as long as its longest sweeps), each swept to the end of the span
     with the dependencies of every reached target."""
+    if r <= 0:
+        r = 2 * gg.get_launch()["n_slabs"]
     gg.run(OPT, fixed_r=256, seed=seed + 999, c=C, edges=True, rtb=True)
     torch.cuda.synchronize()
     tot = {"sweep_ms": 0.0, "launches": 0, "window_edges": 0, "arcs": 0, "touched_nodes": 0, "touched_edges": 0}
