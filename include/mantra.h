@@ -302,8 +302,10 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg);
  * the bootstrap stream of seed, under candidate grid sizes (1, 7/8, 3/4, 5/8
  * and 1/2 of the automatic grid; where device memory, not residency, bounds
  * that grid, also 3/2 and 2 times it, up to the resident workgroups, with
- * smaller arc buffers) and both pair orders, then with 256 hub nodes in LDS
- * at the best of those, then keeps the fastest as the graph's launch
+ * smaller arc buffers) and both pair orders; then, on graphs small enough
+ * for the reached bitmap in LDS, 256 hub nodes in LDS at the best of those
+ * grids, and 256, 512 and 1,024 hub nodes each at the grid resident with
+ * that LDS (all and 7/8 of it).  Keeps the fastest as the graph's launch
  * configuration and writes it to *best (may be NULL).  Blocking; results of
  * later calls do not depend on the choice. */
 int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint64_t seed,

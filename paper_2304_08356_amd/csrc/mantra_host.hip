@@ -401,6 +401,31 @@ static int64_t auto_cap(const mantra_graph *g, int nslabs) {
     return std::max<int64_t>(cap, 1024);
 }
 
+// The slabs and arc room of the pool a launch of ns slabs runs on, for the
+// automatic arc room cap of the graph's grid.  The pool
+// grows to cover every grid used so far.  Where the union of the largest
+// grid and the largest arc buffer would exceed the budget (the automatic arc
+// room shrinks as the grid grows), a pool with enough slabs and at least
+// half of this grid's arc room is kept as it is (the few pairs that overflow
+// it are re-run); otherwise it is sized for this launch alone.  The arc room
+// is never below a cap the caller set.
+static void pool_plan(const mantra_graph *g, int ns, int64_t cap, int *pns, int64_t *pcap) {
+    int want_ns = std::max(ns, g->pool.nslabs);
+    int64_t want_cap = std::max(cap, g->pool.cap);
+    if ((g->pool.nslabs < ns || g->pool.cap < cap) &&
+        (double)want_ns * ((double)slab_state_bytes(g) + (double)want_cap * 32.0) > (double)pool_budget(g)) {
+        if (g->pool.nslabs >= ns && 2 * g->pool.cap >= cap && g->user_cap <= 0) {
+            want_ns = g->pool.nslabs;
+            want_cap = g->pool.cap;
+        } else {
+            want_ns = ns;
+            want_cap = cap;
+        }
+    }
+    *pns = want_ns;
+    *pcap = want_cap;
+}
+
 template <class T>
 static int grow(T **p, int64_t &cap, int64_t need, int64_t minimum) {
     if (need <= cap && *p) return MANTRA_OK;
@@ -461,18 +486,9 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     int ns = auto_slabs(g);
     if ((int64_t)ns > slots) ns = (int)slots;
     if (g->per_pair) ns = 1;
-    int64_t cap = auto_cap(g, auto_slabs(g));
-    // the pool grows to cover every grid used so far, unless the union of
-    // the largest grid and the largest arc buffer exceeds the budget (grids
-    // that trade pairs in flight for arc room, as the autotuner's): then it
-    // is sized for this launch alone
-    int want_ns = std::max(ns, g->pool.nslabs);
-    int64_t want_cap = std::max(cap, g->pool.cap);
-    if ((g->pool.nslabs < ns || g->pool.cap < cap) &&
-        (double)want_ns * ((double)slab_state_bytes(g) + (double)want_cap * 32.0) > (double)pool_budget(g)) {
-        want_ns = ns;
-        want_cap = cap;
-    }
+    int want_ns = 0;
+    int64_t want_cap = 0;
+    pool_plan(g, ns, auto_cap(g, auto_slabs(g)), &want_ns, &want_cap);
     int rc = pool_ensure(g, g->pool, want_ns, want_cap);
     if (rc) return rc;
     if (sp.mode == MODE_RTB && (rc = pool_need_T(g, g->pool))) return rc;
@@ -1028,14 +1044,26 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
         }
         if (rc) break;
     }
-    // hub nodes' state in LDS at the best grid (it costs LDS per workgroup)
+    // hub nodes' state in LDS: 256 of them at the best grid, then 256, 512
+    // and 1,024 at the grids resident with that much more LDS per workgroup
+    // (all and 7/8 of them)
     if (!rc && lds_bitmap_ok(g->nmax)) {
-        g->user_slabs = best_slabs;
         g->order_mode = best_order;
-        g->hub_nodes = 256;
-        double ms = 0;
-        rc = time_one(&ms);
-        if (!rc && ms < best_ms) { best_ms = ms; best_hub = 256; }
+        std::vector<std::pair<int, int>> trials = {{256, best_slabs}};
+        for (int K : {256, 512, 1024}) {
+            g->hub_nodes = K;
+            g->user_slabs = 0;
+            const int rk = auto_slabs(g);
+            for (int ns : {rk, (7 * rk) / 8})
+                if (ns >= 1 && (K != 256 || ns != best_slabs)) trials.push_back({K, ns});
+        }
+        for (const auto &tr : trials) {
+            g->hub_nodes = tr.first;
+            g->user_slabs = tr.second;
+            double ms = 0;
+            if ((rc = time_one(&ms))) break;
+            if (ms < best_ms) { best_ms = ms; best_hub = tr.first; best_slabs = tr.second; }
+        }
     }
     if (rc) {
         g->user_slabs = saved_slabs;
@@ -1044,13 +1072,15 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
         g->hub_nodes = saved_hub;
         return rc;
     }
-    g->user_slabs = best_slabs == full ? 0 : best_slabs;
     g->user_cap = 0;
     g->order_mode = best_order;
     g->hub_nodes = best_hub;
+    g->user_slabs = 0;
+    if (auto_slabs(g) != best_slabs) g->user_slabs = best_slabs;
     if (best) {
         best->n_slabs = best_slabs;
-        best->arc_cap = auto_cap(g, best_slabs);
+        int pns = 0;
+        pool_plan(g, best_slabs, auto_cap(g, best_slabs), &pns, &best->arc_cap);
         best->order = best_order;
         best->graph_rounds = g->graph_rounds;
         best->per_pair_launch = g->per_pair;
@@ -1150,7 +1180,8 @@ int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint6
 int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {
     if (!g || !cfg) return fail(MANTRA_E_INVALID, "graph or config is NULL");
     cfg->n_slabs = auto_slabs(g);
-    cfg->arc_cap = auto_cap(g, cfg->n_slabs);
+    int pns = 0;
+    pool_plan(g, cfg->n_slabs, auto_cap(g, cfg->n_slabs), &pns, &cfg->arc_cap);
     cfg->order = g->order_mode;
     cfg->graph_rounds = g->graph_rounds;
     cfg->per_pair_launch = g->per_pair;

@@ -117,8 +117,9 @@ def test_hub_state_in_lds(lib, opt):
     H = chung_lu_graph(3000, 60_000, 2.3, 4000, seed=91, times="pareto")
     hg, ho = both(lib, H)
     check(hg, ho, opt, 64, 94, ctx="cl")
-    hg.set_launch(hub_nodes=256)
-    check(hg, ho, opt, 64, 94, ctx="cl-hub")
+    for K in (256, 1024):
+        hg.set_launch(hub_nodes=K)
+        check(hg, ho, opt, 64, 94, ctx="cl-hub%d" % K)
     G = uniform_graph(80, 4000, 6, seed=77)
     gg, og = both(lib, G)
     gg.set_launch(hub_nodes=40)

@@ -367,7 +367,8 @@ def test_hub_state_in_lds(lib, opt):
     compare_pairs(gg, og, opt, S, Z, ctx="hub-bigtick")
     H = chung_lu_graph(3000, 60_000, 2.3, 4000, seed=91, times="pareto")
     hg, ho = both(lib, H)
-    hg.set_launch(hub_nodes=256)
     S, Z = oracle.draw_pairs(94, oracle.STREAM_PAIR, H.n, 0, 60)
-    compare_pairs(hg, ho, opt, S, Z, ctx="hub-cl")
-    assert hg.get_launch()["hub_nodes"] == 256
+    for K in (256, 512, 1024):
+        hg.set_launch(hub_nodes=K)
+        compare_pairs(hg, ho, opt, S, Z, ctx="hub-cl%d" % K)
+        assert hg.get_launch()["hub_nodes"] == K

@@ -95,8 +95,9 @@ def test_long_ticks_and_hubs(lib, opt):
     hg, ho = both(lib, H)
     S = oracle.draw_pairs(95, oracle.STREAM_PAIR, H.n, 0, 4)[0]
     compare_sources(hg, ho, opt, S, ctx="cl", mode=1)
-    hg.set_launch(hub_nodes=128)
-    compare_sources(hg, ho, opt, S, ctx="cl-hub", mode=1)
+    for K in (128, 1024):
+        hg.set_launch(hub_nodes=K)
+        compare_sources(hg, ho, opt, S, ctx="cl-hub%d" % K, mode=1)
 
 
 def test_launch_forms_and_arc_retry(tiny_workload):

@@ -89,8 +89,9 @@ def test_long_ticks_star_and_hubs(lib, opt):
     hg, ho = both(lib, H)
     S, Z = oracle.draw_pairs(94, oracle.STREAM_PAIR, H.n, 0, 30)
     compare_walks(hg, ho, opt, S, Z, 5, ctx="cl")
-    hg.set_launch(hub_nodes=256)
-    compare_walks(hg, ho, opt, S, Z, 5, ctx="cl-hub")
+    for K in (256, 1024):
+        hg.set_launch(hub_nodes=K)
+        compare_walks(hg, ho, opt, S, Z, 5, ctx="cl-hub%d" % K)
 
 
 def test_launch_forms_and_arc_retry(tiny_workload):
