@@ -60,8 +60,8 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip
 # valid for the kernel source with this SHA-256 only.
 TRAFFIC = {
     "sweep_sha256": "a67e4431b25d0edfa880a551c0bc9657cf95bcc31eb000ac9cc62522fbd7ba2c",
-    "fetch_bytes_per_launch": 4.9185e+11,   # 2.40167e+08 KiB x 1.99995
-    "write_bytes_per_launch": 7.8464e+10,   # 7.66249e+07 KiB x 1.00000
+    "fetch_bytes_per_launch": 4.9185e+11,   # 2.40169e+08 KiB x 1.99995
+    "write_bytes_per_launch": 7.8459e+10,   # 7.66201e+07 KiB x 1.00000
 }
 
 
@@ -98,11 +98,21 @@ def cpu_baseline(G, seed, budget_s=15.0):
                 done, C, t_used)}
 
 
-def forms(gg, torch, seed):
-    """Algorithm 1 at eps = 0.01, delta = 0.1 (sfm, c = 25) in three launch forms."""
+def tuned_launch(tuned, **over):
+    """set_launch arguments that restore an autotuned configuration (arc room
+    left automatic), with the given overrides."""
+    cfg = {"n_slabs": tuned["n_slabs"], "order": tuned["order"], "hub_nodes": tuned["hub_nodes"],
+           "wide_counts": tuned["wide_counts"]}
+    cfg.update(over)
+    return cfg
+
+
+def forms(gg, torch, seed, tuned):
+    """Algorithm 1 at eps = 0.01, delta = 0.1 (sfm, c = 25) in three launch
+    forms; the autotuned configuration is in force again afterwards."""
     out = {}
     for name, cfg in (("batched", {}), ("graph", {"graph_rounds": True})):
-        gg.set_launch(**cfg)
+        gg.set_launch(**tuned_launch(tuned, **cfg))
         gg.run(OPT, eps=0.01, delta=0.1, seed=seed + 99, c=C)  # warm (pool, capture path)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -114,7 +124,7 @@ def forms(gg, torch, seed):
     # the unbatched form: one single-workgroup launch per pair, on a fixed
     # sample (a whole progressive run this way takes minutes)
     r = 256
-    gg.set_launch(per_pair_launch=True)
+    gg.set_launch(**tuned_launch(tuned, per_pair_launch=True))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gg.run(OPT, fixed_r=r, seed=seed, c=C)
@@ -122,7 +132,7 @@ def forms(gg, torch, seed):
     wall = time.perf_counter() - t0
     out["plain"] = {"pairs": r, "wall_s": wall, "pairs_per_s": r / wall,
                     "note": "fixed sample of %d pairs, one launch per pair" % r}
-    gg.set_launch()
+    gg.set_launch(**tuned_launch(tuned))
     base = out["plain"]["pairs_per_s"]
     for k in ("batched", "graph"):
         out[k]["speedup_vs_plain"] = out[k]["pairs_per_s"] / base
@@ -442,7 +452,7 @@ def main():
                      "kernel": "mantra::k_sweep<0>", "algorithmic_bytes_per_launch": abytes},
     }
     if not args.no_forms:
-        out["forms"] = forms(gg, torch, args.seed)
+        out["forms"] = forms(gg, torch, args.seed, tuned)
     if not args.no_serve:
         out["serve"] = serve(gg, G, torch, n_req=args.serve_requests)
     og = None

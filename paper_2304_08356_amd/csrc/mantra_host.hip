@@ -401,20 +401,27 @@ static int64_t auto_cap(const mantra_graph *g, int nslabs) {
     return std::max<int64_t>(cap, 1024);
 }
 
+// whether device memory, not residency, bounds the automatic grid (large
+// graphs: there the arc room decides how many pairs are re-run)
+static bool memory_bound(const mantra_graph *g) {
+    return (int64_t)(pool_budget(g) / 4 / slab_state_bytes(g)) < (int64_t)resident_slabs(g);
+}
+
 // The slabs and arc room of the pool a launch of ns slabs runs on, for the
-// automatic arc room cap of the graph's grid.  The pool
-// grows to cover every grid used so far.  Where the union of the largest
-// grid and the largest arc buffer would exceed the budget (the automatic arc
-// room shrinks as the grid grows), a pool with enough slabs and at least
-// half of this grid's arc room is kept as it is (the few pairs that overflow
-// it are re-run); otherwise it is sized for this launch alone.  The arc room
-// is never below a cap the caller set.
+// automatic arc room cap of the graph's grid.  The pool grows to cover every
+// grid used so far.  Where the union of the largest grid and the largest arc
+// buffer would exceed the budget (the automatic arc room shrinks as the grid
+// grows), a pool with enough slabs and at least half of this grid's arc room
+// is kept as it is on graphs whose grid residency bounds (their pairs use a
+// small part of that room); otherwise, and on memory-bound graphs, it is
+// sized for this launch alone.  The arc room is never below a cap the
+// caller set.
 static void pool_plan(const mantra_graph *g, int ns, int64_t cap, int *pns, int64_t *pcap) {
     int want_ns = std::max(ns, g->pool.nslabs);
     int64_t want_cap = std::max(cap, g->pool.cap);
     if ((g->pool.nslabs < ns || g->pool.cap < cap) &&
         (double)want_ns * ((double)slab_state_bytes(g) + (double)want_cap * 32.0) > (double)pool_budget(g)) {
-        if (g->pool.nslabs >= ns && 2 * g->pool.cap >= cap && g->user_cap <= 0) {
+        if (g->pool.nslabs >= ns && 2 * g->pool.cap >= cap && g->user_cap <= 0 && !memory_bound(g)) {
             want_ns = g->pool.nslabs;
             want_cap = g->pool.cap;
         } else {
