@@ -60,8 +60,8 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip
 # valid for the kernel source with this SHA-256 only.
 TRAFFIC = {
     "sweep_sha256": "a67e4431b25d0edfa880a551c0bc9657cf95bcc31eb000ac9cc62522fbd7ba2c",
-    "fetch_bytes_per_launch": 4.9185e+11,   # 2.40169e+08 KiB x 1.99995
-    "write_bytes_per_launch": 7.8459e+10,   # 7.66201e+07 KiB x 1.00000
+    "fetch_bytes_per_launch": 4.9171e+11,   # 2.40101e+08 KiB x 1.99995
+    "write_bytes_per_launch": 7.8496e+10,   # 7.66559e+07 KiB x 1.00000
 }
 
 
