@@ -306,8 +306,10 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg);
  * for the reached bitmap in LDS, 256 hub nodes in LDS at the best of those
  * grids, and 256, 512 and 1,024 hub nodes each at the grid resident with
  * that LDS (all and 7/8 of it).  Keeps the fastest as the graph's launch
- * configuration and writes it to *best (may be NULL).  Blocking; results of
- * later calls do not depend on the choice. */
+ * configuration and writes it to *best (may be NULL).  Blocking, for about a
+ * dozen runs of the sample (minutes on graphs of millions of nodes, where a
+ * smaller sample_pairs shortens it); results of later calls do not depend on
+ * the choice. */
 int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint64_t seed,
                     mantra_launch_config *best);
 
