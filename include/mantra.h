@@ -298,11 +298,15 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg);
 int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg);
 
 /* Autotuner: times the sweep on a calibration sample of sample_pairs pairs
- * (0: four times the largest candidate grid) drawn for optimality opt from
- * the bootstrap stream of seed, under candidate grid sizes (1, 7/8, 3/4, 5/8
- * and 1/2 of the automatic grid; where device memory, not residency, bounds
- * that grid, also 3/2 and 2 times it, up to the resident workgroups, with
- * smaller arc buffers) and both pair orders; then, on graphs small enough
+ * (0: four times the largest candidate grid, two times where device memory
+ * bounds the grid) drawn for optimality opt from the bootstrap stream of
+ * seed, under candidate grid sizes (1, 7/8, 3/4, 5/8 and 1/2 of the
+ * automatic grid; where device memory, not residency, bounds that grid, also
+ * 3/2 and 2 times it, up to the resident workgroups, with smaller arc
+ * buffers) and both pair orders.  Where memory bounds the grid, candidates
+ * are compared by the grid's mean busy time (a steady-state rate; the order
+ * is then longest first) rather than by the sample's time, which its longest
+ * pairs decide.  Then, on graphs small enough
  * for the reached bitmap in LDS, 256 hub nodes in LDS at the best of those
  * grids, and 256, 512 and 1,024 hub nodes each at the grid resident with
  * that LDS (all and 7/8 of it).  Keeps the fastest as the graph's launch

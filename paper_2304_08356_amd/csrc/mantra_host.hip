@@ -485,6 +485,7 @@ static int issue_kernels(mantra_graph *g, LaunchArgs &a, int ns, size_t lb, cons
 int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg) {
     memset(o.st, 0, sizeof o.st);
     o.ms = 0;
+    o.first_ms = 0;
     o.launches = 0;
     o.reduced = false;
     if (sp.npairs <= 0) return MANTRA_OK;
@@ -579,6 +580,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     HIPCHK(hipStreamSynchronize(g->st));
     HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
     o.ms += ms;
+    o.first_ms = ms;
     u64 st1[16];
     HIPCHK(hipMemcpy(st1, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
     if (nretry > 0) {
@@ -1017,9 +1019,15 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
     for (int x : {full, (7 * full) / 8, (3 * full) / 4, (5 * full) / 8, full / 2}) slabs.push_back(std::max(1, x));
     std::sort(slabs.begin(), slabs.end(), std::greater<int>());
     slabs.erase(std::unique(slabs.begin(), slabs.end()), slabs.end());
-    // several pairs per workgroup at the largest grid, so that the timing is
-    // not only the longest pair's
-    if (sample <= 0) sample = std::max<int64_t>(4 * (int64_t)slabs.front(), 256);
+    // Candidates are compared by the sample's time.  Where memory bounds the
+    // grid (large graphs), the sample is smaller than the rounds it tunes for
+    // and its time would be its longest pairs': there they are compared by
+    // the grid's mean busy time instead (the persistent launch's time times
+    // its busy share, plus any re-runs), the sample's time at a steady state.
+    // Default sample: four pairs per workgroup of the largest candidate, two
+    // where memory bounds the grid.
+    const bool steady = full < res;
+    if (sample <= 0) sample = std::max<int64_t>((steady ? 2 : 4) * (int64_t)slabs.front(), 256);
     mantra_request rq;
     memset(&rq, 0, sizeof rq);
     rq.opt = opt;
@@ -1038,10 +1046,13 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
         sp.npairs = g->G == 1 ? sample : d.per_graph * g->G;
         SweepOut o;
         const int r = run_sweep(g, sp, o);
-        *ms = o.ms;
+        *ms = steady ? o.first_ms * o.balance + (o.ms - o.first_ms) : o.ms;
         return r;
     };
     for (int order : {MANTRA_ORDER_LONGEST_FIRST, MANTRA_ORDER_DRAWN}) {
+        // the order only shapes the tail of a launch, which the steady-state
+        // comparison leaves out: longest first there
+        if (steady && order != MANTRA_ORDER_LONGEST_FIRST) continue;
         for (int ns : slabs) {
             g->user_slabs = ns;
             g->order_mode = order;

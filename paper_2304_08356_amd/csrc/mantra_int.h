@@ -190,6 +190,7 @@ struct LaunchSpec {
 struct SweepOut {
     u64 st[16];
     double ms = 0;
+    double first_ms = 0;   // the persistent launch alone (without re-runs)
     int launches = 0;
     double balance = 1.0;  // busy share of the persistent grid
     bool reduced = false;  // the graph replay also ran the request's reduction
