@@ -371,7 +371,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2002)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (sampled pairs are "
+        print("bench.py measures one GPU; --gpus %d is not supported (sampled pairs are "
               "independent, so N GPUs would each take 1/N of the pairs)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
