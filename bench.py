@@ -57,8 +57,10 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip
 # FETCH_SIZE, then WRITE_SIZE, summed over the k_sweep dispatches of the
 # profiled run, divided by their count, and scaled by the ratio of bytes to
 # counter bytes that the same counters give for a plain copy of known size),
-# valid for the kernel source with this SHA-256 only.
+# valid for the kernel source with this SHA-256 only, profiled at a fixed
+# grid of 2,880 slabs (the autotuned grid of a run may differ).
 TRAFFIC = {
+    "slabs": 2880,
     "sweep_sha256": "a67e4431b25d0edfa880a551c0bc9657cf95bcc31eb000ac9cc62522fbd7ba2c",
     "fetch_bytes_per_launch": 4.9171e+11,   # 2.40101e+08 KiB x 1.99995
     "write_bytes_per_launch": 7.8496e+10,   # 7.66559e+07 KiB x 1.00000
@@ -449,7 +451,8 @@ def main():
         "launch": tuned,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "mantra::k_sweep<0>", "algorithmic_bytes_per_launch": abytes},
+                     "kernel": "mantra::k_sweep<0>", "algorithmic_bytes_per_launch": abytes,
+                     "traffic_slabs": TRAFFIC["slabs"] if traffic is not None else None},
     }
     if not args.no_forms:
         out["forms"] = forms(gg, torch, args.seed, tuned)
