@@ -14,11 +14,17 @@ Parity status per function (the tests that pin each one are named there):
   graphs, and the exact integer invariants of Lemma 1 and Lemma 6.
 * ``draw_pairs`` / ``word``: pinned to published SplitMix64 outputs and to
   uniformity of the pair distribution.
-* ``bounds``: the closed forms of Theorem 1, Theorem 3 (its numeric
-  approximation) and Hoeffding's bound are pinned by limit and monotonicity
-  properties and by the statistical guarantee (SD <= xi in at least a
-  1 - delta fraction of runs); their exact constants are "parity unpinned"
-  (no independent source for them exists).
+* ``mantra.round_stats`` and the f, f^2 and lambda f sums of
+  ``accumulate``: pinned by the same statistics computed from brute-force
+  walk enumeration in exact fractions, and by the closed forms of all-plus
+  and all-minus sign words and of the time-increasing line.
+* ``bounds``: Theorem 3's size with rho = v is Bernstein's sample size for
+  one function (pinned); the closed forms of Theorem 1 and Hoeffding's bound
+  are checked by limit and monotonicity properties and by the statistical
+  guarantee (SD <= xi in at least a 1 - delta fraction of runs).  "Parity
+  unpinned": the constants of Theorem 1's Eqs. (1)-(3) and Theorem 3's
+  ln(2 rho / v) factor beyond rho = v (no independent source for them
+  exists).
 * ``mantra.estimate`` (Algorithm 1): pinned through its parts and by the
   statistical guarantee of Theorem 5; fm has no guarantee ("parity unpinned"
   beyond its counts).

@@ -10,17 +10,22 @@ deviation bounds, one function per statement:
 * ``first_size``-- the first schedule element of Algorithm 1: the least s in
                    [s', omega] whose Eq. (3) with R = 0 is at most eps.
 
-Readings (the paper is silent or garbled on these; each is listed with its
-reason in the design notes):
+Readings (the paper is silent or garbled on these):
 * a round's failure share is delta_i = delta / 2^(i+1) and the bootstrap's is
   delta/2, so the shares sum to at most delta;
 * the first element's search uses delta_1 = delta / 4;
-* a negative Rademacher bound R~ is clamped at 0 before the square roots;
+* a negative Rademacher bound R~ is clamped at 0 before the square roots
+  (the c-MCERA is a signed supremum and can fall below minus the
+  concentration term, which would put a negative number under Eq. (2)'s
+  root; the quantity it bounds is non-negative, so the clamp does not
+  loosen the bound);
 * omega falls back to Hoeffding's size when the bootstrap saw no internal
   node (v = 0 or rho = 0), and is never below s'.
 
-Parity: the exact constants have no independent source ("parity unpinned"
-beyond the special cases, monotonicity and statistical checks in the tests).
+Parity: omega with rho = v is pinned to Bernstein's sample size for one
+function; the constants of xi's Eqs. (1)-(3) and omega's ln(2 rho / v)
+factor beyond rho = v have no independent source ("parity unpinned" beyond
+the special cases, monotonicity and statistical checks in the tests).
 """
 from __future__ import annotations
 
