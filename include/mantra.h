@@ -173,6 +173,14 @@ typedef struct {
                                sample sizes count sources */
 
 typedef struct {
+    double *node_bc;       /* estimates of every node (host, [n], input node order;
+                              packed graphs: [sum of n_g]).  mantra_estimate: set by
+                              the caller, required; mantra_run and mantra_poll: the
+                              request's buffer, now filled */
+    double *edge_bc;       /* estimates of every temporal edge (host, [m], input edge
+                              order), or NULL.  mantra_estimate: set by the caller,
+                              optional (NULL: no temporal-edge estimates); mantra_run
+                              and mantra_poll: the request's buffer, now filled */
     int32_t status;        /* mantra_status of the request */
     uint32_t flags;        /* MANTRA_RES_* */
     int64_t samples;       /* |S| at the stop */
@@ -197,12 +205,15 @@ typedef struct {
 
 /* Algorithm 1 (bootstrap, sample-size bound of Theorem 3, progressive
  * rounds stopped by the c-MCERA bound of Theorem 1) on the whole time span
- * with the experimental defaults (c = 25), blocking.  node_bc (host, [n],
- * caller-owned) receives the estimates of the temporal betweenness of every
- * node, input node order.  MANTRA_E_OVERFLOW (estimates NaN) if a sampled
- * pair's count saturated; out (may be NULL) gets the run's statistics. */
+ * with the experimental defaults (c = 25), blocking: the problem statement of
+ * Section 3 (input the graph, the optimality, eps, delta; output the
+ * estimates of every node).  The caller sets out->node_bc (host, [n],
+ * caller-owned; NULL is MANTRA_E_INVALID) and out->edge_bc (host, [m], or
+ * NULL: no temporal-edge estimates); the call fills them and the rest of
+ * *out.  MANTRA_E_OVERFLOW (estimates NaN) if a sampled pair's count
+ * saturated. */
 int mantra_estimate(mantra_graph *g, mantra_opt opt, double eps, double delta, uint64_t seed,
-                    double *node_bc, mantra_result *out);
+                    mantra_result *out);
 
 /* Blocking run of one request: Algorithm 1 as above, or with fixed_r > 0 a
  * fixed sample of fixed_r pairs (per packed graph), over the request's window,

@@ -186,12 +186,15 @@ class Graph:
         out["rc"] = rc
         return node_bc, edge_bc, out
 
-    def estimate(self, opt, eps, delta, seed):
+    def estimate(self, opt, eps, delta, seed, edges=False):
+        """Algorithm 1 with the paper's defaults (whole span, c = 25): returns
+        (node_bc, edge_bc or None, result dict)."""
         node_bc = np.zeros(self.n, dtype=np.float64)
-        res = Result()
+        edge_bc = np.zeros(self.m_input, dtype=np.float64) if edges else None
+        res = Result(node_bc=_p(node_bc), edge_bc=_p(edge_bc))
         _lib.check(_lib._lib.mantra_estimate(self._h, _opt(opt), float(eps), float(delta), int(seed),
-                                             _p(node_bc), ctypes.byref(res)))
-        return node_bc, res.to_dict()
+                                             ctypes.byref(res)))
+        return node_bc, edge_bc, res.to_dict()
 
     def distances(self, opt, r, seed=0, tau=0.9, t0=0, t1=T_MAX, hist_len=64):
         """Algorithm 2 from r sampled sources: returns (hist[hist_len] of

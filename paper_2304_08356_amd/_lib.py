@@ -54,13 +54,13 @@ ORDER = {"longest": 0, "drawn": 1}
 
 
 class Result(ctypes.Structure):
-    _fields_ = [("status", I32), ("flags", U32), ("samples", I64), ("rounds", I64), ("omega", I64),
+    _fields_ = [("node_bc", P), ("edge_bc", P), ("status", I32), ("flags", U32), ("samples", I64), ("rounds", I64), ("omega", I64),
                 ("s_boot", I64), ("s1", I64), ("n_overflow", I64), ("n_reachable", I64),
                 ("window_edges", I64), ("arcs", I64), ("xi", F64), ("rho_hat", F64), ("v_hat", F64),
                 ("wimpy", F64), ("mcera", F64), ("gpu_ms", F64), ("latency_ms", F64)]
 
     def to_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("node_bc", "edge_bc")}
 
 
 class DistanceResult(ctypes.Structure):
@@ -80,7 +80,7 @@ SIGNATURES = {
     "mantra_count_pairs": (I32, [P, I32, I32, I32, I64, P, P, P, P, P, P]),
     "mantra_sample_paths": (I32, [P, I32, I32, I32, I64, P, P, P, U64, P, P, P]),
     "mantra_source_dependencies": (I32, [P, I32, I32, I32, I64, P, P, P, P, P]),
-    "mantra_estimate": (I32, [P, I32, F64, F64, U64, P, P]),
+    "mantra_estimate": (I32, [P, I32, F64, F64, U64, P]),
     "mantra_run": (I32, [P, P, P]),
     "mantra_distances": (I32, [P, I32, I32, I32, I64, U64, F64, P, I32, P]),
     "mantra_submit": (I32, [P, P, P]),

@@ -956,6 +956,8 @@ int req_finish(mantra_graph *g, ReqRun &q, mantra_result *out) {
         for (int64_t i = 0; i < g->m_in; ++i) q.rq.edge_bc[i] = NAN;
     q.R.latency_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q.t_start).count();
     q.R.status = rc;
+    q.R.node_bc = q.rq.node_bc;
+    q.R.edge_bc = q.edges ? q.rq.edge_bc : nullptr;
     if (rc < 0 && q.rc == MANTRA_OK) q.err = g_err;
     q.rc = rc;
     if (out) *out = q.R;
@@ -1344,12 +1346,15 @@ int mantra_run(mantra_graph *g, const mantra_request *req, mantra_result *out) {
     return run_request(g, *req, out);
 }
 
-int mantra_estimate(mantra_graph *g, mantra_opt opt, double eps, double delta, uint64_t seed, double *node_bc,
+int mantra_estimate(mantra_graph *g, mantra_opt opt, double eps, double delta, uint64_t seed,
                     mantra_result *out) {
+    if (!out || !out->node_bc) return fail(MANTRA_E_INVALID, "mantra_estimate needs out->node_bc");
     mantra_request rq;
     memset(&rq, 0, sizeof rq);
     rq.opt = opt; rq.t0 = 0; rq.t1 = INT32_MAX; rq.eps = eps; rq.delta = delta; rq.seed = seed; rq.c = 25;
-    rq.node_bc = node_bc;
+    rq.node_bc = out->node_bc;
+    rq.edge_bc = out->edge_bc;
+    if (out->edge_bc) rq.flags |= MANTRA_F_EDGE_BC;
     return mantra_run(g, &rq, out);
 }
 

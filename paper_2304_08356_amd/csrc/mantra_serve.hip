@@ -47,6 +47,9 @@ static void complete(const std::shared_ptr<Ticket> &t, int rc, const mantra_resu
     t->rc = rc;
     t->res = res;
     t->res.status = rc;
+    // the result names the request's output buffers, filled or not
+    t->res.node_bc = t->run.rq.node_bc;
+    t->res.edge_bc = (t->run.rq.flags & MANTRA_F_EDGE_BC) ? t->run.rq.edge_bc : nullptr;
     if (rc < 0) t->err = !t->run.err.empty() ? t->run.err : g_err;
     t->done = true;
     g_tcv.notify_all();

@@ -212,7 +212,7 @@ def test_progressive_tiny(tiny_workload, opt):
     assert abs(res["v_hat"] - ref["v_hat"]) <= 1e-12 * max(ref["v_hat"], 1e-300)
     assert res["omega"] == ref["omega"] and res["s1"] == ref["s1"]
     assert res["samples"] == ref["samples"] and res["rounds"] == len(ref["rounds"])
-    assert abs(res["xi"] - ref["xi"]) <= 1e-9 * ref["xi"]
+    assert abs(res["xi"] - ref["xi"]) <= 1e-12 * ref["xi"]
     ok, worst = rel_close(nb, ref["node_bc"], rel=1e-12, abs_floor=1e-300)
     assert ok, worst
     if opt == "fm":
