@@ -40,16 +40,21 @@ class TemporalGraph:
 
 
 def _dup_mask(src: np.ndarray, dst: np.ndarray, t: np.ndarray, n: int) -> np.ndarray:
-    """True at every position whose triple already occurred at a lower index."""
+    """True at every position whose triple already occurred at a lower index
+    (a hash table over the packed triples: every occurrence but the first)."""
+    import pandas as pd
     tmax = int(t.max()) + 1 if t.size else 1
     key = (src.astype(np.int64) * n + dst.astype(np.int64)) * tmax + t.astype(np.int64)
-    order = np.argsort(key, kind="stable")
-    ks = key[order]
-    dup_sorted = np.zeros(ks.shape[0], dtype=bool)
-    dup_sorted[1:] = ks[1:] == ks[:-1]
-    mask = np.zeros(ks.shape[0], dtype=bool)
-    mask[order[dup_sorted]] = True
-    return mask
+    return pd.Series(key).duplicated(keep="first").to_numpy()
+
+
+def _inv_cdf(cum: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """searchsorted(cum, x, side="right") for unsorted x, done on sorted x
+    (a merge instead of one cache-missing binary search per draw)."""
+    order = np.argsort(x)
+    out = np.empty(x.shape[0], dtype=np.int64)
+    out[order] = np.searchsorted(cum, x[order], side="right")
+    return out
 
 
 def _draw(rng: np.random.Generator, k: int, n: int, cum: Optional[np.ndarray]):
@@ -58,8 +63,8 @@ def _draw(rng: np.random.Generator, k: int, n: int, cum: Optional[np.ndarray]):
         v = rng.integers(0, n - 1, size=k, dtype=np.int64)
         v = v + (v >= u)
         return u, v
-    u = np.searchsorted(cum, rng.random(k), side="right")
-    v = np.searchsorted(cum, rng.random(k), side="right")
+    u = _inv_cdf(cum, rng.random(k))
+    v = _inv_cdf(cum, rng.random(k))
     np.minimum(u, n - 1, out=u)
     np.minimum(v, n - 1, out=v)
     return u.astype(np.int64), v.astype(np.int64)
