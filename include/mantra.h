@@ -218,7 +218,10 @@ int mantra_estimate(mantra_graph *g, mantra_opt opt, double eps, double delta, u
 /* Blocking run of one request: Algorithm 1 as above, or with fixed_r > 0 a
  * fixed sample of fixed_r pairs (per packed graph), over the request's window,
  * with c sign vectors and, with MANTRA_F_EDGE_BC, temporal-edge estimates in
- * edge_bc[m] (input edge order).  Same errors as mantra_estimate. */
+ * edge_bc[m] (input edge order).  Same errors as mantra_estimate.  A request
+ * whose sample holds a saturated pair stops at the end of that phase (the
+ * bootstrap or a round) with MANTRA_E_OVERFLOW: its estimates are void, so
+ * it runs no further rounds (served requests alike). */
 int mantra_run(mantra_graph *g, const mantra_request *req, mantra_result *out);
 
 /* Result of mantra_distances (appendix on temporal distance metrics,
@@ -272,7 +275,9 @@ int mantra_submit(mantra_graph *g, const mantra_request *req, uint64_t *ticket);
 int mantra_poll(uint64_t ticket, mantra_result *out, int32_t timeout_ms);
 
 /* Serving configuration: device bytes the scheduler may use for per-request
- * sums (0: a default share of free memory), maximum concurrent requests. */
+ * sums (0: the default, three quarters of the memory left free once the slab
+ * pool -- the per-pair node state and arc buffers that every launch shares,
+ * 45% of the device -- is reserved), maximum concurrent requests. */
 int mantra_serve_config(mantra_graph *g, uint64_t mem_budget_bytes, int32_t max_active);
 
 /* Launch configuration of the sweep (it changes how the work is scheduled,
@@ -290,8 +295,7 @@ typedef struct {
     int32_t per_pair_launch; /* 1: the unbatched form, one single-workgroup
                                 launch per pair (a baseline for measurement) */
     int32_t hub_nodes;    /* forward state of the hub_nodes highest-degree nodes
-                             of each pair kept in LDS (graphs whose reached
-                             bitmap fits LDS; 0: none) */
+                             of each pair kept in LDS (0: none, at most 4,096) */
     int32_t wide_counts;  /* pairs whose 64-bit counts saturate, counted again in
                              256-bit words (dependency estimator): MANTRA_WIDE_* */
 } mantra_launch_config;
@@ -317,10 +321,10 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg);
  * buffers) and both pair orders.  Where memory bounds the grid, candidates
  * are compared by the grid's mean busy time (a steady-state rate; the order
  * is then longest first) rather than by the sample's time, which its longest
- * pairs decide.  Then, on graphs small enough
- * for the reached bitmap in LDS, 256 hub nodes in LDS at the best of those
- * grids, and 256, 512 and 1,024 hub nodes each at the grid resident with
- * that LDS (all and 7/8 of it).  Keeps the fastest as the graph's launch
+ * pairs decide.  Then hub nodes in LDS: where residency bounds the grid, 256
+ * of them at the best of those grids, and 256, 512 and 1,024 each at the
+ * grid resident with that LDS (all and 7/8 of it); where memory bounds it,
+ * 1,024, 2,048 and 4,096 at the best grid (or the grid still resident).  Keeps the fastest as the graph's launch
  * configuration and writes it to *best (may be NULL).  Blocking, for about a
  * dozen runs of the sample (minutes on graphs of millions of nodes, where a
  * smaller sample_pairs shortens it); results of later calls do not depend on

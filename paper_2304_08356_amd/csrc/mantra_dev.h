@@ -20,7 +20,6 @@ constexpr int kFwN = 2 * kC;         // LDS forwarding / tail table slots
 constexpr int kFwBits = kFwN == 128 ? 7 : (kFwN == 256 ? 8 : (kFwN == 512 ? 9 : 10));
 static_assert((1 << kFwBits) == kFwN, "table size must be a power of two");
 constexpr int kOrderBuckets = 160;   // log-scale cost buckets of the launch order (4 per octave)
-constexpr int kAliveN = 512;         // alive-set hash slots of the reverse sweep (no LDS bitmap)
 constexpr u32 kHInf = 0xFFFFu;       // "unreached" hop count
 constexpr u64 kUMax = ~0ull;
 
@@ -100,6 +99,7 @@ struct DevSlabs {
     u64 *arcs;        // [ns][cap][4]   per slab: cap x {head | t<<32}, then cap x {k | u<<32, tail count, tl | hl<<16}
     u64 *XS;          // [ns][gmax][2]  big-tick scratch
     u64 *T;           // [ns][nmax][2]  RTB sources: first arrival of each reached node (allocated for them)
+    unsigned char *BM;// [ns][nmax rounded up to 16] reached / alive node bytes (graphs whose bitmap is not in LDS)
     u32 *hdr;         // [ns][4]        pair serial, tick stamp
     int64_t nmax, cap, gmax;
 };
@@ -109,8 +109,8 @@ struct LaunchArgs {
     DevSlabs sl;
     const DevReq *reqs;
     int32_t nreq;
-    int32_t lds_bitmap;      // 1: reached-bitmap of nmax bits in LDS
-    int32_t hub_nodes;       // with the bitmap: forward state of nodes < hub_nodes lives in LDS
+    int32_t lds_bitmap;      // 1: reached bitmap of nmax bits in LDS; 0: reached node bytes in the slabs' BM
+    int32_t hub_nodes;       // forward state of nodes < hub_nodes lives in LDS
     int64_t npairs;              // launch slots (grid sizes); the pairs are slots qbase..np-1
     const int64_t *npairs_dev;   // np read from device memory (graph replays), or null: np = npairs
     int64_t qbase;               // first slot this launch takes

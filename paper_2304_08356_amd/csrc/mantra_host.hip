@@ -250,29 +250,26 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
 // A reached-bitmap in LDS lets a batch skip the state loads of unreached
 // tails; beyond 8 KB it costs more occupancy than it saves, and the reached
 // test reads the gathered per-node state (its pair tag) instead.
+// the pair's reached set: a bitmap in LDS up to 65,536 nodes, else one byte
+// per node in the slab (global memory)
 static int lds_bitmap_ok(int64_t nmax) { return ((nmax + 31) / 32) * 4 <= 8 * 1024; }
-// forward state of the top hub nodes in LDS (bitmap graphs only)
-static int hub_nodes(const mantra_graph *g) {
-    if (!lds_bitmap_ok(g->nmax)) return 0;
-    return (int)std::min<int64_t>(g->hub_nodes, g->nmax);
-}
+static size_t node_bytes_per_slab(int64_t nmax) { return lds_bitmap_ok(nmax) ? 0 : (size_t)((nmax + 15) / 16) * 16; }
+// forward state of the top hub nodes in LDS
+static int hub_nodes(const mantra_graph *g) { return (int)std::min<int64_t>(g->hub_nodes, g->nmax); }
 static size_t lds_bytes(const mantra_graph *g) {
     const int64_t nmax = g->nmax;
     size_t b = mantra_tab_lds_bytes();
-    if (lds_bitmap_ok(nmax)) {
-        b += ((size_t)((nmax + 31) / 32) * 4 + 7) & ~(size_t)7;
-        b += (size_t)hub_nodes(g) * 12;
-    } else {
-        b += (size_t)kAliveN * 4;  // alive-set hash of the reverse sweep
-    }
+    if (lds_bitmap_ok(nmax)) b += ((size_t)((nmax + 31) / 32) * 4 + 7) & ~(size_t)7;
+    b += (size_t)hub_nodes(g) * 12;
     return b;
 }
 
 // device bytes of one slab's per-node state (F: 16 B, shared by the forward
-// and the reverse; N: 8 B; touched: 4 B) and of its per-tick scratch (XS and
-// AG: 16 B, AGF: 4 B per edge of the longest tick)
+// and the reverse; N: 8 B; touched: 4 B; the reached byte where the bitmap
+// is not in LDS) and of its per-tick scratch (XS and AG: 16 B, AGF: 4 B per
+// edge of the longest tick)
 static size_t slab_state_bytes(const mantra_graph *g) {
-    return (size_t)g->nmax * 28 + (size_t)g->gmax * 36 + 16;
+    return (size_t)g->nmax * 28 + node_bytes_per_slab(g->nmax) + (size_t)g->gmax * 36 + 16;
 }
 
 // device memory and the share of it the slab pool (state and arc buffers)
@@ -297,6 +294,20 @@ static size_t pool_budget(const mantra_graph *g) {
     return (size_t)std::min(0.45 * (double)tot, 0.7 * (double)(fr + own));
 }
 
+// default device bytes the serving scheduler may give to per-request sums:
+// what is free once the slab pool (the per-pair state and arc buffers every
+// launch shares) holds its whole share of the device, less a margin for
+// launch buffers and the multiword path
+size_t serve_sums_budget(const mantra_graph *g) {
+    size_t fr, tot;
+    device_mem(g, &fr, &tot);
+    const size_t own = g->pool.nslabs ? (size_t)g->pool.nslabs * (slab_state_bytes(g) + (size_t)g->pool.cap * 32) : 0;
+    const size_t share = (size_t)(0.45 * (double)tot);
+    const size_t reserve = share > own ? share - own : 0;
+    const size_t left = fr > reserve ? fr - reserve : 0;
+    return std::max<size_t>((size_t)64 << 20, (size_t)(0.75 * (double)left));
+}
+
 // sweep workgroups the device holds at once (registers and LDS, as the
 // runtime reports them)
 static int resident_slabs(const mantra_graph *g) {
@@ -304,7 +315,7 @@ static int resident_slabs(const mantra_graph *g) {
     hipGetDeviceProperties(&pr, g->device);
     int cus = pr.multiProcessorCount > 0 ? pr.multiProcessorCount : 256;
     size_t lb = lds_bytes(g);
-    int per_cu = mantra_sweep_occupancy(lb);
+    int per_cu = mantra_sweep_occupancy(lb, lds_bitmap_ok(g->nmax) ? 0 : 1);
     if (per_cu <= 0) {
         int by_lds = (int)((160 * 1024) / (lb ? lb : 1));
         per_cu = std::min(8, std::max(1, by_lds));
@@ -331,7 +342,7 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
     if (dalloc(&p.F, ns * nmax * 2) || dalloc(&p.N, ns * nmax) ||
         dalloc(&p.AG, ns * (size_t)gmax * 2) || dalloc(&p.AGF, ns * (size_t)gmax) || dalloc(&p.touched, ns * nmax) ||
         dalloc(&p.arcs, ns * (size_t)cap * 4) || dalloc(&p.XS, ns * (size_t)gmax * 2) ||
-        dalloc(&p.hdr, ns * 4)) {
+        dalloc(&p.hdr, ns * 4) || (node_bytes_per_slab(nmax) && dalloc(&p.BM, ns * node_bytes_per_slab(nmax)))) {
         p.release();
         (void)hipGetLastError();
         return fail(MANTRA_E_OOM, "slab pool: %d slabs x (%lld nodes, %lld arcs) does not fit", nslabs,
@@ -342,6 +353,7 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
     HIPCHK(hipMemsetAsync(p.AG, 0xFF, sizeof(u64) * ns * gmax * 2, g->st));
     HIPCHK(hipMemsetAsync(p.AGF, 0, sizeof(u32) * ns * gmax, g->st));
     HIPCHK(hipMemsetAsync(p.hdr, 0, sizeof(u32) * ns * 4, g->st));
+    if (p.BM) HIPCHK(hipMemsetAsync(p.BM, 0, ns * node_bytes_per_slab(nmax), g->st));
     HIPCHK(hipStreamSynchronize(g->st));
     p.nslabs = nslabs;
     return MANTRA_OK;
@@ -890,8 +902,21 @@ int req_advance(mantra_graph *g, ReqRun &q) {
     int rc = phase_stats(g, q, rs);
     if (rc) return rc;
     const int c = q.c;
-    if (q.phase == ReqRun::BOOT) {
+    // a sampled pair whose counts saturated voids the request's estimates
+    // (MANTRA_E_OVERFLOW, never rounded): it stops at the end of that phase
+    // instead of running the rest of its schedule for nothing
+    if (rs[RS_OVERFLOW]) {
         q.R.n_overflow += (int64_t)rs[RS_OVERFLOW];
+        q.R.n_reachable += q.phase == ReqRun::BOOT ? 0 : (int64_t)rs[RS_REACHABLE];
+        if (q.phase == ReqRun::ROUND) {
+            q.round += 1;
+            q.R.rounds = q.round;
+            q.R.samples = q.rq.fixed_r > 0 ? q.rq.fixed_r : q.target;
+        }
+        q.phase = ReqRun::DONE;
+        return MANTRA_OK;
+    }
+    if (q.phase == ReqRun::BOOT) {
         double mw = 0, sumb = 0;
         std::vector<double> mr;
         if ((rc = reduce(g, q.boot.W, q.boot.B, q.boot.R, g->n_total, 0, &mw, &sumb, mr))) return rc;
@@ -913,7 +938,6 @@ int req_advance(mantra_graph *g, ReqRun &q) {
         return MANTRA_OK;
     }
     // a round (or the fixed sample) is complete
-    q.R.n_overflow += (int64_t)rs[RS_OVERFLOW];
     q.R.n_reachable += (int64_t)rs[RS_REACHABLE];
     q.round += 1;
     const int64_t r = q.rq.fixed_r > 0 ? q.rq.fixed_r : q.target;
@@ -1064,18 +1088,28 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
         }
         if (rc) break;
     }
-    // hub nodes' state in LDS: 256 of them at the best grid, then 256, 512
-    // and 1,024 at the grids resident with that much more LDS per workgroup
-    // (all and 7/8 of them)
-    if (!rc && lds_bitmap_ok(g->nmax)) {
+    // hub nodes' state in LDS.  Where residency bounds the grid: 256 of
+    // them at the best grid, then 256, 512 and 1,024 at the grids resident
+    // with that much more LDS per workgroup (all and 7/8 of them).  Where
+    // memory bounds it (few workgroups per CU, LDS to spare): 1,024, 2,048
+    // and 4,096 at the best grid, or at the grid still resident with them.
+    if (!rc) {
         g->order_mode = best_order;
-        std::vector<std::pair<int, int>> trials = {{256, best_slabs}};
-        for (int K : {256, 512, 1024}) {
-            g->hub_nodes = K;
-            g->user_slabs = 0;
-            const int rk = auto_slabs(g);
-            for (int ns : {rk, (7 * rk) / 8})
-                if (ns >= 1 && (K != 256 || ns != best_slabs)) trials.push_back({K, ns});
+        std::vector<std::pair<int, int>> trials;
+        if (!steady) {
+            trials.push_back({256, best_slabs});
+            for (int K : {256, 512, 1024}) {
+                g->hub_nodes = K;
+                g->user_slabs = 0;
+                const int rk = auto_slabs(g);
+                for (int ns : {rk, (7 * rk) / 8})
+                    if (ns >= 1 && (K != 256 || ns != best_slabs)) trials.push_back({K, ns});
+            }
+        } else {
+            for (int K : {1024, 2048, 4096}) {
+                g->hub_nodes = K;
+                trials.push_back({K, std::min(best_slabs, resident_slabs(g))});
+            }
         }
         for (const auto &tr : trials) {
             g->hub_nodes = tr.first;

@@ -36,7 +36,7 @@ hipError_t mantra_launch_wide(const mantra::LaunchArgs *a, const mantra::WideSla
 hipError_t mantra_launch_order(const mantra::LaunchArgs *a, mantra::u32 *bucket, mantra::u64 *hist,
                                int32_t *order, hipStream_t st);
 size_t mantra_tab_lds_bytes(void);
-int mantra_sweep_occupancy(size_t lds_bytes);
+int mantra_sweep_occupancy(size_t lds_bytes, int gbm);
 }
 
 namespace mantra {
@@ -69,12 +69,14 @@ struct SlabPool {
     int64_t nmax = 0, cap = 0, gmax = 0;
     u64 *F = nullptr, *N = nullptr, *AG = nullptr, *arcs = nullptr, *XS = nullptr;
     u64 *T = nullptr;  // RTB launches only: first arrivals, [nslabs][nmax][2]
+    unsigned char *BM = nullptr;  // reached node bytes (graphs whose bitmap is not in LDS)
     u32 *AGF = nullptr, *hdr = nullptr;
     int32_t *touched = nullptr;
     void release() {
-        hipFree(F); hipFree(N); hipFree(AG); hipFree(arcs); hipFree(XS); hipFree(T);
+        hipFree(F); hipFree(N); hipFree(AG); hipFree(arcs); hipFree(XS); hipFree(T); hipFree(BM);
         hipFree(AGF); hipFree(hdr); hipFree(touched);
         F = N = AG = arcs = XS = T = nullptr;
+        BM = nullptr;
         AGF = hdr = nullptr;
         touched = nullptr;
         nslabs = 0;
@@ -82,7 +84,7 @@ struct SlabPool {
     DevSlabs view() const {
         DevSlabs s;
         s.F = F; s.N = N; s.T = T; s.AG = AG; s.AGF = AGF; s.touched = touched; s.arcs = arcs;
-        s.XS = XS; s.hdr = hdr; s.nmax = nmax; s.cap = cap; s.gmax = gmax;
+        s.XS = XS; s.BM = BM; s.hdr = hdr; s.nmax = nmax; s.cap = cap; s.gmax = gmax;
         return s;
     }
 };
@@ -213,6 +215,9 @@ int reduce_blocks(int64_t n);
 int reduce_part_ensure(mantra_graph *g, int c);
 // persistent workgroups of a launch on this graph
 int auto_slabs(const mantra_graph *g);
+// default device bytes of the serving scheduler's per-request sums (the slab
+// pool's share of the device reserved)
+size_t serve_sums_budget(const mantra_graph *g);
 
 // per-request device accumulators of Section 4.2: sums of f, f^2 and the c
 // Rademacher-weighted sums per node; sums of f per temporal edge

@@ -55,12 +55,7 @@ static void complete(const std::shared_ptr<Ticket> &t, int rc, const mantra_resu
     g_tcv.notify_all();
 }
 
-static size_t default_budget(const mantra_graph *g) {
-    size_t fr = 0, tot = 0;
-    hipSetDevice(g->device);
-    hipMemGetInfo(&fr, &tot);
-    return tot / 4;
-}
+static size_t default_budget(const mantra_graph *g) { return serve_sums_budget(g); }
 
 // pairs a request may put into one shared launch
 static int64_t slice_quota(mantra_graph *g, size_t nactive) {

@@ -228,7 +228,23 @@ struct FwdOut {
     int64_t reached_n;    // single source: nodes listed in S.touched
 };
 
-__device__ __forceinline__ bool bm_test(const u32 *bm, int32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
+// The pair's reached set (forward) and alive set (reverse).  On graphs of
+// up to 65,536 nodes it is a bitmap in LDS (bit v, LDS atomics).  Larger
+// graphs keep one byte per node in the slab's global memory instead (GBM):
+// bit 0 = reached in the forward, bit 1 = alive in the reverse, written with
+// plain byte stores (a node's byte is written only by the lane that commits
+// the node, and a wave sees its own stores after the batch barrier, as it
+// does for the node state); the map is cleared at the start of each pair.
+template <bool GBM>
+__device__ __forceinline__ bool rch_test(const u32 *bm, int32_t v) {
+    if (GBM) return reinterpret_cast<const unsigned char *>(bm)[v] & 1u;
+    return (bm[v >> 5] >> (v & 31)) & 1u;
+}
+template <bool GBM>
+__device__ __forceinline__ void rch_set(u32 *bm, int32_t v) {
+    if (GBM) reinterpret_cast<unsigned char *>(bm)[v] = 1u;
+    else atomicOr(&bm[v >> 5], 1u << (v & 31));
+}
 
 __device__ __forceinline__ void put_arc(const Slab &S, int64_t cap, int64_t pos, int32_t v, int32_t t, u32 k,
                                         int32_t u, u64 tc, u32 tl, u32 hl) {
@@ -279,7 +295,7 @@ __device__ __forceinline__ bool head_commit(int opt, bool rv, u32 hv, u64 Sv, u3
 // node's first arrival {time | hops << 32, count} in T)
 enum { FWD_PAIR = 0, FWD_DIST = 1, FWD_RTB = 2 };
 
-template <int FM>
+template <int FM, bool GBM>
 __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
                               int64_t g0, int64_t g1, int32_t t, u32 &agstamp, FwdOut &o,
                               u32 &zh, u64 &zS, bool &zhit) {
@@ -308,7 +324,7 @@ __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, c
         u32 hu = 0;
         u64 Su = 0;
         if (act) {
-            bool maybe = a.lds_bitmap ? bm_test(bm, u) : true;
+            const bool maybe = rch_test<GBM>(bm, u);
             if (maybe && u < H.K) {
                 rt = true; hu = H.h[u]; Su = H.s[u];
             } else if (maybe) {
@@ -367,7 +383,7 @@ __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, c
                 bool rv = false;
                 u32 hv = 0;
                 u64 Sv = 0;
-                bool maybe = a.lds_bitmap ? bm_test(bm, v) : true;
+                const bool maybe = rch_test<GBM>(bm, v);
                 if (maybe && v < H.K) {
                     rv = true; hv = H.h[v]; Sv = H.s[v];
                 } else if (maybe) {
@@ -389,7 +405,7 @@ __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, c
                         S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh << 32);
                         S.F[2 * (int64_t)v + 1] = nS;
                     }
-                    if (a.lds_bitmap) atomicOr(&bm[v >> 5], 1u << (v & 31));
+                    rch_set<GBM>(bm, v);
                     zl = (v == P.z);
                 }
             }
@@ -470,7 +486,7 @@ __device__ __forceinline__ void load_batch(KArgs &a, const Pair &P, int64_t b, i
 // from the slab) or the commit of an earlier tick of the same batch, passed
 // from the committing lane's registers.  Maximal runs of ticks that read no
 // commit made inside the run ("segments") are processed together.
-template <int FM>
+template <int FM, bool GBM>
 __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H, FwdLds &L,
                         u32 &agstamp, FwdOut &o) {
     constexpr bool SINGLE = FM != FWD_PAIR;
@@ -507,7 +523,7 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
                         if (m) { g1 = i + (__ffsll((long long)m) - 1); break; }
                     }
                     __syncthreads();
-                    fwd_long_tick<FM>(a, P, S, bm, H, b0, g1, tlast, agstamp, o, zh, zS, zhit);
+                    fwd_long_tick<FM, GBM>(a, P, S, bm, H, b0, g1, tlast, agstamp, o, zh, zS, zhit);
                     o.swept = g1 - P.lo;
                     b0 = g1;
                     if (o.flags & REC_HOPS_LIMIT) return;
@@ -530,33 +546,22 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
         const int tid = __popcll(gm & le) - 1;
         const int ntick = __popcll(gm);
         const int rsl = 63 - __clzll((long long)((rsall & le) | 1ull));  // lane of my run's start
-        // ---- state at batch start.  With the LDS bitmap, a set bit is exactly
-        // a node whose state this pair wrote: the reached test needs no load,
-        // and the state loads of a live batch are in flight while its
-        // dependencies are worked out.  Without it, the state's pair tag
-        // decides.
+        // ---- state at batch start.  A set bit of the reached set is exactly
+        // a node whose state this pair wrote: the reached test needs no load
+        // of the state, and the state loads of a live batch are in flight
+        // while its dependencies are worked out.
         // (thu, su) / (thv, sv): the slab's {tag | hops << 32, count} words;
         // the hops are taken out where they are first used, so that nothing
-        // waits for the loads before then
-        bool rt = false, hr = false;
+        // waits for the loads before then.
+        // pfm: a node's state is final at its first arrival, so an edge
+        // whose head was reached before the batch can neither commit nor lie
+        // on an optimal walk (its whole run is dead); its tail needs no load.
+        const bool dead = opt == OPT_PFM && in && rch_test<GBM>(bm, v);
+        const bool rt = in && !dead && rch_test<GBM>(bm, u);
+        const bool hr = rs && rch_test<GBM>(bm, v);
         u64 thu = 0, thv = 0, su = 0, sv = 0;
         u32 lhu = 0, lhv = 0;
         u64 lsu = 0, lsv = 0;
-        if (a.lds_bitmap) {
-            rt = in && bm_test(bm, u);
-            hr = rs && bm_test(bm, v);
-        } else {
-            if (in) {
-                thu = S.F[2 * (int64_t)u];
-                su = S.F[2 * (int64_t)u + 1];
-                rt = (u32)thu == P.tag;
-            }
-            if (rs) {
-                thv = S.F[2 * (int64_t)v];
-                sv = S.F[2 * (int64_t)v + 1];
-                hr = (u32)thv == P.tag;
-            }
-        }
         // the next batch's edges, in flight while this one is processed
         int32_t t2, u2, v2, tn2;
         load_batch(a, P, b0 + nbat, t2, u2, v2, tn2);
@@ -567,7 +572,7 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
             t = t2; u = u2; v = v2; tnext = tn2;
             continue;
         }
-        if (a.lds_bitmap) {
+        {
             // every lane loads (lanes with nothing to load read the origin's
             // state, one line for all of them): no merge of a loaded value
             // with a default, so no early wait for the loads
@@ -711,7 +716,7 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
                     S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh2 << 32);
                     S.F[2 * (int64_t)v + 1] = nS;
                 }
-                if (a.lds_bitmap) atomicOr(&bm[v >> 5], 1u << (v & 31));
+                rch_set<GBM>(bm, v);
             }
             if (SINGLE) {
                 // first arrivals: the list of reached nodes, and the hops
@@ -782,36 +787,20 @@ struct RevCtx {
     int64_t touched_n;
     int64_t edges_n;   // arcs with a non-zero dependency (touched temporal edges)
     bool ovf;
-    bool alive_all;    // alive hash overflowed: treat every node as alive
 };
 
 // alive set: nodes with a non-zero dependency accumulator for this pair
-__device__ __forceinline__ bool alive_test(KArgs &a, const u32 *bm, const RevCtx &X, int32_t v) {
-    if (a.lds_bitmap) return bm_test(bm, v);
-    if (X.alive_all) return true;
-    u32 sl = (((u32)v) * 2654435761u) >> (32 - 9);
-    for (int it = 0; it < kAliveN; ++it) {
-        u32 k = bm[sl];
-        if (k == 0) return false;
-        if (k == (u32)v + 1) return true;
-        sl = (sl + 1) & (kAliveN - 1);
-    }
-    return false;
+// (the LDS bitmap, emptied before the reverse; or bit 1 of the node bytes,
+// clear since the pair started)
+template <bool GBM>
+__device__ __forceinline__ bool alive_test(const u32 *bm, int32_t v) {
+    if (GBM) return reinterpret_cast<const unsigned char *>(bm)[v] & 2u;
+    return (bm[v >> 5] >> (v & 31)) & 1u;
 }
-__device__ __forceinline__ bool alive_set(KArgs &a, u32 *bm, int32_t v) {
-    if (a.lds_bitmap) { atomicOr(&bm[v >> 5], 1u << (v & 31)); return true; }
-    u32 sl = (((u32)v) * 2654435761u) >> (32 - 9);
-    for (int it = 0; it < kAliveN / 2; ++it) {
-        u32 k = bm[sl];
-        if (k == (u32)v + 1) return true;
-        if (k == 0) {
-            u32 old = atomicCAS(&bm[sl], 0u, (u32)v + 1);
-            if (old == 0u || old == (u32)v + 1) return true;
-            continue;
-        }
-        sl = (sl + 1) & (kAliveN - 1);
-    }
-    return false;  // too full: the caller switches to "everything alive"
+template <bool GBM>
+__device__ __forceinline__ void alive_set(u32 *bm, int32_t v) {
+    if (GBM) reinterpret_cast<unsigned char *>(bm)[v] = 2u;
+    else atomicOr(&bm[v >> 5], 1u << (v & 31));
 }
 
 __device__ __forceinline__ void rev_contrib(KArgs &a, const Pair &P, const Slab &S,
@@ -851,6 +840,7 @@ __device__ __forceinline__ u64 head_B(const Pair &P, const RevCtx &X, int32_t v,
 
 // a tick with more arcs than one batch: heads first (all read state older
 // than the tick), then level resets and additions at the tails
+template <bool GBM>
 __device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, RevCtx &X,
                               int64_t a0, int64_t a1) {
     const int l = lane_id();
@@ -859,7 +849,7 @@ __device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, R
         bool inr = i < a1;
         u64 mm = inr ? S.arcm[i] : 0;
         int32_t v = (int32_t)(u32)mm;
-        bool act = inr && (v == P.z || alive_test(a, bm, X, v));
+        bool act = inr && (v == P.z || alive_test<GBM>(bm, v));
         u64 B = 0, tc = 0;
         u32 k = 0;
         if (act) {
@@ -903,19 +893,18 @@ __device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, R
         if (!B) continue;
         int32_t u = (int32_t)(S.arcx[3 * i] >> 32);
         atomicAdd((unsigned long long *)&S.R[2 * (int64_t)u + 1], (unsigned long long)B);
-        if (!alive_set(a, bm, u)) full = true;
+        alive_set<GBM>(bm, u);
     }
-    if (ballot(full)) X.alive_all = true;
     __syncthreads();
 }
 
+template <bool GBM>
 __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t bmw, RevLds &L,
                         u32 &stamp, int64_t narcs, RevCtx &X) {
     const int l = lane_id();
-    // the alive set starts empty
-    const int64_t words = a.lds_bitmap ? bmw : kAliveN;
-    for (int64_t w = l; w < words; w += kWave) bm[w] = 0;
-    X.alive_all = false;
+    // the alive set starts empty (the node bytes' bit 1 already is)
+    if (!GBM)
+        for (int64_t w = l; w < bmw; w += kWave) bm[w] = 0;
     __syncthreads();
     int64_t ac = narcs;
     while (ac > 0) {
@@ -931,7 +920,7 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
             u64 mm = in[j] ? S.arcm[blo + off] : 0;
             vv[j] = (int32_t)(u32)mm;
             tt[j] = in[j] ? (int32_t)(mm >> 32) : INT32_MIN;
-            al[j] = in[j] && (vv[j] == P.z || alive_test(a, bm, X, vv[j]));
+            al[j] = in[j] && (vv[j] == P.z || alive_test<GBM>(bm, vv[j]));
             if (ballot(al[j])) any = true;
         }
         // no arc of this batch can carry a dependency: nothing to do
@@ -958,7 +947,7 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
                         if (m) { a0 = i + (63 - __clzll((long long)m)) + 1; break; }
                         if (i <= 0) { a0 = 0; break; }
                     }
-                    rev_long_tick(a, P, S, bm, X, a0, ac);
+                    rev_long_tick<GBM>(a, P, S, bm, X, a0, ac);
                     ac = a0;
                     continue;
                 }
@@ -994,7 +983,7 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
                 u64 th = ld_agent(&S.R[2 * (int64_t)vv[j]]);
                 if ((u32)th == P.rtag) { hval[j] = true; hlvl[j] = (u32)(th >> 32) & 0xFFFFu; hacc[j] = ld_agent(&S.R[2 * (int64_t)vv[j] + 1]); }
             }
-            if (in[j] && alive_test(a, bm, X, uu[j])) {
+            if (in[j] && alive_test<GBM>(bm, uu[j])) {
                 u64 th = ld_agent(&S.R[2 * (int64_t)uu[j]]);
                 if ((u32)th == P.rtag) { tval[j] = true; tlvl[j] = (u32)(th >> 32) & 0xFFFFu; tacc[j] = ld_agent(&S.R[2 * (int64_t)uu[j] + 1]); }
             }
@@ -1066,14 +1055,12 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
                     }
                 }
                 __syncthreads();
-                bool full = false;
 #pragma unroll
                 for (int j = 0; j < kE; ++j) {
                     if (tsl[j] < 0) continue;
                     atomicAdd((unsigned long long *)&L.tb_acc[tsl[j]], (unsigned long long)Bv[j]);
-                    if (!alive_set(a, bm, uu[j])) full = true;
+                    alive_set<GBM>(bm, uu[j]);
                 }
-                if (ballot(full)) X.alive_all = true;
                 __syncthreads();
             }
             ge = gs;
@@ -1427,7 +1414,9 @@ __device__ __forceinline__ Slab slab_of(KArgs &a, int64_t slab) {
     return S;
 }
 
-template <int MODE>
+// GBM: the reached set in the slab's node bytes (graphs of more than 65,536
+// nodes) instead of an LDS bitmap
+template <int MODE, bool GBM>
 __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg) {
     constexpr bool RTB = MODE == MODE_RTB;
     constexpr bool SINGLE = MODE == MODE_DISTANCES || RTB;
@@ -1437,7 +1426,6 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
     const int64_t slab = blockIdx.x;
     (void)a_arg;
     TabLds &tab = *reinterpret_cast<TabLds *>(lds_raw);
-    u32 *bm = reinterpret_cast<u32 *>(lds_raw + sizeof(TabLds));
     for (int i = l; i < kFwN; i += kWave) { tab.r.tb_key[i] = 0; }
     u32 serial, agstamp;
     int64_t np;
@@ -1454,10 +1442,13 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
     for (;;) {
         KArgs &a = launch_args();
         const Slab S = slab_of(a, slab);
-        const int64_t bmw = a.lds_bitmap ? (a.sl.nmax + 31) / 32 : 0;
+        // LDS bitmap words, or the 16-byte words of the node bytes
+        const int64_t bmw = GBM ? (a.sl.nmax + 15) / 16 : (a.sl.nmax + 31) / 32;
+        u32 *bm = GBM ? reinterpret_cast<u32 *>(a.sl.BM + slab * bmw * 16)
+                      : reinterpret_cast<u32 *>(lds_raw + sizeof(TabLds));
         Hub H;
-        H.K = a.lds_bitmap ? a.hub_nodes : 0;
-        H.s = reinterpret_cast<u64 *>(lds_raw + sizeof(TabLds) + ((bmw * 4 + 7) & ~7ll));
+        H.K = a.hub_nodes;
+        H.s = reinterpret_cast<u64 *>(lds_raw + sizeof(TabLds) + (GBM ? 0 : ((bmw * 4 + 7) & ~7ll)));
         H.h = reinterpret_cast<u32 *>(H.s + H.K);
         u32 qq = 0;
         if (l == 0) qq = atomicAdd(a.work, 1u);
@@ -1497,8 +1488,13 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
         if (ok) {
             P.lo = wave_lower_bound(a.g.T, P.elo, P.ehi, dep);
             P.hi = wave_upper_bound(a.g.T, P.lo, P.ehi, lin);
-            // reset the reached bitmap, seed the origin
-            for (int64_t w = l; w < bmw; w += kWave) bm[w] = 0;
+            // reset the reached set, seed the origin
+            if (GBM) {
+                uint4 *w4 = reinterpret_cast<uint4 *>(bm);
+                for (int64_t w = l; w < bmw; w += kWave) w4[w] = make_uint4(0u, 0u, 0u, 0u);
+            } else {
+                for (int64_t w = l; w < bmw; w += kWave) bm[w] = 0;
+            }
             __syncthreads();
             if (l == 0) {
                 if (P.s < H.K) { H.h[P.s] = 0u; H.s[P.s] = 1ull; }
@@ -1506,10 +1502,10 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
                     S.F[2 * (int64_t)P.s] = (u64)P.tag;  // h = 0
                     S.F[2 * (int64_t)P.s + 1] = 1ull;
                 }
-                if (a.lds_bitmap) bm[P.s >> 5] |= 1u << (P.s & 31);
+                rch_set<GBM>(bm, P.s);
             }
             __syncthreads();
-            forward<SINGLE ? (RTB ? FWD_RTB : FWD_DIST) : FWD_PAIR>(a, P, S, bm, H, tab.f, agstamp, fo);
+            forward<SINGLE ? (RTB ? FWD_RTB : FWD_DIST) : FWD_PAIR, GBM>(a, P, S, bm, H, tab.f, agstamp, fo);
             __syncthreads();
             if (MODE == MODE_DISTANCES)
                 distance_hist(P, S, H, reinterpret_cast<u32 *>(tab.r.tb_key), fo.reached_n,
@@ -1542,7 +1538,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
         }
         bool do_rev = reach && !(flags & REC_OVERFLOW);
         RevCtx X;
-        X.sigma = sigma; X.dsh = fo.zh; X.touched_n = 0; X.edges_n = 0; X.ovf = false; X.alive_all = false;
+        X.sigma = sigma; X.dsh = fo.zh; X.touched_n = 0; X.edges_n = 0; X.ovf = false;
         if (RTB && do_rev) {
             if (!rev_rtb(a, P, S, fo.arcs, X)) {
                 // a saturated count: the source is void, its f(e) rows cleared
@@ -1564,7 +1560,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
             // is a broken invariant
             if (!trk_walk(a, P, S, fo.arcs, fo.zh, fo.t_arr, sigma, X)) flags |= REC_SELFCHECK;
         } else if (do_rev) {
-            reverse(a, P, S, bm, bmw, tab.r, stamp, fo.arcs, X);
+            reverse<GBM>(a, P, S, bm, bmw, tab.r, stamp, fo.arcs, X);
             __syncthreads();
             // flow conservation at the origin: B(origin) must equal sigma
             u64 th = ld_agent(&S.R[2 * (int64_t)P.s]);
@@ -2168,22 +2164,34 @@ hipError_t mantra_launch_wide(const mantra::LaunchArgs *a, const mantra::WideSla
     return hipGetLastError();
 }
 hipError_t mantra_launch_sweep(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_PAIRS>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    if (a->lds_bitmap)
+        hipLaunchKernelGGL((mantra::k_sweep<mantra::MODE_PAIRS, false>), dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    else
+        hipLaunchKernelGGL((mantra::k_sweep<mantra::MODE_PAIRS, true>), dim3(nslabs), dim3(64), lds_bytes, st, *a);
     return hipGetLastError();
 }
 // the single-source (distance) form of the sweep
 hipError_t mantra_launch_sweep_sources(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_DISTANCES>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    if (a->lds_bitmap)
+        hipLaunchKernelGGL((mantra::k_sweep<mantra::MODE_DISTANCES, false>), dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    else
+        hipLaunchKernelGGL((mantra::k_sweep<mantra::MODE_DISTANCES, true>), dim3(nslabs), dim3(64), lds_bytes, st, *a);
     return hipGetLastError();
 }
 // the sweep with the RTB estimator (sources, all targets; needs the slabs' T)
 hipError_t mantra_launch_sweep_rtb(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_RTB>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    if (a->lds_bitmap)
+        hipLaunchKernelGGL((mantra::k_sweep<mantra::MODE_RTB, false>), dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    else
+        hipLaunchKernelGGL((mantra::k_sweep<mantra::MODE_RTB, true>), dim3(nslabs), dim3(64), lds_bytes, st, *a);
     return hipGetLastError();
 }
 // the sweep with the TRK estimator (one sampled optimal walk per pair)
 hipError_t mantra_launch_sweep_trk(const mantra::LaunchArgs *a, int nslabs, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(mantra::k_sweep<mantra::MODE_TRK>, dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    if (a->lds_bitmap)
+        hipLaunchKernelGGL((mantra::k_sweep<mantra::MODE_TRK, false>), dim3(nslabs), dim3(64), lds_bytes, st, *a);
+    else
+        hipLaunchKernelGGL((mantra::k_sweep<mantra::MODE_TRK, true>), dim3(nslabs), dim3(64), lds_bytes, st, *a);
     return hipGetLastError();
 }
 hipError_t mantra_launch_reduce(const mantra::ReduceArgs *a, int blocks, hipStream_t st) {
@@ -2220,12 +2228,13 @@ hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u3
     return hipGetLastError();
 }
 size_t mantra_tab_lds_bytes(void) { return sizeof(mantra::TabLds); }
-// resident sweep workgroups per CU for a given dynamic LDS size
-int mantra_sweep_occupancy(size_t lds_bytes) {
+// resident sweep workgroups per CU for a given dynamic LDS size (gbm: the
+// instance with the reached set in global node bytes)
+int mantra_sweep_occupancy(size_t lds_bytes, int gbm) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mantra::k_sweep<mantra::MODE_PAIRS>, 64, lds_bytes) !=
-        hipSuccess)
-        return 0;
-    return nb;
+    const hipError_t e =
+        gbm ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mantra::k_sweep<mantra::MODE_PAIRS, true>, 64, lds_bytes)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mantra::k_sweep<mantra::MODE_PAIRS, false>, 64, lds_bytes);
+    return e == hipSuccess ? nb : 0;
 }
 }
