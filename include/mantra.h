@@ -285,9 +285,12 @@ int mantra_serve_config(mantra_graph *g, uint64_t mem_budget_bytes, int32_t max_
 typedef struct {
     int32_t n_slabs;      /* persistent workgroups per launch, each one pair at a
                              time (0: as many as fit the device) */
-    int64_t arc_cap;      /* appearance-DAG arc records per workgroup (0: from
-                             free memory); a pair that overflows them is re-run
-                             with room for every edge */
+    int64_t arc_cap;      /* appearance-DAG arc records of each workgroup's own
+                             buffer (0: 2^18, at most one per edge of the graph);
+                             a pair with more takes chunks of 2^16 arcs from a
+                             pool the launch shares (the rest of the slab
+                             budget), and a pair that finds none free is re-run
+                             after the launch with room for every edge */
     int32_t order;        /* MANTRA_ORDER_*: the order pairs are handed out in */
     int32_t graph_rounds; /* 1: the progressive rounds of a blocking request
                              replay one captured HIP graph (counters, order,
@@ -298,6 +301,8 @@ typedef struct {
                              of each pair kept in LDS (0: none, at most 4,096) */
     int32_t wide_counts;  /* pairs whose 64-bit counts saturate, counted again in
                              256-bit words (dependency estimator): MANTRA_WIDE_* */
+    int32_t no_arc_chunks; /* 1: no shared arc chunks (every pair beyond its
+                              workgroup's own buffer is re-run) */
 } mantra_launch_config;
 
 #define MANTRA_WIDE_NONE 0    /* reported as saturated */
@@ -335,13 +340,22 @@ int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint6
 /* Work and timing of the last blocking call on g: device time of the sweep
  * kernel launches (HIP events on the graph's stream), their count, the
  * totals over its pairs of swept window edges, recorded appearance-DAG arcs,
- * touched nodes (N(v) > 0) and touched temporal edges (N(e) > 0), and the
- * load balance of the persistent grid (busy time of its workgroups over
- * workgroups x launch span, averaged over launch time).  Any pointer may be
- * NULL. */
+ * touched nodes (N(v) > 0) and touched temporal edges (N(e) > 0), the load
+ * balance of the persistent grid (busy time of its workgroups over
+ * workgroups x launch span, averaged over launch time), and the forward
+ * sweep's batches of up to 64 window edges that loaded node state and that
+ * were skipped (no reached tail).  Any pointer may be NULL. */
 int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launches,
                        int64_t *window_edges, int64_t *arcs, int64_t *touched_nodes,
-                       int64_t *touched_edges, double *balance);
+                       int64_t *touched_edges, double *balance, int64_t *live_batches,
+                       int64_t *skipped_batches);
+
+/* Test entry point: sets the pair serial and the long-tick stamp of every
+ * workgroup of the graph's slab pool (allocating the pool first), as a pool
+ * in use for billions of pairs would hold them.  Slab state words are tagged
+ * with these 32-bit counters; the library clears the pool's tagged state
+ * before either could wrap, so results never depend on them. */
+int mantra_debug_stamps(mantra_graph *g, uint32_t serial, uint32_t tick_stamp);
 
 const char *mantra_last_error(void);
 

@@ -88,7 +88,7 @@ class Graph:
                 "t_max": t1.value, "n_graphs": G.value}
 
     def set_launch(self, n_slabs=0, arc_cap=0, order="longest", graph_rounds=False, per_pair_launch=False,
-                   hub_nodes=0, wide_counts=1):
+                   hub_nodes=0, wide_counts=1, no_arc_chunks=False):
         """Launch configuration: scheduling (results do not change), and which
         saturated pairs are counted again in 256-bit words (wide_counts: 0
         none, 1 all but fm, 2 all)."""
@@ -96,7 +96,7 @@ class Graph:
                                 order=_lib.ORDER[order] if isinstance(order, str) else int(order),
                                 graph_rounds=1 if graph_rounds else 0,
                                 per_pair_launch=1 if per_pair_launch else 0, hub_nodes=int(hub_nodes),
-                                wide_counts=int(wide_counts))
+                                wide_counts=int(wide_counts), no_arc_chunks=1 if no_arc_chunks else 0)
         _lib.check(_lib._lib.mantra_set_launch(self._h, ctypes.byref(cfg)))
 
     def autotune(self, opt, sample_pairs=0, seed=0):
@@ -114,11 +114,13 @@ class Graph:
     def last_timing(self):
         ms = ctypes.c_double(); nl = ctypes.c_int64(); w = ctypes.c_int64(); a = ctypes.c_int64()
         tn = ctypes.c_int64(); te = ctypes.c_int64(); bal = ctypes.c_double()
+        lv = ctypes.c_int64(); sk = ctypes.c_int64()
         _lib.check(_lib._lib.mantra_last_timing(self._h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(w),
                                                 ctypes.byref(a), ctypes.byref(tn), ctypes.byref(te),
-                                                ctypes.byref(bal)))
+                                                ctypes.byref(bal), ctypes.byref(lv), ctypes.byref(sk)))
         return {"sweep_ms": ms.value, "launches": nl.value, "window_edges": w.value, "arcs": a.value,
-                "touched_nodes": tn.value, "touched_edges": te.value, "balance": bal.value}
+                "touched_nodes": tn.value, "touched_edges": te.value, "balance": bal.value,
+                "live_batches": lv.value, "skipped_batches": sk.value}
 
     def count_pairs(self, opt, s, z, t0=0, t1=T_MAX, graph=None, node_f=False, edge_f=False):
         """Records (and optionally dense per-pair f over nodes / input edges)

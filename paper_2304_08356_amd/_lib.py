@@ -44,7 +44,7 @@ class Request(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("n_slabs", I32), ("arc_cap", I64), ("order", I32), ("graph_rounds", I32), ("per_pair_launch", I32),
-                ("hub_nodes", I32), ("wide_counts", I32)]
+                ("hub_nodes", I32), ("wide_counts", I32), ("no_arc_chunks", I32)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,7 +89,8 @@ SIGNATURES = {
     "mantra_set_launch": (I32, [P, P]),
     "mantra_get_launch": (I32, [P, P]),
     "mantra_autotune": (I32, [P, I32, I64, U64, P]),
-    "mantra_last_timing": (I32, [P, P, P, P, P, P, P, P]),
+    "mantra_last_timing": (I32, [P, P, P, P, P, P, P, P, P, P]),
+    "mantra_debug_stamps": (I32, [P, U32, U32]),
     "mantra_last_error": (ctypes.c_char_p, []),
 }
 

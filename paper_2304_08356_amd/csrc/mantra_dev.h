@@ -20,6 +20,8 @@ constexpr int kFwN = 2 * kC;         // LDS forwarding / tail table slots
 constexpr int kFwBits = kFwN == 128 ? 7 : (kFwN == 256 ? 8 : (kFwN == 512 ? 9 : 10));
 static_assert((1 << kFwBits) == kFwN, "table size must be a power of two");
 constexpr int kOrderBuckets = 160;   // log-scale cost buckets of the launch order (4 per octave)
+constexpr int kArcChunkBits = 16;    // arcs per chunk of the shared arc pool: 2^16 (2 MiB)
+constexpr int64_t kArcChunk = 1ll << kArcChunkBits;
 constexpr u32 kHInf = 0xFFFFu;       // "unreached" hop count
 constexpr u64 kUMax = ~0ull;
 
@@ -97,6 +99,10 @@ struct DevSlabs {
     u32 *AGF;         // [ns][gmax]     big-tick commit stamp per head run
     int32_t *touched; // [ns][nmax]
     u64 *arcs;        // [ns][cap][4]   per slab: cap x {head | t<<32}, then cap x {k | u<<32, tail count, tl | hl<<16}
+    u64 *xarcs;       // [nchunks][4 kArcChunk] the shared arc chunks (same layout), taken by pairs beyond cap
+    u32 *xfree;       // [xwords] bit c set: chunk c is free
+    u32 *xtab;        // [ns][xmax] chunk ids a slab's pair holds, in arc order
+    int64_t xwords, xmax;
     u64 *XS;          // [ns][gmax][2]  big-tick scratch
     u64 *T;           // [ns][nmax][2]  RTB sources: first arrival of each reached node (allocated for them)
     unsigned char *BM;// [ns][nmax rounded up to 16] reached / alive node bytes (graphs whose bitmap is not in LDS)
@@ -120,7 +126,9 @@ struct LaunchArgs {
     double *node_f;              // dense per-pair node output [npairs][n_total] or null
     double *edge_f;              // dense per-pair edge output [npairs][m] or null
     u32 *work;                   // work counter, zero at launch
-    u64 *stats;                  // [16] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck, touched nodes, touched edges, slab busy ticks, last end, ~first start
+    u64 *stats;                  // [16] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck, touched nodes,
+                                 // touched edges, slab busy ticks, last end, ~first start, largest pair serial, largest tick stamp,
+                                 // batches that loaded state, batches skipped
     int32_t *retry;              // [1 + npairs] pairs whose arcs did not fit
     int32_t *wide;               // [1 + npairs] pairs whose counts saturated, for the multiword path
                                  // (null: they are reported as saturated)

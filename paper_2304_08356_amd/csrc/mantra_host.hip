@@ -249,14 +249,14 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
 
 // A reached-bitmap in LDS lets a batch skip the state loads of unreached
 // tails; beyond 8 KB it costs more occupancy than it saves, and the reached
-// test reads the gathered per-node state (its pair tag) instead.
+// set is a byte per node in the slab's global memory instead.
 // the pair's reached set: a bitmap in LDS up to 65,536 nodes, else one byte
 // per node in the slab (global memory)
-static int lds_bitmap_ok(int64_t nmax) { return ((nmax + 31) / 32) * 4 <= 8 * 1024; }
-static size_t node_bytes_per_slab(int64_t nmax) { return lds_bitmap_ok(nmax) ? 0 : (size_t)((nmax + 15) / 16) * 16; }
+int lds_bitmap_ok(int64_t nmax) { return ((nmax + 31) / 32) * 4 <= 8 * 1024; }
+size_t node_bytes_per_slab(int64_t nmax) { return lds_bitmap_ok(nmax) ? 0 : (size_t)((nmax + 15) / 16) * 16; }
 // forward state of the top hub nodes in LDS
 static int hub_nodes(const mantra_graph *g) { return (int)std::min<int64_t>(g->hub_nodes, g->nmax); }
-static size_t lds_bytes(const mantra_graph *g) {
+size_t lds_bytes(const mantra_graph *g) {
     const int64_t nmax = g->nmax;
     size_t b = mantra_tab_lds_bytes();
     if (lds_bitmap_ok(nmax)) b += ((size_t)((nmax + 31) / 32) * 4 + 7) & ~(size_t)7;
@@ -285,12 +285,31 @@ static size_t device_bytes(const mantra_graph *g) {
     device_mem(g, &fr, &tot);
     return tot;
 }
+// Arc records (32 B each).  Each slab has a buffer of its own (own_cap
+// arcs); a pair with more arcs takes chunks of kArcChunk arcs from a pool the
+// launch shares, so that the arc room follows the pairs in flight rather
+// than the largest pair times the grid.
+static const size_t kChunkBytes = (size_t)kArcChunk * 32;
+static int64_t own_cap(const mantra_graph *g) {
+    if (g->user_cap > 0) return std::min<int64_t>(g->user_cap, g->m + 1);
+    return std::min<int64_t>(g->m + 1, (int64_t)1 << 18);
+}
+// chunk-table entries per slab: enough for a pair with an arc per edge
+static int64_t xmax_of(const mantra_graph *g, int64_t cap) {
+    return cap >= g->m + 1 ? 0 : (g->m + 1 - cap + kArcChunk - 1) / kArcChunk;
+}
+static size_t slab_bytes(const mantra_graph *g, int64_t cap) {
+    return slab_state_bytes(g) + (size_t)cap * 32 + (size_t)xmax_of(g, cap) * 4;
+}
+static size_t pool_bytes(const mantra_graph *g, const SlabPool &p) {
+    return p.nslabs ? (size_t)p.nslabs * slab_bytes(g, p.cap) + (size_t)p.nchunks * kChunkBytes : 0;
+}
 // 45% of the device, less when other graphs or callers already hold memory
 // (the graph's own pool counts as available)
 static size_t pool_budget(const mantra_graph *g) {
     size_t fr, tot;
     device_mem(g, &fr, &tot);
-    const size_t own = g->pool.nslabs ? (size_t)g->pool.nslabs * (slab_state_bytes(g) + (size_t)g->pool.cap * 32) : 0;
+    const size_t own = pool_bytes(g, g->pool);
     return (size_t)std::min(0.45 * (double)tot, 0.7 * (double)(fr + own));
 }
 
@@ -301,7 +320,7 @@ static size_t pool_budget(const mantra_graph *g) {
 size_t serve_sums_budget(const mantra_graph *g) {
     size_t fr, tot;
     device_mem(g, &fr, &tot);
-    const size_t own = g->pool.nslabs ? (size_t)g->pool.nslabs * (slab_state_bytes(g) + (size_t)g->pool.cap * 32) : 0;
+    const size_t own = pool_bytes(g, g->pool);
     const size_t share = (size_t)(0.45 * (double)tot);
     const size_t reserve = share > own ? share - own : 0;
     const size_t left = fr > reserve ? fr - reserve : 0;
@@ -323,30 +342,54 @@ static int resident_slabs(const mantra_graph *g) {
     return cus * per_cu;
 }
 
-int auto_slabs(const mantra_graph *g) {
-    if (g->user_slabs > 0) return g->user_slabs;
-    // large graphs: the per-node state in a quarter of the pool budget bounds
-    // the number of pairs in flight; the rest holds their arc records, whose
-    // room decides how many pairs must be re-run with a full-window buffer
-    int64_t by_mem = (int64_t)(pool_budget(g) / 4 / slab_state_bytes(g));
-    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)resident_slabs(g), by_mem));
+// slabs whose state and own arc buffers fill half of the pool budget (large
+// graphs); the other half holds the shared arc chunks
+static int64_t slabs_by_memory(const mantra_graph *g) {
+    return (int64_t)(pool_budget(g) / 2 / slab_bytes(g, own_cap(g)));
 }
 
-static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap) {
+int auto_slabs(const mantra_graph *g) {
+    if (g->user_slabs > 0) return g->user_slabs;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)resident_slabs(g), slabs_by_memory(g)));
+}
+
+// shared chunks of a pool of ns slabs: the rest of the budget, no more than
+// the slabs could ever hold
+static int64_t auto_chunks(const mantra_graph *g, int ns, int64_t cap) {
+    const int64_t xm = xmax_of(g, cap);
+    if (xm == 0 || g->no_chunks) return 0;
+    const size_t bud = pool_budget(g), slabs = (size_t)ns * slab_bytes(g, cap);
+    const int64_t fit = bud > slabs ? (int64_t)((bud - slabs) / kChunkBytes) : 0;
+    return std::min<int64_t>(fit, (int64_t)ns * xm);
+}
+
+static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap, int64_t nchunks) {
     int64_t nmax = g->nmax;
     int64_t gmax = g->gmax;
-    if (p.nslabs >= nslabs && p.cap >= cap && p.nmax == nmax && p.gmax >= gmax) return MANTRA_OK;
+    if (p.nslabs >= nslabs && p.cap == cap && p.nmax == nmax && p.gmax >= gmax && p.nchunks >= nchunks)
+        return MANTRA_OK;
     p.release();
     p.nmax = nmax; p.cap = cap; p.gmax = gmax;
     size_t ns = (size_t)nslabs;
+    const int64_t xm = xmax_of(g, cap), xwords = (nchunks + 31) / 32;
     if (dalloc(&p.F, ns * nmax * 2) || dalloc(&p.N, ns * nmax) ||
         dalloc(&p.AG, ns * (size_t)gmax * 2) || dalloc(&p.AGF, ns * (size_t)gmax) || dalloc(&p.touched, ns * nmax) ||
         dalloc(&p.arcs, ns * (size_t)cap * 4) || dalloc(&p.XS, ns * (size_t)gmax * 2) ||
-        dalloc(&p.hdr, ns * 4) || (node_bytes_per_slab(nmax) && dalloc(&p.BM, ns * node_bytes_per_slab(nmax)))) {
+        dalloc(&p.hdr, ns * 4) || (node_bytes_per_slab(nmax) && dalloc(&p.BM, ns * node_bytes_per_slab(nmax))) ||
+        (nchunks > 0 && (dalloc(&p.xarcs, (size_t)nchunks * 4 * (size_t)kArcChunk) ||
+                         dalloc(&p.xfree, (size_t)xwords) || dalloc(&p.xtab, ns * (size_t)xm)))) {
         p.release();
         (void)hipGetLastError();
-        return fail(MANTRA_E_OOM, "slab pool: %d slabs x (%lld nodes, %lld arcs) does not fit", nslabs,
-                    (long long)nmax, (long long)cap);
+        return fail(MANTRA_E_OOM, "slab pool: %d slabs x (%lld nodes, %lld arcs) + %lld arc chunks does not fit",
+                    nslabs, (long long)nmax, (long long)cap, (long long)nchunks);
+    }
+    p.nchunks = nchunks;
+    p.xmax = nchunks > 0 ? xm : 0;
+    if (nchunks > 0) {
+        // every chunk free
+        std::vector<u32> bits((size_t)xwords, ~0u);
+        if (nchunks % 32) bits.back() = (1u << (nchunks % 32)) - 1u;
+        HIPCHK(hipMemcpy(p.xfree, bits.data(), sizeof(u32) * (size_t)xwords, hipMemcpyHostToDevice));
     }
     HIPCHK(hipMemsetAsync(p.F, 0, sizeof(u64) * ns * nmax * 2, g->st));
     HIPCHK(hipMemsetAsync(p.N, 0, sizeof(u64) * ns * nmax, g->st));
@@ -401,48 +444,66 @@ static int wide_ensure(mantra_graph *g, int nslabs, int64_t cap) {
     return MANTRA_OK;
 }
 
-// arc records (32 B each) per slab: the rest of the pool budget, at most
-// one per edge of the graph
-static int64_t auto_cap(const mantra_graph *g, int nslabs) {
-    if (g->user_cap > 0) return g->user_cap;
-    size_t state = slab_state_bytes(g) * (size_t)std::max(1, nslabs);
-    size_t bud = pool_budget(g);
-    size_t left = bud > state ? bud - state : 0;
-    int64_t per = (int64_t)(left / 32 / (size_t)std::max(1, nslabs));
-    int64_t cap = std::min<int64_t>(g->m + 1, std::max<int64_t>(per, 1 << 16));
-    return std::max<int64_t>(cap, 1024);
-}
-
 // whether device memory, not residency, bounds the automatic grid (large
-// graphs: there the arc room decides how many pairs are re-run)
-static bool memory_bound(const mantra_graph *g) {
-    return (int64_t)(pool_budget(g) / 4 / slab_state_bytes(g)) < (int64_t)resident_slabs(g);
+// graphs)
+static bool memory_bound(const mantra_graph *g) { return slabs_by_memory(g) < (int64_t)resident_slabs(g); }
+
+// The pool a launch of ns slabs runs on.  Where residency bounds the grid,
+// a pool with at least ns slabs (and the same own arc room) is kept, so that
+// alternating grids (the autotuner's) do not reallocate it.  Where memory
+// bounds it, the pool is sized for this grid: slabs and their own buffers,
+// and the shared chunks in the rest of the budget.
+static int pool_for(mantra_graph *g, int ns) {
+    const int64_t cap = own_cap(g);
+    SlabPool &p = g->pool;
+    if (p.nslabs >= ns && p.cap == cap && p.nmax == g->nmax && p.gmax >= g->gmax &&
+        (p.nchunks == 0) == (auto_chunks(g, ns, cap) == 0) && (!memory_bound(g) || p.nslabs == ns))
+        return MANTRA_OK;
+    if (p.nslabs) p.release();
+    return pool_ensure(g, p, ns, cap, auto_chunks(g, ns, cap));
 }
 
-// The slabs and arc room of the pool a launch of ns slabs runs on, for the
-// automatic arc room cap of the graph's grid.  The pool grows to cover every
-// grid used so far.  Where the union of the largest grid and the largest arc
-// buffer would exceed the budget (the automatic arc room shrinks as the grid
-// grows), a pool with enough slabs and at least half of this grid's arc room
-// is kept as it is on graphs whose grid residency bounds (their pairs use a
-// small part of that room); otherwise, and on memory-bound graphs, it is
-// sized for this launch alone.  The arc room is never below a cap the
-// caller set.
-static void pool_plan(const mantra_graph *g, int ns, int64_t cap, int *pns, int64_t *pcap) {
-    int want_ns = std::max(ns, g->pool.nslabs);
-    int64_t want_cap = std::max(cap, g->pool.cap);
-    if ((g->pool.nslabs < ns || g->pool.cap < cap) &&
-        (double)want_ns * ((double)slab_state_bytes(g) + (double)want_cap * 32.0) > (double)pool_budget(g)) {
-        if (g->pool.nslabs >= ns && 2 * g->pool.cap >= cap && g->user_cap <= 0 && !memory_bound(g)) {
-            want_ns = g->pool.nslabs;
-            want_cap = g->pool.cap;
-        } else {
-            want_ns = ns;
-            want_cap = cap;
-        }
-    }
-    *pns = want_ns;
-    *pcap = want_cap;
+// Slab state words carry their pair's tag (the slab's pair serial, +2 per
+// pair) and the long-tick scratch a tick stamp (+1 per long tick); both are
+// u32 that a slab carries across launches.  Before either could wrap -- a
+// word left by a pair 2^31 pairs earlier would then read as current -- the
+// pool's tagged words and stamps are cleared and the slabs start over.  The
+// kernels report each slab's serial and stamp; a launch advances a serial
+// by at most 2 per pair it holds, and a stamp by one per tick of more than
+// 64 edges (a launch would need 2^31 of them on one slab to wrap).
+static constexpr u64 kStampLimit = 1ull << 31;
+static int stamps_clear(mantra_graph *g, SlabPool &p) {
+    const size_t ns = (size_t)p.nslabs;
+    HIPCHK(hipMemsetAsync(p.F, 0, sizeof(u64) * ns * (size_t)p.nmax * 2, g->st));
+    HIPCHK(hipMemsetAsync(p.AG, 0xFF, sizeof(u64) * ns * (size_t)p.gmax * 2, g->st));
+    HIPCHK(hipMemsetAsync(p.AGF, 0, sizeof(u32) * ns * (size_t)p.gmax, g->st));
+    HIPCHK(hipMemsetAsync(p.hdr, 0, sizeof(u32) * ns * 4, g->st));
+    HIPCHK(hipStreamSynchronize(g->st));
+    p.serial_hi = p.tick_hi = 0;
+    return MANTRA_OK;
+}
+static int stamps_before(mantra_graph *g, SlabPool &p, int64_t slots) {
+    if (p.serial_hi + 2 * (u64)(slots + 1) >= 2 * kStampLimit || p.tick_hi >= kStampLimit) return stamps_clear(g, p);
+    return MANTRA_OK;
+}
+static int stamps_after(mantra_graph *g, SlabPool &p, const u64 *st) {
+    p.serial_hi = std::max(p.serial_hi, st[12]);
+    p.tick_hi = std::max(p.tick_hi, st[13]);
+    if (p.serial_hi >= kStampLimit || p.tick_hi >= kStampLimit) return stamps_clear(g, p);
+    return MANTRA_OK;
+}
+static int wide_stamps(mantra_graph *g, int64_t slots, const u64 *st) {
+    WidePool &p = g->wide;
+    if (st) p.serial_hi = std::max(p.serial_hi, st[12]);
+    const bool before = !st && p.serial_hi + 2 * (u64)(slots + 1) >= 2 * kStampLimit;
+    if (!before && p.serial_hi < kStampLimit) return MANTRA_OK;
+    const size_t ns = (size_t)p.nslabs, n = (size_t)p.nmax;
+    HIPCHK(hipMemsetAsync(p.ST, 0, sizeof(u64) * ns * n, g->st));
+    HIPCHK(hipMemsetAsync(p.RT, 0, sizeof(u64) * ns * n, g->st));
+    HIPCHK(hipMemsetAsync(p.hdr, 0, sizeof(u32) * ns * 4, g->st));
+    HIPCHK(hipStreamSynchronize(g->st));
+    p.serial_hi = 0;
+    return MANTRA_OK;
 }
 
 template <class T>
@@ -506,11 +567,10 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     int ns = auto_slabs(g);
     if ((int64_t)ns > slots) ns = (int)slots;
     if (g->per_pair) ns = 1;
-    int want_ns = 0;
-    int64_t want_cap = 0;
-    pool_plan(g, ns, auto_cap(g, auto_slabs(g)), &want_ns, &want_cap);
-    int rc = pool_ensure(g, g->pool, want_ns, want_cap);
+    // the pool is sized for the graph's grid (a smaller launch uses part of it)
+    int rc = pool_for(g, auto_slabs(g));
     if (rc) return rc;
+    if ((rc = stamps_before(g, g->pool, slots))) return rc;
     if (sp.mode == MODE_RTB && (rc = pool_need_T(g, g->pool))) return rc;
     int64_t rcap = g->dreq_cap;
     if ((rc = grow(&g->dreqs, rcap, (int64_t)sp.reqs.size(), 64))) return rc;
@@ -595,6 +655,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     o.first_ms = ms;
     u64 st1[16];
     HIPCHK(hipMemcpy(st1, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
+    if ((rc = stamps_after(g, g->pool, st1))) return rc;
     if (nretry > 0) {
         // pairs whose arcs overflowed get slabs that hold every edge of the
         // graph, as many as a fifth of device memory allows
@@ -604,7 +665,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         device_mem(g, &fr, &tot);
         int64_t fit = (int64_t)(std::min(tot / 5, fr / 2) / (slab_state_bytes(g) + (size_t)cap2 * 32));
         int ns2 = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int>(nretry, 64), fit));
-        rc = pool_ensure(g, g->pool_big, ns2, cap2);
+        rc = pool_ensure(g, g->pool_big, ns2, cap2, 0);
         if (rc) return rc;
         if (sp.mode == MODE_RTB && (rc = pool_need_T(g, g->pool_big))) return rc;
         std::vector<int32_t> q((size_t)nretry + 1);
@@ -633,7 +694,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         HIPCHK(hipMemcpy(&n2, g->dretry, sizeof(int32_t), hipMemcpyDeviceToHost));
         if (n2 > 0) return fail(MANTRA_E_INTERNAL, "arc buffer of a full window overflowed");
         for (int i = 0; i < 16; ++i)
-            if (i != 5 && i < 9) st1[i] += st2[i];
+            if ((i != 5 && i < 9) || i == 14 || i == 15) st1[i] += st2[i];
     }
     int32_t nwide = 0;
     if (a.wide) HIPCHK(hipMemcpy(&nwide, g->dwide, sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -647,6 +708,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         const int64_t fit = (int64_t)(std::min(tot / 8, fr / 2) / wide_slab_bytes(g, cap3));
         const int ns3 = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int>(nwide, 128), fit));
         if ((rc = wide_ensure(g, std::max(ns3, g->wide.nslabs), cap3))) return rc;
+        if ((rc = wide_stamps(g, nwide, nullptr))) return rc;
         HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, nullptr, g->dstats, g->st));
         a.npairs = nwide;
         a.npairs_dev = nullptr;
@@ -662,6 +724,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         o.launches += 1;
         u64 st3[16];
         HIPCHK(hipMemcpy(st3, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
+        if ((rc = wide_stamps(g, nwide, st3))) return rc;
         st1[2] += st3[2];
         st1[4] += st3[4];
         st1[6] += st3[6];
@@ -675,11 +738,12 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
 }
 
 // blocking calls report their work through mantra_last_timing
-static void timing_reset(mantra_graph *g) {
+void timing_reset(mantra_graph *g) {
     g->last_ms = 0; g->last_launches = 0; g->last_W = 0; g->last_arcs = 0; g->last_tn = 0; g->last_te = 0;
+    g->last_live = 0; g->last_dead = 0;
     g->last_busy_ms = 0;
 }
-static void timing_add(mantra_graph *g, const SweepOut &o) {
+void timing_add(mantra_graph *g, const SweepOut &o) {
     g->last_busy_ms += o.balance * o.ms;
     g->last_ms += o.ms;
     g->last_launches += o.launches;
@@ -687,6 +751,8 @@ static void timing_add(mantra_graph *g, const SweepOut &o) {
     g->last_arcs += (int64_t)o.st[1];
     g->last_tn += (int64_t)o.st[7];
     g->last_te += (int64_t)o.st[8];
+    g->last_live += (int64_t)o.st[14];
+    g->last_dead += (int64_t)o.st[15];
 }
 
 // per-block partials of max W, sum B, max R_j
@@ -1033,16 +1099,18 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
     g->hub_nodes = 0;
     const int full = auto_slabs(g);
     std::vector<int> slabs;
-    // a grid bounded by memory (large graphs) is also tried with up to twice
-    // the pairs in flight: their state then takes up to half of the pool
-    // budget and their arc buffers are smaller (pairs that overflow them are
-    // re-run after the launch, inside the timed call)
+    // a grid bounded by memory (large graphs) trades pairs in flight against
+    // the shared arc chunks: 3/2 and 5/4 of it leave a quarter and three
+    // eighths of the budget to the chunks (pairs that find none are re-run
+    // after the launch, inside the timed call), 3/4 to 3/8 of it leave more
     const int res = resident_slabs(g);
     if (full < res) {
-        slabs.push_back(std::min(res, 2 * full));
         slabs.push_back(std::min(res, (3 * full) / 2));
+        slabs.push_back(std::min(res, (5 * full) / 4));
+        for (int x : {full, (3 * full) / 4, full / 2, (3 * full) / 8}) slabs.push_back(std::max(1, x));
+    } else {
+        for (int x : {full, (7 * full) / 8, (3 * full) / 4, (5 * full) / 8, full / 2}) slabs.push_back(std::max(1, x));
     }
-    for (int x : {full, (7 * full) / 8, (3 * full) / 4, (5 * full) / 8, full / 2}) slabs.push_back(std::max(1, x));
     std::sort(slabs.begin(), slabs.end(), std::greater<int>());
     slabs.erase(std::unique(slabs.begin(), slabs.end()), slabs.end());
     // Candidates are compared by the sample's time.  Where memory bounds the
@@ -1133,8 +1201,8 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
     if (auto_slabs(g) != best_slabs) g->user_slabs = best_slabs;
     if (best) {
         best->n_slabs = best_slabs;
-        int pns = 0;
-        pool_plan(g, best_slabs, auto_cap(g, best_slabs), &pns, &best->arc_cap);
+        best->arc_cap = own_cap(g);
+        best->no_arc_chunks = g->no_chunks;
         best->order = best_order;
         best->graph_rounds = g->graph_rounds;
         best->per_pair_launch = g->per_pair;
@@ -1210,9 +1278,11 @@ int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg) {
     if (cfg->wide_counts < MANTRA_WIDE_NONE || cfg->wide_counts > MANTRA_WIDE_ALL)
         return fail(MANTRA_E_INVALID, "unknown wide_counts %d", cfg->wide_counts);
     std::lock_guard<std::mutex> lk(g->mu);
-    if (g->user_slabs != cfg->n_slabs || g->user_cap != cfg->arc_cap) g->pool.release();
+    if (g->user_slabs != cfg->n_slabs || g->user_cap != cfg->arc_cap || g->no_chunks != (cfg->no_arc_chunks ? 1 : 0))
+        g->pool.release();
     g->user_slabs = cfg->n_slabs;
     g->user_cap = cfg->arc_cap;
+    g->no_chunks = cfg->no_arc_chunks ? 1 : 0;
     g->order_mode = cfg->order;
     g->graph_rounds = cfg->graph_rounds ? 1 : 0;
     g->per_pair = cfg->per_pair_launch ? 1 : 0;
@@ -1234,8 +1304,8 @@ int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint6
 int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {
     if (!g || !cfg) return fail(MANTRA_E_INVALID, "graph or config is NULL");
     cfg->n_slabs = auto_slabs(g);
-    int pns = 0;
-    pool_plan(g, cfg->n_slabs, auto_cap(g, cfg->n_slabs), &pns, &cfg->arc_cap);
+    cfg->arc_cap = own_cap(g);
+    cfg->no_arc_chunks = g->no_chunks;
     cfg->order = g->order_mode;
     cfg->graph_rounds = g->graph_rounds;
     cfg->per_pair_launch = g->per_pair;
@@ -1244,8 +1314,29 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {
     return MANTRA_OK;
 }
 
+int mantra_debug_stamps(mantra_graph *g, uint32_t serial, uint32_t tick_stamp) {
+    if (!g) return fail(MANTRA_E_INVALID, "graph is NULL");
+    std::lock_guard<std::mutex> lk(g->mu);
+    hipSetDevice(g->device);
+    int rc = pool_for(g, auto_slabs(g));
+    if (rc) return rc;
+    std::vector<u32> h((size_t)g->pool.nslabs * 4, 0u);
+    for (size_t i = 0; i < (size_t)g->pool.nslabs; ++i) { h[4 * i] = serial; h[4 * i + 1] = tick_stamp; }
+    HIPCHK(hipMemcpy(g->pool.hdr, h.data(), sizeof(u32) * h.size(), hipMemcpyHostToDevice));
+    g->pool.serial_hi = serial;
+    g->pool.tick_hi = tick_stamp;
+    if (g->wide.nslabs) {
+        std::vector<u32> w((size_t)g->wide.nslabs * 4, 0u);
+        for (size_t i = 0; i < (size_t)g->wide.nslabs; ++i) w[4 * i] = serial;
+        HIPCHK(hipMemcpy(g->wide.hdr, w.data(), sizeof(u32) * w.size(), hipMemcpyHostToDevice));
+        g->wide.serial_hi = serial;
+    }
+    return MANTRA_OK;
+}
+
 int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launches, int64_t *window_edges,
-                       int64_t *arcs, int64_t *touched_nodes, int64_t *touched_edges, double *balance) {
+                       int64_t *arcs, int64_t *touched_nodes, int64_t *touched_edges, double *balance,
+                       int64_t *live_batches, int64_t *skipped_batches) {
     if (!g) return fail(MANTRA_E_INVALID, "graph is NULL");
     g_err.clear();
     if (sweep_ms) *sweep_ms = g->last_ms;
@@ -1255,6 +1346,8 @@ int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launche
     if (touched_nodes) *touched_nodes = g->last_tn;
     if (touched_edges) *touched_edges = g->last_te;
     if (balance) *balance = g->last_ms > 0 ? g->last_busy_ms / g->last_ms : 1.0;
+    if (live_batches) *live_batches = g->last_live;
+    if (skipped_batches) *skipped_batches = g->last_dead;
     return MANTRA_OK;
 }
 

@@ -72,19 +72,28 @@ struct SlabPool {
     unsigned char *BM = nullptr;  // reached node bytes (graphs whose bitmap is not in LDS)
     u32 *AGF = nullptr, *hdr = nullptr;
     int32_t *touched = nullptr;
+    // shared arc chunks for pairs whose arcs pass the slab's own buffer
+    u64 *xarcs = nullptr;
+    u32 *xfree = nullptr, *xtab = nullptr;
+    int64_t nchunks = 0, xmax = 0;
+    // largest pair serial and tick stamp of any slab (the wrap guard)
+    u64 serial_hi = 0, tick_hi = 0;
     void release() {
         hipFree(F); hipFree(N); hipFree(AG); hipFree(arcs); hipFree(XS); hipFree(T); hipFree(BM);
-        hipFree(AGF); hipFree(hdr); hipFree(touched);
-        F = N = AG = arcs = XS = T = nullptr;
+        hipFree(AGF); hipFree(hdr); hipFree(touched); hipFree(xarcs); hipFree(xfree); hipFree(xtab);
+        F = N = AG = arcs = XS = T = xarcs = nullptr;
         BM = nullptr;
-        AGF = hdr = nullptr;
+        AGF = hdr = xfree = xtab = nullptr;
         touched = nullptr;
         nslabs = 0;
+        nchunks = xmax = 0;
+        serial_hi = tick_hi = 0;
     }
     DevSlabs view() const {
         DevSlabs s;
         s.F = F; s.N = N; s.T = T; s.AG = AG; s.AGF = AGF; s.touched = touched; s.arcs = arcs;
         s.XS = XS; s.BM = BM; s.hdr = hdr; s.nmax = nmax; s.cap = cap; s.gmax = gmax;
+        s.xarcs = xarcs; s.xfree = xfree; s.xtab = xtab; s.xwords = (nchunks + 31) / 32; s.xmax = xmax;
         return s;
     }
 };
@@ -96,6 +105,7 @@ struct WidePool {
     u64 *ST = nullptr, *SS = nullptr, *RT = nullptr, *RA = nullptr, *NV = nullptr, *TC = nullptr, *AR = nullptr;
     u32 *TL = nullptr, *hdr = nullptr;
     int32_t *touched = nullptr;
+    u64 serial_hi = 0;  // largest pair serial of any slab (the wrap guard)
     void release() {
         hipFree(ST); hipFree(SS); hipFree(RT); hipFree(RA); hipFree(NV); hipFree(TC); hipFree(AR);
         hipFree(TL); hipFree(hdr); hipFree(touched);
@@ -103,6 +113,7 @@ struct WidePool {
         TL = hdr = nullptr;
         touched = nullptr;
         nslabs = 0;
+        serial_hi = 0;
     }
     WideSlabs view() const {
         WideSlabs w;
@@ -138,6 +149,7 @@ struct mantra_graph {
     int64_t wide_cap = 0;
     int user_slabs = 0;
     int64_t user_cap = 0;
+    int no_chunks = 0;              // no shared arc chunks (launch option)
     int order_mode = MANTRA_ORDER_LONGEST_FIRST;
     int hub_nodes = 0;              // forward state of nodes below this id in LDS
     int wide_mode = MANTRA_WIDE_NOT_FM;  // which saturated pairs take the multiword path
@@ -161,7 +173,7 @@ struct mantra_graph {
     std::mutex mu;  // one blocking call at a time per graph
     // timing of the last blocking call
     double last_ms = 0;
-    int64_t last_launches = 0, last_W = 0, last_arcs = 0, last_tn = 0, last_te = 0;
+    int64_t last_launches = 0, last_W = 0, last_arcs = 0, last_tn = 0, last_te = 0, last_live = 0, last_dead = 0;
     double last_busy_ms = 0;
     mantra::ServeState *serve = nullptr;
     mantra::DevGraph dev() const {
@@ -211,10 +223,20 @@ struct RoundGraph {
 };
 
 int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg = nullptr);
+// the work and device time mantra_last_timing reports: cleared by each
+// blocking call, summed over its launches
+void timing_reset(mantra_graph *g);
+void timing_add(mantra_graph *g, const SweepOut &o);
 int reduce_blocks(int64_t n);
 int reduce_part_ensure(mantra_graph *g, int c);
 // persistent workgroups of a launch on this graph
 int auto_slabs(const mantra_graph *g);
+// the reached set of a pair: an LDS bitmap (graphs of up to 65,536 nodes),
+// else node bytes in the slab; bytes of those per slab (0 with the bitmap)
+int lds_bitmap_ok(int64_t nmax);
+size_t node_bytes_per_slab(int64_t nmax);
+// dynamic LDS of a sweep workgroup on this graph (its hub setting included)
+size_t lds_bytes(const mantra_graph *g);
 // default device bytes of the serving scheduler's per-request sums (the slab
 // pool's share of the device reserved)
 size_t serve_sums_budget(const mantra_graph *g);

@@ -205,9 +205,26 @@ struct Slab {
     u64 *T;                // RTB: [nmax][2] first arrival {time | hops << 32, count} of each reached node
     u64 *arcm;             // [cap] head | time << 32
     u64 *arcx;             // [cap][3] edge | tail << 32, tail count, tl | hl << 16
+    u64 *xarcs;            // the launch's shared arc chunks, each laid out as arcm / arcx of kArcChunk arcs
+    u32 *xt;               // [xmax] the chunks this slab holds, in arc order: arc cap + j is in chunk xt[j / kArcChunk]
+    int64_t cap;           // arcs of the slab's own buffer
     u32 *AGF, *hdr;
     int32_t *touched;
+    int32_t id;
 };
+
+// Arc i of the pair: in the slab's own buffer below cap, else in the shared
+// chunks it took (arc records are written and read only through these).
+__device__ __forceinline__ u64 *arc_m(const Slab &S, int64_t i) {
+    if (i < S.cap) return S.arcm + i;
+    const int64_t j = i - S.cap;
+    return S.xarcs + (int64_t)S.xt[j >> kArcChunkBits] * (4 * kArcChunk) + (j & (kArcChunk - 1));
+}
+__device__ __forceinline__ u64 *arc_x(const Slab &S, int64_t i) {
+    if (i < S.cap) return S.arcx + 3 * i;
+    const int64_t j = i - S.cap;
+    return S.xarcs + (int64_t)S.xt[j >> kArcChunkBits] * (4 * kArcChunk) + kArcChunk + 3 * (j & (kArcChunk - 1));
+}
 
 // forward state of the highest-degree nodes (internal ids below K) in LDS:
 // hops and count, valid where the reached bitmap is set (no pair tag)
@@ -226,7 +243,75 @@ struct FwdOut {
     int64_t swept;
     u32 flags;
     int64_t reached_n;    // single source: nodes listed in S.touched
+    u32 live, dead;       // batches that loaded state, batches skipped (no reached tail)
+    int64_t room;         // arcs the slab's buffer and its chunks hold
+    int32_t nch;          // shared chunks the pair holds
 };
+
+__device__ __forceinline__ u32 ld_agent32(const u32 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Takes one free chunk of the launch's shared arc pool (a bitmap of free
+// chunks, bit set = free): the wave scans the map from a per-slab offset, 64
+// words at a time, and claims a set bit with an atomic AND.  Each word is
+// tried until its bits run out, so the scan ends; -1 if no chunk is free.
+__device__ int32_t chunk_take(KArgs &a, int32_t slab) {
+    const int l = lane_id();
+    const int64_t words = a.sl.xwords;
+    if (words <= 0) return -1;
+    const int64_t start = ((int64_t)slab * 97) % words;
+    for (int64_t base = 0; base < words; base += kWave) {
+        const bool valid = base + l < words;
+        int64_t w = start + base + l;
+        if (w >= words) w -= words;
+        const u32 x = valid ? ld_agent32(&a.sl.xfree[w]) : 0u;
+        u64 mk = ballot(x != 0u);
+        while (mk) {
+            const int src = __ffsll((long long)mk) - 1;
+            mk &= mk - 1;
+            u32 xw = (u32)rl32((int)x, src);
+            const int64_t ww = base + src + start >= words ? base + src + start - words : base + src + start;
+            while (xw) {
+                const int b = __ffs((int)xw) - 1;
+                u32 old = 0;
+                if (l == 0)
+                    old = __hip_atomic_fetch_and(&a.sl.xfree[ww], ~(1u << b), __ATOMIC_ACQUIRE,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+                old = (u32)rl32((int)old, 0);
+                if (old & (1u << b)) return (int32_t)(ww * 32 + b);
+                xw = old & ~(1u << b);
+            }
+        }
+    }
+    return -1;
+}
+
+// Room for the pair's arcs [0, need): takes shared chunks while the slab's
+// buffer and its chunks hold fewer.  false (the pair is then re-run with a
+// buffer for every edge) if none is free.  Wave-uniform.
+__device__ bool arc_room(KArgs &a, const Slab &S, FwdOut &o, int64_t need) {
+    while (need > o.room) {
+        if (o.nch >= a.sl.xmax) return false;
+        const int32_t c = chunk_take(a, S.id);
+        if (c < 0) return false;
+        if (lane_id() == 0) S.xt[o.nch] = (u32)c;
+        o.nch += 1;
+        o.room += kArcChunk;
+        __syncthreads();  // every lane's arc addresses read the new table entry
+    }
+    return true;
+}
+
+// gives the pair's chunks back (after every read of its arcs)
+__device__ void chunks_free(KArgs &a, const Slab &S, int32_t nch) {
+    if (nch <= 0) return;
+    __threadfence();
+    for (int i = lane_id(); i < nch; i += kWave) {
+        const u32 c = S.xt[i];
+        __hip_atomic_fetch_or(&a.sl.xfree[c >> 5], 1u << (c & 31), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 // The pair's reached set (forward) and alive set (reverse).  On graphs of
 // up to 65,536 nodes it is a bitmap in LDS (bit v, LDS atomics).  Larger
@@ -246,14 +331,14 @@ __device__ __forceinline__ void rch_set(u32 *bm, int32_t v) {
     else atomicOr(&bm[v >> 5], 1u << (v & 31));
 }
 
-__device__ __forceinline__ void put_arc(const Slab &S, int64_t cap, int64_t pos, int32_t v, int32_t t, u32 k,
+// (room for pos was made by arc_room)
+__device__ __forceinline__ void put_arc(const Slab &S, int64_t pos, int32_t v, int32_t t, u32 k,
                                         int32_t u, u64 tc, u32 tl, u32 hl) {
-    if (pos < cap) {
-        S.arcm[pos] = (u64)(u32)v | ((u64)(u32)t << 32);
-        S.arcx[3 * pos] = (u64)k | ((u64)(u32)u << 32);
-        S.arcx[3 * pos + 1] = tc;
-        S.arcx[3 * pos + 2] = (u64)tl | ((u64)hl << 16);
-    }
+    *arc_m(S, pos) = (u64)(u32)v | ((u64)(u32)t << 32);
+    u64 *x = arc_x(S, pos);
+    x[0] = (u64)k | ((u64)(u32)u << 32);
+    x[1] = tc;
+    x[2] = (u64)tl | ((u64)hl << 16);
 }
 
 // decide the commit of head v at time t given its run's (d, c) and its
@@ -457,7 +542,8 @@ __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, c
         }
         u64 m = ballot(rec);
         if (m) {
-            if (rec) put_arc(S, a.sl.cap, o.arcs + mbcnt(m), v, t, (u32)idx, u, su, hu, d);
+            if (!arc_room(a, S, o, o.arcs + __popcll(m))) { o.flags |= REC_ARCS_LIMIT; return; }
+            if (rec) put_arc(S, o.arcs + mbcnt(m), v, t, (u32)idx, u, su, hu, d);
             o.arcs += __popcll(m);
         }
     }
@@ -526,8 +612,7 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
                     fwd_long_tick<FM, GBM>(a, P, S, bm, H, b0, g1, tlast, agstamp, o, zh, zS, zhit);
                     o.swept = g1 - P.lo;
                     b0 = g1;
-                    if (o.flags & REC_HOPS_LIMIT) return;
-                    if (o.arcs > a.sl.cap) { o.flags |= REC_ARCS_LIMIT; return; }
+                    if (o.flags & (REC_HOPS_LIMIT | REC_ARCS_LIMIT)) return;
                     if (zhit && opt != OPT_SH) done = true;
                     load_batch(a, P, b0, t, u, v, tnext);
                     continue;
@@ -570,8 +655,10 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
             b0 += nbat;
             o.swept = b0 - P.lo;
             t = t2; u = u2; v = v2; tnext = tn2;
+            o.dead += 1;
             continue;
         }
+        o.live += 1;
         {
             // every lane loads (lanes with nothing to load read the origin's
             // state, one line for all of them): no merge of a loaded value
@@ -750,10 +837,10 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
             const bool rec = tight && okr && keep && FM != FWD_DIST;
             const u64 m = ballot(rec);
             if (m) {
-                if (rec) put_arc(S, a.sl.cap, o.arcs + mbcnt(m), v, t, (u32)(b0 + l), u, s_u, h_u, d);
+                if (!arc_room(a, S, o, o.arcs + __popcll(m))) { o.flags |= REC_ARCS_LIMIT; return; }
+                if (rec) put_arc(S, o.arcs + mbcnt(m), v, t, (u32)(b0 + l), u, s_u, h_u, d);
                 o.arcs += __popcll(m);
             }
-            if (o.arcs > a.sl.cap) { o.flags |= REC_ARCS_LIMIT; return; }
             if (zhit && opt != OPT_SH) {
                 done = true;
                 const u64 after = ballot(in && tid >= cut);
@@ -847,15 +934,15 @@ __device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, R
     for (int64_t sb = a0; sb < a1; sb += kWave) {
         int64_t i = sb + l;
         bool inr = i < a1;
-        u64 mm = inr ? S.arcm[i] : 0;
+        u64 mm = inr ? (*arc_m(S, i)) : 0;
         int32_t v = (int32_t)(u32)mm;
         bool act = inr && (v == P.z || alive_test<GBM>(bm, v));
         u64 B = 0, tc = 0;
         u32 k = 0;
         if (act) {
-            u64 x0 = S.arcx[3 * i];
-            tc = S.arcx[3 * i + 1];
-            u32 hl = (u32)(S.arcx[3 * i + 2] >> 16) & 0xFFFFu;
+            u64 x0 = arc_x(S, i)[0];
+            tc = arc_x(S, i)[1];
+            u32 hl = (u32)(arc_x(S, i)[2] >> 16) & 0xFFFFu;
             k = (u32)x0;
             bool valid = false;
             u32 lvl = 0;
@@ -875,8 +962,8 @@ __device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, R
         if (i >= a1) continue;
         u64 B = S.XS[i - a0];
         if (!B) continue;
-        int32_t u = (int32_t)(S.arcx[3 * i] >> 32);
-        u32 tl = (u32)S.arcx[3 * i + 2] & 0xFFFFu;
+        int32_t u = (int32_t)(arc_x(S, i)[0] >> 32);
+        u32 tl = (u32)arc_x(S, i)[2] & 0xFFFFu;
         u32 want = P.level ? tl : 0u;
         u64 th = ld_agent(&S.R[2 * (int64_t)u]);
         if ((u32)th != P.rtag || ((u32)(th >> 32) & 0xFFFFu) != want) {
@@ -891,7 +978,7 @@ __device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, R
         if (i >= a1) continue;
         u64 B = S.XS[i - a0];
         if (!B) continue;
-        int32_t u = (int32_t)(S.arcx[3 * i] >> 32);
+        int32_t u = (int32_t)(arc_x(S, i)[0] >> 32);
         atomicAdd((unsigned long long *)&S.R[2 * (int64_t)u + 1], (unsigned long long)B);
         alive_set<GBM>(bm, u);
     }
@@ -917,7 +1004,7 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
         for (int j = 0; j < kE; ++j) {
             int off = j * kWave + l;
             in[j] = off < nb;
-            u64 mm = in[j] ? S.arcm[blo + off] : 0;
+            u64 mm = in[j] ? (*arc_m(S, blo + off)) : 0;
             vv[j] = (int32_t)(u32)mm;
             tt[j] = in[j] ? (int32_t)(mm >> 32) : INT32_MIN;
             al[j] = in[j] && (vv[j] == P.z || alive_test<GBM>(bm, vv[j]));
@@ -929,7 +1016,7 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
         int cut = 0;
         if (blo > 0) {
             int32_t t_first = rl32(tt[0], 0);
-            int32_t t_before = (int32_t)(S.arcm[blo - 1] >> 32);
+            int32_t t_before = (int32_t)((*arc_m(S, blo - 1)) >> 32);
             if (t_before == t_first) {
                 int firstdiff = -1;
 #pragma unroll
@@ -942,7 +1029,7 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
                     for (int64_t i = blo - kWave; ; i -= kWave) {
                         int64_t idx = i + l;
                         bool okk = idx >= 0 && idx < blo;
-                        bool diff = okk && (int32_t)(S.arcm[idx] >> 32) != t_first;
+                        bool diff = okk && (int32_t)((*arc_m(S, idx)) >> 32) != t_first;
                         u64 m = ballot(diff);
                         if (m) { a0 = i + (63 - __clzll((long long)m)) + 1; break; }
                         if (i <= 0) { a0 = 0; break; }
@@ -970,9 +1057,9 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
             int32_t tp = __shfl_up(tt[j], 1);
             if (l == 0) tp = j > 0 ? rl32(tt[j - 1], kWave - 1) : INT32_MIN;
             gm[j] = ballot(in[j] && (off == cut || tt[j] != tp));
-            u64 x0 = in[j] ? S.arcx[3 * (blo + off)] : 0;
-            tc[j] = in[j] ? S.arcx[3 * (blo + off) + 1] : 0;
-            u64 x2 = in[j] ? S.arcx[3 * (blo + off) + 2] : 0;
+            u64 x0 = in[j] ? arc_x(S, blo + off)[0] : 0;
+            tc[j] = in[j] ? arc_x(S, blo + off)[1] : 0;
+            u64 x2 = in[j] ? arc_x(S, blo + off)[2] : 0;
             kk[j] = (u32)x0;
             uu[j] = (int32_t)(x0 >> 32);
             tl[j] = (u32)x2 & 0xFFFFu;
@@ -1211,14 +1298,14 @@ __device__ bool trk_walk(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, 
         for (int64_t b = 0; b < hi; b += kWave) {
             const int64_t i = b + l;
             if (i >= hi) continue;
-            const u64 mm = S.arcm[i];
+            const u64 mm = (*arc_m(S, i));
             if ((int32_t)(u32)mm != node) continue;
             const int32_t ti = (int32_t)(mm >> 32);
-            const u32 hl = (u32)(S.arcx[3 * i + 2] >> 16) & 0xFFFFu;
+            const u32 hl = (u32)(arc_x(S, i)[2] >> 16) & 0xFFFFu;
             bool c;
             if (term) c = P.opt == OPT_SH ? hl == lvl : ti == t_arr;
             else c = ti < tmax && (!P.level || hl == lvl);
-            if (c) part = sat_add(part, S.arcx[3 * i + 1]);
+            if (c) part = sat_add(part, arc_x(S, i)[1]);
         }
         for (int o = kWave / 2; o > 0; o >>= 1) part = sat_add(part, shfl64(part, l ^ o));
         u64 W = uni64(part);
@@ -1234,14 +1321,14 @@ __device__ bool trk_walk(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, 
             const int64_t i = b + l;
             u64 wt = 0;
             if (i < hi) {
-                const u64 mm = S.arcm[i];
+                const u64 mm = (*arc_m(S, i));
                 if ((int32_t)(u32)mm == node) {
                     const int32_t ti = (int32_t)(mm >> 32);
-                    const u32 hl = (u32)(S.arcx[3 * i + 2] >> 16) & 0xFFFFu;
+                    const u32 hl = (u32)(arc_x(S, i)[2] >> 16) & 0xFFFFu;
                     bool c;
                     if (term) c = P.opt == OPT_SH ? hl == lvl : ti == t_arr;
                     else c = ti < tmax && (!P.level || hl == lvl);
-                    if (c) wt = S.arcx[3 * i + 1];
+                    if (c) wt = arc_x(S, i)[1];
                 }
             }
             // inclusive scan of the weights over the wave (no wrap: the
@@ -1257,12 +1344,12 @@ __device__ bool trk_walk(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, 
             else carry += rl64(x, kWave - 1);
         }
         if (pick < 0) return false;
-        const u64 x0 = S.arcx[3 * pick];
+        const u64 x0 = arc_x(S, pick)[0];
         const int32_t k = (int32_t)(u32)x0;           // stream index of the edge
         const int32_t tail = (int32_t)(x0 >> 32);
-        const u32 tl = (u32)S.arcx[3 * pick + 2] & 0xFFFFu;
-        const int32_t tp = (int32_t)(S.arcm[pick] >> 32);
-        const u64 tcp = S.arcx[3 * pick + 1];
+        const u32 tl = (u32)arc_x(S, pick)[2] & 0xFFFFu;
+        const int32_t tp = (int32_t)((*arc_m(S, pick)) >> 32);
+        const u64 tcp = arc_x(S, pick)[1];
         // visit counts in the slab's N (zero between pairs) and the list of
         // the distinct internal nodes, as the reverse sweep leaves them
         if (tail != P.s && tail != P.z) {
@@ -1311,11 +1398,11 @@ __device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, R
     int64_t ac = narcs;
     while (ac > 0) {
         // the tick [a0, ac) of the newest arcs left
-        const int32_t th = (int32_t)(S.arcm[ac - 1] >> 32);
+        const int32_t th = (int32_t)((*arc_m(S, ac - 1)) >> 32);
         int64_t a0 = 0;
         for (int64_t i0 = ac - kWave;; i0 -= kWave) {
             const int64_t i = i0 + l;
-            const bool diff = i >= 0 && i < ac && (int32_t)(S.arcm[i] >> 32) != th;
+            const bool diff = i >= 0 && i < ac && (int32_t)((*arc_m(S, i)) >> 32) != th;
             const u64 m = ballot(diff);
             if (m) { a0 = i0 + (63 - __clzll((long long)m)) + 1; break; }
             if (i0 <= 0) { a0 = 0; break; }
@@ -1326,13 +1413,13 @@ __device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, R
             bool first = false, nz = false;
             int32_t v = 0;
             if (i < ac) {
-                const u64 mm = S.arcm[i];
+                const u64 mm = (*arc_m(S, i));
                 v = (int32_t)(u32)mm;
                 const int32_t t = (int32_t)(mm >> 32);
-                const u64 x0 = S.arcx[3 * i];
+                const u64 x0 = arc_x(S, i)[0];
                 const u32 k = (u32)x0;
-                const u64 tc = S.arcx[3 * i + 1];
-                const u32 hl = (u32)(S.arcx[3 * i + 2] >> 16) & 0xFFFFu;
+                const u64 tc = arc_x(S, i)[1];
+                const u32 hl = (u32)(arc_x(S, i)[2] >> 16) & 0xFFFFu;
                 if (tc == kUMax) bad = true;
                 double thru = 0.0;
                 const u64 tw = ld_agent(&S.R[2 * (int64_t)v]);
@@ -1371,8 +1458,8 @@ __device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, R
             const int64_t i = sb + l;
             if (i >= ac) continue;
             if (S.XS[i - a0] == 0ull) continue;
-            const int32_t u = (int32_t)(S.arcx[3 * i] >> 32);
-            const u32 want = P.level ? ((u32)S.arcx[3 * i + 2] & 0xFFFFu) : 0u;
+            const int32_t u = (int32_t)(arc_x(S, i)[0] >> 32);
+            const u32 want = P.level ? ((u32)arc_x(S, i)[2] & 0xFFFFu) : 0u;
             const u64 tw = ld_agent(&S.R[2 * (int64_t)u]);
             if ((u32)tw != P.rtag || ((u32)(tw >> 32) & 0xFFFFu) != want) {
                 S.R[2 * (int64_t)u] = (u64)P.rtag | ((u64)want << 32);
@@ -1385,7 +1472,7 @@ __device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, R
             if (i >= ac) continue;
             const u64 cb = S.XS[i - a0];
             if (cb == 0ull) continue;
-            const int32_t u = (int32_t)(S.arcx[3 * i] >> 32);
+            const int32_t u = (int32_t)(arc_x(S, i)[0] >> 32);
             atomicAdd(reinterpret_cast<double *>(&S.R[2 * (int64_t)u + 1]), __longlong_as_double((long long)cb));
         }
         __syncthreads();
@@ -1408,6 +1495,10 @@ __device__ __forceinline__ Slab slab_of(KArgs &a, int64_t slab) {
     S.touched = a.sl.touched + slab * a.sl.nmax;
     S.arcm = a.sl.arcs + slab * a.sl.cap * 4;
     S.arcx = S.arcm + a.sl.cap;
+    S.cap = a.sl.cap;
+    S.xarcs = a.sl.xarcs;
+    S.xt = a.sl.xtab + slab * a.sl.xmax;
+    S.id = (int32_t)slab;
     S.XS = a.sl.XS + slab * a.sl.gmax * 2;
     S.T = a.sl.T ? a.sl.T + slab * a.sl.nmax * 2 : nullptr;
     S.hdr = a.sl.hdr + slab * 4;
@@ -1485,6 +1576,9 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
         FwdOut fo;
         fo.reached = false; fo.zh = kHInf; fo.zS = 0; fo.t_arr = -1; fo.arcs = 0; fo.swept = 0; fo.flags = 0;
         fo.reached_n = 0;
+        fo.room = S.cap;
+        fo.nch = 0;
+        fo.live = fo.dead = 0;
         if (ok) {
             P.lo = wave_lower_bound(a.g.T, P.elo, P.ehi, dep);
             P.hi = wave_upper_bound(a.g.T, P.lo, P.ehi, lin);
@@ -1545,7 +1639,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
                 flags |= REC_OVERFLOW;
                 if (a.edge_f)
                     for (int64_t i = l; i < fo.arcs; i += kWave)
-                        a.edge_f[P.qout * a.g.m + (int64_t)(u32)S.arcx[3 * i]] = 0.0;
+                        a.edge_f[P.qout * a.g.m + (int64_t)(u32)arc_x(S, i)[0]] = 0.0;
             } else {
                 // every reached target contributes exactly one to the origin
                 const u64 tw = ld_agent(&S.R[2 * (int64_t)P.s]);
@@ -1575,7 +1669,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
             flags |= REC_OVERFLOW;
             if (a.edge_f)
                 for (int64_t i = l; i < fo.arcs; i += kWave)
-                    a.edge_f[P.qout * a.g.m + (int64_t)(u32)S.arcx[3 * i]] = 0.0;
+                    a.edge_f[P.qout * a.g.m + (int64_t)(u32)arc_x(S, i)[0]] = 0.0;
         }
         // finalize: f(v) = N(v) / sigma into the sums; reset N
         bool accum = do_rev && !(flags & REC_OVERFLOW);
@@ -1597,6 +1691,8 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
             }
             if (a.node_f) a.node_f[P.qout * (int64_t)a.g.n_total + gv] = f;
         }
+        // the pair's arcs are read no more: its shared chunks go back
+        chunks_free(a, S, fo.nch);
         if (l == 0) {
             if (a.rec) {
                 int32_t *rr = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(a.rec) + P.qout * 24);
@@ -1623,6 +1719,8 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
             if (flags & REC_HOPS_LIMIT) atomicAdd((unsigned long long *)&a.stats[4], 1ull);
             if (flags & REC_SELFCHECK) atomicAdd((unsigned long long *)&a.stats[6], 1ull);
             atomicAdd((unsigned long long *)&a.stats[7], (unsigned long long)X.touched_n);
+            atomicAdd((unsigned long long *)&a.stats[14], (unsigned long long)fo.live);
+            atomicAdd((unsigned long long *)&a.stats[15], (unsigned long long)fo.dead);
             atomicAdd((unsigned long long *)&a.stats[8], (unsigned long long)X.edges_n);
             if (R->rstat && !(flags & REC_ARCS_LIMIT)) {
                 if ((flags & REC_OVERFLOW) && !defer) atomicAdd((unsigned long long *)&R->rstat[0], 1ull);
@@ -1650,6 +1748,9 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
         atomicAdd((unsigned long long *)&a.stats[9], (unsigned long long)(t_end - t_begin));
         atomicMax((unsigned long long *)&a.stats[10], (unsigned long long)t_end);
         atomicMax((unsigned long long *)&a.stats[11], (unsigned long long)~t_begin);
+        // the slab's pair serial and tick stamp, for the host's wrap guard
+        atomicMax((unsigned long long *)&a.stats[12], (unsigned long long)serial);
+        atomicMax((unsigned long long *)&a.stats[13], (unsigned long long)agstamp);
     }
 }
 
@@ -2010,6 +2111,7 @@ __global__ void __launch_bounds__(64) k_wide(LaunchArgs a_arg, WideSlabs ws) {
         (void)swept;
     }
     ws.hdr[slab * 4] = serial;
+    atomicMax((unsigned long long *)&a.stats[12], (unsigned long long)serial);
 }
 
 // ------------------------------------------------------------ pair order

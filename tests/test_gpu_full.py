@@ -78,6 +78,25 @@ def test_big_pfm_prefix_sums_against_oracle(big):
     assert abs(res["mcera"] - ref["Rc"]) <= 1e-12 * max(scale, 1e-300)
 
 
+def test_big_autotune(big):
+    """The autotuner on the n = 10^6 graph, where device memory bounds the
+    grid (candidate grids reallocate the slab pool and its shared arc
+    chunks): it keeps a configuration, and a fixed sample run under it gives
+    the same sums as under the automatic one."""
+    G, gg, og = big
+    base, _, r0 = gg.run("pfm", fixed_r=512, seed=2013, c=16)
+    tuned = gg.autotune("pfm", sample_pairs=1024, seed=2014)
+    try:
+        assert tuned["n_slabs"] >= 1 and tuned["arc_cap"] >= 1
+        assert gg.get_launch()["n_slabs"] == tuned["n_slabs"]
+        nb, _, r1 = gg.run("pfm", fixed_r=512, seed=2013, c=16)
+        assert r1["rc"] == 0 and r1["n_reachable"] == r0["n_reachable"]
+        ok, worst = rel_close(nb, base, rel=1e-12, abs_floor=1e-300)
+        assert ok, worst
+    finally:
+        gg.set_launch(0, 0)
+
+
 @pytest.fixture(scope="module")
 def packed(lib):
     gs = workload("packed-256")

@@ -145,15 +145,41 @@ def test_duplicates_and_validation(lib):
         g.count_pairs("sh", [1], [1])  # s == z
 
 
-def test_arc_capacity_retry(tiny_workload):
-    """Pairs whose DAG arcs exceed the slab buffer are re-run with a full
-    window buffer; results are unchanged."""
+def test_arc_chunks_and_retry(tiny_workload):
+    """Pairs whose DAG arcs exceed the workgroup's own buffer take chunks of
+    the launch's shared arc pool (one launch); with no shared chunks they are
+    re-run after the launch with a full-window buffer (two launches).
+    Results are unchanged either way."""
     G, gg, og = tiny_workload
     S, Z = oracle.draw_pairs(11, 0, G.n, 0, 300)
-    gg.set_launch(n_slabs=32, arc_cap=1024)
     try:
-        compare_pairs(gg, og, "sh", S, Z, ctx="retry")
-        compare_pairs(gg, og, "fm", S, Z, ctx="retry-fm")
+        for no_chunks, launches in ((False, 1), (True, 2)):
+            gg.set_launch(n_slabs=32, arc_cap=64, no_arc_chunks=no_chunks)
+            assert gg.get_launch()["arc_cap"] == 64 and gg.get_launch()["no_arc_chunks"] == int(no_chunks)
+            compare_pairs(gg, og, "sh", S, Z, ctx="chunks%d" % no_chunks)
+            assert gg.last_timing()["launches"] == launches, no_chunks
+            compare_pairs(gg, og, "fm", S, Z, ctx="chunks-fm%d" % no_chunks)
+    finally:
+        gg.set_launch(0, 0)
+
+
+def test_stamp_wrap_guard(lib):
+    """Slab state words are tagged with 32-bit pair serials and tick stamps
+    that slabs carry across launches.  Seeded just below the wrap (after a
+    first launch left tagged words in the slabs), and past half the range,
+    the results still match the oracle: the library clears the tagged state
+    before a serial or stamp could wrap."""
+    from paper_2304_08356_amd import _lib
+    G = uniform_graph(80, 4000, 6, seed=78)  # long ticks: the tick stamps move too
+    gg, og = both(lib, G)
+    S, Z = oracle.draw_pairs(6, 0, G.n, 0, 200)
+    gg.set_launch(n_slabs=8)
+    try:
+        for opt in ("sh", "pfm"):
+            compare_pairs(gg, og, opt, S, Z, ctx="stamps-before")
+            for serial, tick in ((2**32 - 12, 2**32 - 3), (2**31 + 6, 2**31 + 1), (7, 2**32 - 2)):
+                assert _lib._lib.mantra_debug_stamps(gg._h, serial, tick) == 0
+                compare_pairs(gg, og, opt, S, Z, ctx="stamps-%d-%d" % (serial, tick))
     finally:
         gg.set_launch(0, 0)
 
@@ -162,6 +188,20 @@ def test_arc_capacity_retry(tiny_workload):
 def mid_workload(lib):
     G = workload("mid-chunglu-n50k")
     return G, lib.Graph.of(G), oracle.Graph.of(G)
+
+
+def test_mid_workload_shared_arc_chunks(mid_workload):
+    """Full size with a small own arc buffer (4,096 arcs): most pairs write
+    their arcs into shared chunks taken and given back across the launch."""
+    G, gg, og = mid_workload
+    S, Z = oracle.draw_pairs(2002, oracle.STREAM_PAIR, G.n, 0, 12)
+    gg.set_launch(arc_cap=4096)
+    try:
+        compare_pairs(gg, og, "sfm", S, Z, mode=1, ctx="C2-chunks")
+        assert gg.last_timing()["launches"] == 1
+        compare_pairs(gg, og, "sh", S[:4], Z[:4], mode=1, edges=False, ctx="C2-chunks-sh")
+    finally:
+        gg.set_launch(0, 0)
 
 
 def test_mid_workload_sampled_pairs_sfm(mid_workload):
