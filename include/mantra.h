@@ -117,6 +117,25 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
                        const int32_t *graph, const int32_t *s, const int32_t *z,
                        mantra_pair_record *out, double *node_f, double *edge_f);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture of the surrounding work, tight serving loops, harnesses that
+ * forbid hipMalloc): the records of mantra_count_pairs (no dense outputs)
+ * computed without any device allocation.  Every buffer beyond the graph --
+ * the per-pair node state and arc records of up to 64 workgroups, the launch
+ * counters, the pairs and the records -- lives in one device array of the
+ * library, 256 MiB, that each GPU holds from the library's load until the
+ * process ends.  A workgroup holds an arc record for every edge of the
+ * graph, so the graph must fit: one workgroup needs 28 B per node (+1 B per
+ * node above 65,536 nodes) + 36 B per edge of the longest tick + 32 B per
+ * edge, and the pairs 36 B each; beyond the array MANTRA_E_TOO_LARGE.  Pairs
+ * whose counts pass 2^64 carry MANTRA_REC_OVERFLOW (no 256-bit re-count: that
+ * path allocates).  Calls on one GPU share the array and would race; the
+ * library serializes them per device.  Arguments, outputs and the other
+ * errors as mantra_count_pairs; blocking. */
+int mantra_count_pairs_static(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, int64_t r,
+                              const int32_t *graph, const int32_t *s, const int32_t *z,
+                              mantra_pair_record *out);
+
 /* The TRK estimator's walks for r explicit pairs (arguments and outputs as
  * mantra_count_pairs): one optimal walk per reachable pair, drawn backwards
  * from z with probability 1/sigma_sz (the appendix's path sampler, Theorem on

@@ -78,6 +78,7 @@ SIGNATURES = {
     "mantra_graph_destroy": (None, [P]),
     "mantra_graph_info": (I32, [P, P, P, P, P, P, P]),
     "mantra_count_pairs": (I32, [P, I32, I32, I32, I64, P, P, P, P, P, P]),
+    "mantra_count_pairs_static": (I32, [P, I32, I32, I32, I64, P, P, P, P]),
     "mantra_sample_paths": (I32, [P, I32, I32, I32, I64, P, P, P, U64, P, P, P]),
     "mantra_source_dependencies": (I32, [P, I32, I32, I32, I64, P, P, P, P, P]),
     "mantra_estimate": (I32, [P, I32, F64, F64, U64, P]),

@@ -12,7 +12,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmantra.so")
-SOURCES = ["mantra_sweep.hip", "mantra_host.hip", "mantra_serve.hip"]
+SOURCES = ["mantra_sweep.hip", "mantra_host.hip", "mantra_serve.hip", "mantra_static.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-munsafe-fp-atomics",
          # packed fp32 instructions are kept out of every kernel
