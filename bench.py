@@ -1,38 +1,39 @@
 """Benchmark of the temporal-betweenness hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--slabs N]
-                    [--no-forms] [--no-serve] [--no-trk] [--no-rtb] [--no-distances]
-                    [--no-cpu-baseline]
+                    [--no-mid] [--no-forms] [--no-serve] [--no-trk] [--no-rtb] [--no-distances]
+                    [--no-optimalities] [--no-cpu-baseline]
     python bench.py --calibrate-copy     (plain copy kernel for the traffic counters)
     python bench.py --batching           (n = 10^6 Algorithm 1 and the 256 packed graphs)
-    python bench.py --serve-only [--serve-workload NAME] [--serve-requests K]
+    python bench.py --serve-only [--serve-workload NAME] [--serve-requests K] [--serve-rate R]
 
-Workload "mid-chunglu-n50k": directed Chung-Lu temporal graph (degree
-exponent 2.3, n = 50,000, |E| = 2,000,000, bursty Pareto(1.5) renewal
-timestamps over 10^5 ticks), shortest-foremost paths, a fixed sample of
-r = 20,000 pairs per step, node and temporal-edge betweenness, c = 25
-Rademacher vectors.  One step = one whole pass of the hot path: pair and sign
-sampling, launch ordering, forward sweep, reverse dependency sweep,
-accumulation of the estimator sums, the MCERA reduction and the bound on the
-host.  The graph is resident in HBM before the timed region.
+Headline workload "serve-chunglu-n2m", the largest graph of the workloads:
+directed Chung-Lu temporal graph (degree exponent 2.3, n = 2,000,000,
+|E| = 50,000,000, bursty Pareto(1.5) renewal timestamps over 10^6 ticks),
+shortest-foremost paths over the whole span, a fixed sample of R pairs per
+step, node and temporal-edge betweenness, c = 25 Rademacher vectors.  One
+step = one whole pass of the hot path: pair and sign sampling, launch
+ordering, forward sweep, reverse dependency sweep, accumulation of the
+estimator sums, the MCERA reduction and the bound on the host, and the
+estimates copied to host arrays.  The graph is resident in HBM before the
+timed region.
 
 Prints one JSON line (value: sampled pairs/s of the steps) with
  - "roofline": the sweep kernel's algorithmic bytes per launch over its mean
    HIP-event duration, against the HBM peak; "traffic" is the DRAM bytes per
    launch that rocprofv3's FETCH_SIZE / WRITE_SIZE counters read for this
-   kernel source (null once the source differs from the profiled one);
- - "forms": Algorithm 1 at eps = 0.01, delta = 0.1 on the same graph, as
-   persistent launches, as one replayed HIP graph per round, and the
-   unbatched one-launch-per-pair form (timed on a fixed sample);
- - "serve": requests with Poisson arrivals (random windows, optimalities,
-   eps in {0.01, 0.005}) through the serving scheduler: p50/p99 latency;
- - "trk": the same step with the TRK estimator (one sampled optimal walk per
-   pair instead of the dependency sweep);
- - "rtb": the RTB estimator (sampled sources, all targets) on the same graph;
- - "distances": Algorithm 2 (sampled temporal distance metrics) from 256
-   sources, the paper's seed count, for sh and pfm on the same graph, with
-   the oracle's per-source distances timed beside it on 32 sources;
- - "cpu_baseline": the oracle on the host's cores, on a bounded sample.
+   kernel source at this workload and grid (null once either differs);
+ - "optimalities": fixed samples of the other optimalities on the same graph;
+ - "plain": the unbatched form (one launch per pair) on the step's first
+   pairs, against the step's rate;
+ - "cpu_baseline": the oracle on the host's cores (all of them, and one), on
+   the first pairs of the step's pair stream;
+ - "mid": the mid-size workload "mid-chunglu-n50k" (n = 50,000, |E| = 2*10^6,
+   sfm, r = 20,000 per step) with its own roofline, and on it: "forms"
+   (Algorithm 1 at eps = 0.01, delta = 0.1 batched, as replayed HIP graphs,
+   served, and one launch per pair), "serve" (requests with Poisson
+   arrivals), "trk", "rtb" and "distances" (the other estimators and
+   Algorithm 2).
 """
 import argparse
 import hashlib
@@ -46,30 +47,52 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "sampled pairs/s + temporal edges/s (HBM GB/s vs peak); p50/p99 request latency"
-WORKLOAD = "mid-chunglu-n50k"
+WORKLOAD = "serve-chunglu-n2m"
 OPT = "sfm"
-R_PER_STEP = 20_000
+R_PER_STEP = 4096
 C = 25
+MID = "mid-chunglu-n50k"
+MID_R = 20_000
 HBM_PEAK_GBS = 8000.0
 SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip")
 
-# DRAM traffic of the sweep kernel on the step above (rocprofv3 --pmc
-# FETCH_SIZE, then WRITE_SIZE, summed over the k_sweep dispatches of the
-# profiled run, divided by their count, and scaled by the ratio of bytes to
-# counter bytes that the same counters give for a plain copy of known size),
-# valid for the kernel source with this SHA-256 only, profiled at a fixed
-# grid of 2,880 slabs (the autotuned grid of a run may differ).
-TRAFFIC = {
-    "slabs": 2880,
-    "sweep_sha256": "a67e4431b25d0edfa880a551c0bc9657cf95bcc31eb000ac9cc62522fbd7ba2c",
-    "fetch_bytes_per_launch": 4.9171e+11,   # 2.40101e+08 KiB x 1.99995
-    "write_bytes_per_launch": 7.8496e+10,   # 7.66559e+07 KiB x 1.00000
-}
+# Launch configuration of the headline step: 2,048 hub nodes' state in LDS,
+# the grid the device keeps resident with that LDS (1,536 single-wave
+# workgroups), the rest automatic.  Taken from a sweep of grids and hub
+# counts on this graph (the design notes give it); the autotuner itself
+# would take minutes here.
+HEADLINE_LAUNCH = {"n_slabs": 0, "hub_nodes": 2048}
+
+# DRAM traffic of the sweep kernel (rocprofv3 --pmc FETCH_SIZE, then
+# WRITE_SIZE, summed over the k_sweep dispatches of the profiled run, divided
+# by their count, and scaled by the ratio of bytes to counter bytes that the
+# same counters give for a plain copy of known size), per workload, valid for
+# the kernel source with the given SHA-256 at the given grid only.
+TRAFFIC = {}
 
 
 def sha256(path):
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
 
 
 def algorithmic_bytes(t, c):
@@ -81,27 +104,119 @@ def algorithmic_bytes(t, c):
             + 8 * t["touched_edges"])
 
 
-def cpu_baseline(G, seed, budget_s=15.0):
-    import oracle
-    og = oracle.Graph.of(G)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    done = 0
-    t_used = 0.0
-    batch = 2 * threads
-    while t_used < budget_s and done < R_PER_STEP:
-        S, Z = oracle.draw_pairs(seed, oracle.STREAM_PAIR, G.n, done, batch)
-        lam = oracle.rade_words(seed, done, batch)
+def hbm_frac(t, c):
+    """Algorithmic bytes of a call's sweep launches over their summed HIP-event
+    duration, as a fraction of the HBM peak."""
+    if t["sweep_ms"] <= 0:
+        return None
+    return algorithmic_bytes(t, c) / (t["sweep_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
+
+
+def traffic_of(workload, slabs):
+    tr = TRAFFIC.get(workload)
+    if not tr or tr["sweep_sha256"] != sha256(SWEEP_SRC) or tr["slabs"] != slabs:
+        return None
+    return tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+
+
+def timed_steps(gg, torch, opt, r, steps, warmup, seed, c=C):
+    """warmup + steps fixed samples of r pairs (node and edge sums); totals of
+    the timed steps."""
+    for i in range(warmup):
+        gg.run(opt, fixed_r=r, seed=seed + 1000 + i, c=c, edges=True)
+    torch.cuda.synchronize()
+    tot = {"sweep_ms": 0.0, "launches": 0, "window_edges": 0, "arcs": 0, "touched_nodes": 0,
+           "touched_edges": 0}
+    bal = 0.0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        _, _, res = gg.run(opt, fixed_r=r, seed=seed + k, c=c, edges=True)
+        t = gg.last_timing()
+        for key in tot:
+            tot[key] += t[key]
+        bal += t["balance"] * t["sweep_ms"]
+        log("step %d: %.1f ms sweep, %d launches" % (k, t["sweep_ms"], t["launches"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return tot, wall, bal / max(tot["sweep_ms"], 1e-9)
+
+
+def roofline(tot, workload, slabs, kernel="mantra::k_sweep<0>"):
+    kern_ms = tot["sweep_ms"] / max(1, tot["launches"])
+    abytes = algorithmic_bytes(tot, C) / max(1, tot["launches"])
+    achieved = abytes / (kern_ms / 1e3) / 1e9
+    traffic = traffic_of(workload, slabs)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "algorithmic_bytes_per_launch": abytes, "sweep_ms_per_launch": kern_ms,
+            "traffic_slabs": TRAFFIC[workload]["slabs"] if traffic is not None else None}
+
+
+class OracleOneThread(threading.Thread):
+    """The oracle on one thread (the first pair of the step's pair stream),
+    run beside the GPU sections that follow the timed steps: a host core the
+    GPU work does not use."""
+
+    def __init__(self, og, n, seed, opt, c=C):
+        super().__init__(daemon=True)
+        self.og, self.n, self.seed, self.opt, self.c = og, n, seed, opt, c
+        self.dt = None
+
+    def run(self):
+        import oracle
+        S, Z = oracle.draw_pairs(self.seed, oracle.STREAM_PAIR, self.n, 0, 1)
+        lam = oracle.rade_words(self.seed, 0, 1)
         t0 = time.perf_counter()
-        oracle.accumulate(og, OPT, S, Z, lam, c=C, mode=1, edges=True, nthreads=threads)
+        oracle.accumulate(self.og, self.opt, S, Z, lam, c=self.c, mode=1, edges=True, nthreads=1)
+        self.dt = time.perf_counter() - t0
+
+
+def cpu_baseline(og, n, seed, opt, one=None, c=C, t_budget=30.0):
+    """The oracle (mode 1, OpenMP over pairs) on the first pairs of the step's
+    pair stream, on every host thread (one pair per thread, repeated while
+    within the budget); and its one-thread figure (one pair)."""
+    import oracle
+    if one is not None:
+        one.join()  # the one-thread run ends before every thread is busy
+    threads = host_threads()
+    out = {"unit": "pairs/s", "kind": "oracle", "cpu_model": cpu_model(), "cores": threads}
+    done, t_used = 0, 0.0
+    while done == 0 or (t_used < t_budget and done < 64 * threads):
+        S, Z = oracle.draw_pairs(seed, oracle.STREAM_PAIR, n, done, threads)
+        lam = oracle.rade_words(seed, done, threads)
+        t0 = time.perf_counter()
+        oracle.accumulate(og, opt, S, Z, lam, c=c, mode=1, edges=True, nthreads=threads)
         t_used += time.perf_counter() - t0
-        done += batch
-    return {"value": done / t_used, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d pairs of the step's pair stream (sfm, c=%d, node+edge sums), %.1f s" % (
-                done, C, t_used)}
+        done += threads
+    out["value"] = done / t_used
+    out["sample"] = "first %d pairs of the step's pair stream (%s, c=%d, node+edge sums), %.1f s on %d threads" % (
+        done, opt, c, t_used, threads)
+    if one is None:
+        one = OracleOneThread(og, n, seed, opt, c)
+        one.run()
+    out["value_1_thread"] = 1.0 / one.dt
+    out["sample_1_thread"] = "the first pair of the same stream on one thread, %.1f s" % one.dt
+    return out
+
+
+def plain_fixed(gg, torch, opt, r, seed, tuned):
+    """The unbatched form (one single-workgroup launch per pair) on the first
+    r pairs of the step's pair stream."""
+    gg.set_launch(**tuned_launch(tuned, per_pair_launch=True))
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gg.run(opt, fixed_r=r, seed=seed, c=C, edges=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        gg.set_launch(**tuned_launch(tuned))
+    return {"pairs": r, "wall_s": wall, "pairs_per_s": r / wall,
+            "note": "first %d pairs of the step's pair stream, one launch per pair" % r}
 
 
 def tuned_launch(tuned, **over):
-    """set_launch arguments that restore an autotuned configuration (arc room
+    """set_launch arguments that restore a launch configuration (arc room
     left automatic), with the given overrides."""
     cfg = {"n_slabs": tuned["n_slabs"], "order": tuned["order"], "hub_nodes": tuned["hub_nodes"],
            "wide_counts": tuned["wide_counts"]}
@@ -109,9 +224,36 @@ def tuned_launch(tuned, **over):
     return cfg
 
 
+def optimalities(gg, torch, seed, plan):
+    """Fixed samples of the given optimalities on the headline graph (node and
+    edge sums, c = 25): pairs/s, window edges/s and the roofline fraction."""
+    out = {}
+    for opt, r in plan:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, res = gg.run(opt, fixed_r=r, seed=seed, c=C, edges=True, raise_on_error=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        t = gg.last_timing()
+        out[opt] = {"pairs": r, "rc": res["rc"], "n_overflow": res["n_overflow"], "wall_s": wall,
+                    "pairs_per_s": r / wall, "sweep_ms": t["sweep_ms"], "launches": t["launches"],
+                    "temporal_edges_per_s": t["window_edges"] / max(t["sweep_ms"] / 1e3, 1e-9),
+                    "mean_window_edges": t["window_edges"] / r, "mean_arcs": t["arcs"] / r,
+                    "hbm_frac": hbm_frac(t, C), "grid_balance": t["balance"]}
+        log("%s: %s" % (opt, json.dumps(out[opt])))
+    return out
+
+
+# ------------------------------------------------------------------ mid-size workload
+
+
 def forms(gg, torch, seed, tuned):
-    """Algorithm 1 at eps = 0.01, delta = 0.1 (sfm, c = 25) in three launch
-    forms; the autotuned configuration is in force again afterwards."""
+    """Algorithm 1 at eps = 0.01, delta = 0.1 (sfm, c = 25) in four launch
+    forms on the same request: persistent launches, rounds replayed from one
+    captured HIP graph, the serving scheduler (one request submitted alone),
+    and one launch per pair.  The last is timed on the run's first 512 pairs
+    (a whole run that way takes minutes) and scaled to the run's pair count,
+    labelled as such."""
     out = {}
     for name, cfg in (("batched", {}), ("graph", {"graph_rounds": True})):
         gg.set_launch(**tuned_launch(tuned, **cfg))
@@ -123,46 +265,54 @@ def forms(gg, torch, seed, tuned):
         wall = time.perf_counter() - t0
         out[name] = {"pairs": res["samples"] + res["s_boot"], "rounds": res["rounds"], "wall_s": wall,
                      "pairs_per_s": (res["samples"] + res["s_boot"]) / wall, "xi": res["xi"]}
-    # the unbatched form: one single-workgroup launch per pair, on a fixed
-    # sample (a whole progressive run this way takes minutes)
-    r = 256
+    gg.set_launch(**tuned_launch(tuned))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tk = gg.submit(OPT, eps=0.01, delta=0.1, seed=seed, c=C)
+    res = tk.poll(timeout_ms=-1)
+    wall = time.perf_counter() - t0
+    out["served"] = {"pairs": res["samples"] + res["s_boot"], "rounds": res["rounds"], "wall_s": wall,
+                     "pairs_per_s": (res["samples"] + res["s_boot"]) / wall, "xi": res["xi"],
+                     "latency_ms": res["latency_ms"]}
+    r = 512
     gg.set_launch(**tuned_launch(tuned, per_pair_launch=True))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gg.run(OPT, fixed_r=r, seed=seed, c=C)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    out["plain"] = {"pairs": r, "wall_s": wall, "pairs_per_s": r / wall,
-                    "note": "fixed sample of %d pairs, one launch per pair" % r}
     gg.set_launch(**tuned_launch(tuned))
+    n_run = out["batched"]["pairs"]
+    out["plain"] = {"pairs_timed": r, "wall_s_timed": wall, "pairs_per_s": r / wall,
+                    "pairs": n_run, "wall_s": wall / r * n_run,
+                    "note": "one launch per pair, timed on the run's first %d pairs and scaled to its %d pairs"
+                            % (r, n_run)}
     base = out["plain"]["pairs_per_s"]
-    for k in ("batched", "graph"):
+    for k in ("batched", "graph", "served"):
         out[k]["speedup_vs_plain"] = out[k]["pairs_per_s"] / base
     return out
 
 
-def trk_step(gg, torch, seed, steps=3):
-    """The bench step (sfm, r = 20,000, c = 25, node + edge sums) with the
-    TRK estimator."""
-    gg.run(OPT, fixed_r=R_PER_STEP, seed=seed + 999, c=C, edges=True, trk=True)
+def trk_step(gg, torch, seed, r, steps=3):
+    """The mid step (sfm, c = 25, node + edge sums) with the TRK estimator."""
+    gg.run(OPT, fixed_r=r, seed=seed + 999, c=C, edges=True, trk=True)
     torch.cuda.synchronize()
     tot = {"sweep_ms": 0.0, "launches": 0, "window_edges": 0, "arcs": 0, "touched_nodes": 0, "touched_edges": 0}
     t0 = time.perf_counter()
     for k in range(steps):
-        gg.run(OPT, fixed_r=R_PER_STEP, seed=seed + k, c=C, edges=True, trk=True)
+        gg.run(OPT, fixed_r=r, seed=seed + k, c=C, edges=True, trk=True)
         t = gg.last_timing()
         for key in tot:
             tot[key] += t[key]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    out = {"steps": steps, "pairs_per_s": R_PER_STEP * steps / wall, "ms_per_step": wall * 1e3 / steps,
-           "sweep_ms_per_launch": tot["sweep_ms"] / max(1, tot["launches"]), "hbm_frac": hbm_frac(tot, C),
-           "kernel": "mantra::k_sweep<2>"}
-    return out
+    return {"steps": steps, "pairs_per_s": r * steps / wall, "ms_per_step": wall * 1e3 / steps,
+            "sweep_ms_per_launch": tot["sweep_ms"] / max(1, tot["launches"]), "hbm_frac": hbm_frac(tot, C),
+            "kernel": "mantra::k_sweep<2>"}
 
 
 def rtb_step(gg, torch, seed, r=0, steps=2):
-    """The bench step's settings (sfm, c = 25, node + edge sums) with the RTB
+    """The mid step's settings (sfm, c = 25, node + edge sums) with the RTB
     estimator: r sampled sources per step (default: two per workgroup of the
     grid, since each source's sweep runs to the end of the span and a launch
     lasts as long as its longest sweeps), each swept to the end of the span
@@ -186,14 +336,6 @@ def rtb_step(gg, torch, seed, r=0, steps=2):
             "hbm_frac": hbm_frac(tot, C), "kernel": "mantra::k_sweep<3>"}
 
 
-def hbm_frac(t, c):
-    """Algorithmic bytes of a call's sweep launches over their summed HIP-event
-    duration, as a fraction of the HBM peak."""
-    if t["sweep_ms"] <= 0:
-        return None
-    return algorithmic_bytes(t, c) / (t["sweep_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
-
-
 def distances(gg, torch, seed, r=256, og=None):
     """Algorithm 2 from r sources (sh and pfm, tau = 0.9), blocking calls;
     beside it the oracle's per-source distances on a bounded sample."""
@@ -212,7 +354,7 @@ def distances(gg, torch, seed, r=256, og=None):
                     "rho": res["rho"]}
         if og is not None:
             from oracle import distances as odist
-            threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+            threads = host_threads()
             S = odist.draw_sources(seed, og.n, 32)
             t0 = time.perf_counter()
             odist.source_hops(og, opt, S, nthreads=threads)
@@ -223,32 +365,35 @@ def distances(gg, torch, seed, r=256, og=None):
     return out
 
 
-def serve(gg, G, torch, n_req=12, rate=50.0, seed=4002, workload_name=WORKLOAD):
+def serve(gg, G, torch, n_req=24, rate=50.0, seed=4002, workload_name=MID):
     """Poisson arrivals at `rate` req/s; each request a random window of
-    5-100% of the span, a uniform optimality and eps in {0.01, 0.005}."""
+    5-100% of the span, a uniform optimality and eps in {0.01, 0.005}.
+    Latencies are reported over every finished request (a request that fails
+    finishes too) and over the completed ones, with their counts."""
     import numpy as np
     from synthgen import request_stream
     reqs = request_stream(n_req, rate, int(G.t.min()), int(G.t.max()), seed)
     opts = ("sh", "fm", "sfm", "pfm")
     lat = [None] * n_req
+    ok_ = [False] * n_req
     pairs = [0] * n_req
-    errs = []  # saturated fm counts (E_OVERFLOW): reported, never rounded
     t_start = time.perf_counter()
 
     def waiter(i, tk):
         ok = True
         try:
             res = tk.poll(timeout_ms=-1)
-        except Exception as e:  # noqa: BLE001 - saturated fm counts are reported, not fatal
+        except Exception:  # noqa: BLE001 - a failed request finishes too (saturated fm counts)
             res = tk.result
-            errs.append(str(e))
             ok = False
         if res is not None:
             pairs[i] = res["samples"] + res["s_boot"]
-            if ok:
-                lat[i] = res["latency_ms"]
-            print("request %d (%s) %s after %.0f ms, %d pairs" % (i, opts[reqs[i]["opt"]], "done" if ok else "failed",
-                                                               res["latency_ms"], pairs[i]), file=sys.stderr, flush=True)
+            lat[i] = res["latency_ms"]
+            ok_[i] = ok
+            log("request %d (%s, eps %g, window %.0f%%) %s after %.0f ms, %d pairs" % (
+                i, opts[reqs[i]["opt"]], reqs[i]["eps"],
+                100.0 * (reqs[i]["t1"] - reqs[i]["t0"]) / max(1, int(G.t.max()) - int(G.t.min())),
+                "done" if ok else "failed", res["latency_ms"], pairs[i]))
 
     threads = []
     for i, rq in enumerate(reqs):
@@ -264,13 +409,54 @@ def serve(gg, G, torch, n_req=12, rate=50.0, seed=4002, workload_name=WORKLOAD):
         th.join()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    L = np.array([x for x in lat if x is not None])
-    return {"requests": n_req, "offered_req_per_s": rate, "completed": int(L.size), "wall_s": wall,
-            "completed_req_per_s": L.size / wall, "pairs_per_s": sum(pairs) / wall,
-            "p50_ms": float(np.percentile(L, 50)) if L.size else None,
-            "p99_ms": float(np.percentile(L, 99)) if L.size else None,
-            "latency_of": "completed requests", "overflowed": len(errs),
+    La = np.array([x for x in lat if x is not None])
+    Lc = np.array([x for x, o in zip(lat, ok_) if x is not None and o])
+
+    def pct(L, q):
+        return float(np.percentile(L, q)) if L.size else None
+
+    return {"requests": n_req, "offered_req_per_s": rate, "finished": int(La.size), "completed": int(Lc.size),
+            "failed": int(La.size - Lc.size), "wall_s": wall, "completed_req_per_s": Lc.size / wall,
+            "pairs_per_s": sum(pairs) / wall,
+            "p50_ms": pct(La, 50), "p99_ms": pct(La, 99), "latency_of": "every finished request (failed ones too)",
+            "p50_ms_completed": pct(Lc, 50), "p99_ms_completed": pct(Lc, 99),
+            "failure": "fm walk counts past 2^64 (MANTRA_E_OVERFLOW at the end of the phase that saturated)",
             "workload": workload_name + ", windows/optimalities/eps of the serving recipe"}
+
+
+def mid_sections(args, pk, torch):
+    from synthgen import workload
+    G = workload(MID)
+    gg = pk.Graph.of(G)
+    log("%s resident" % MID)
+    tuned = gg.autotune(OPT, sample_pairs=MID_R, seed=args.seed + 7)
+    tot, wall, bal = timed_steps(gg, torch, OPT, MID_R, max(3, args.steps // 4), 1, args.seed)
+    steps = max(3, args.steps // 4)
+    out = {"workload": MID, "n": G.n, "edges": G.m, "optimality": OPT, "pairs_per_step": MID_R, "c": C,
+           "steps": steps, "pairs_per_s": MID_R * steps / wall, "ms_per_step": wall * 1e3 / steps,
+           "temporal_edges_per_s": tot["window_edges"] / wall, "mean_window_edges": tot["window_edges"] / (MID_R * steps),
+           "mean_arcs": tot["arcs"] / (MID_R * steps), "grid_balance": bal, "launch": tuned,
+           "roofline": roofline(tot, MID, tuned["n_slabs"])}
+    log("mid: %s" % json.dumps(out))
+    if not args.no_forms:
+        out["forms"] = forms(gg, torch, args.seed, tuned)
+        log("forms: %s" % json.dumps(out["forms"]))
+    if not args.no_serve:
+        out["serve"] = serve(gg, G, torch, n_req=args.serve_requests, rate=args.serve_rate)
+    og = None
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Graph.of(G)
+    if not args.no_trk:
+        out["trk"] = trk_step(gg, torch, args.seed, MID_R)
+    if not args.no_rtb:
+        out["rtb"] = rtb_step(gg, torch, args.seed)
+    if not args.no_distances:
+        out["distances"] = distances(gg, torch, args.seed, og=og)
+    return out
+
+
+# ------------------------------------------------------------------ other modes
 
 
 def batching(pk, torch, seed):
@@ -286,12 +472,12 @@ def batching(pk, torch, seed):
 
     def note(key, d):
         out[key] = d
-        print("%s: %s" % (key, json.dumps(d)), file=sys.stderr, flush=True)
+        log("%s: %s" % (key, json.dumps(d)))
 
     t0 = time.perf_counter()
     gs = workload("packed-256")
     pg = pk.Graph.packed(gs)
-    print("packed-256 resident after %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    log("packed-256 resident after %.1f s" % (time.perf_counter() - t0))
     r = 2000
     pg.run("sh", fixed_r=64, seed=seed + 99, c=C)
     for k in range(2):
@@ -311,11 +497,11 @@ def batching(pk, torch, seed):
     t0 = time.perf_counter()
     G = workload("big-chunglu-n1m")
     gg = pk.Graph.of(G)
-    print("big-chunglu-n1m resident after %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    log("big-chunglu-n1m resident after %.1f s" % (time.perf_counter() - t0))
     gg.set_launch(graph_rounds=True)
     t0 = time.perf_counter()
     tuned = gg.autotune("pfm", seed=seed + 7)
-    print("autotuned in %.1f s: %s" % (time.perf_counter() - t0, json.dumps(tuned)), file=sys.stderr, flush=True)
+    log("autotuned in %.1f s: %s" % (time.perf_counter() - t0, json.dumps(tuned)))
 
     def timed(opt, **kw):
         torch.cuda.synchronize()
@@ -355,22 +541,24 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mid", action="store_true", help="skip the mid-size workload's sections")
+    ap.add_argument("--no-optimalities", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-distances", action="store_true")
     ap.add_argument("--no-trk", action="store_true")
+    ap.add_argument("--no-rtb", action="store_true")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving measurement, on --serve-workload (prints {\"serve\": ...})")
-    ap.add_argument("--serve-workload", default=WORKLOAD)
-    ap.add_argument("--serve-requests", type=int, default=12)
+    ap.add_argument("--serve-workload", default=MID)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--batching", action="store_true",
                     help="only the batching workloads (n = 10^6 Algorithm 1, packed-256; prints {\"batching\": ...})")
-    ap.add_argument("--no-rtb", action="store_true")
     ap.add_argument("--slabs", type=int, default=0,
-                    help="fixed number of persistent workgroups instead of the autotuner's pick "
-                         "(profiling runs: every sweep launch of the run is then alike)")
-    ap.add_argument("--seed", type=int, default=2002)
+                    help="fixed number of persistent workgroups for the headline step (profiling runs)")
+    ap.add_argument("--seed", type=int, default=2005)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported (sampled pairs are "
@@ -391,43 +579,22 @@ def main():
         t0 = time.perf_counter()
         G = workload(args.serve_workload)
         gg = pk.Graph.of(G)
-        print("graph %s resident after %.1f s" % (args.serve_workload, time.perf_counter() - t0), file=sys.stderr,
-              flush=True)
-        print(json.dumps({"serve": serve(gg, G, torch, n_req=args.serve_requests,
-                                         workload_name=args.serve_workload)}), flush=True)
+        log("graph %s resident after %.1f s" % (args.serve_workload, time.perf_counter() - t0))
+        print(json.dumps({"serve": serve(gg, G, torch, n_req=args.serve_requests, rate=args.serve_rate,
+                                         seed=args.seed + 2000, workload_name=args.serve_workload)}), flush=True)
         return
-    G = workload(WORKLOAD)
-    gg = pk.Graph.of(G)
-    # launch configuration picked by the autotuner on a calibration sample
-    if args.slabs > 0:
-        gg.set_launch(n_slabs=args.slabs)
-        tuned = gg.get_launch()
-    else:
-        tuned = gg.autotune(OPT, sample_pairs=R_PER_STEP, seed=args.seed + 7)
-    for i in range(args.warmup):
-        gg.run(OPT, fixed_r=R_PER_STEP, seed=args.seed + 1000 + i, c=C, edges=True)
-    torch.cuda.synchronize()
-    tot = {"sweep_ms": 0.0, "launches": 0, "window_edges": 0, "arcs": 0, "touched_nodes": 0,
-           "touched_edges": 0}
-    bal = 0.0
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        _, _, res = gg.run(OPT, fixed_r=R_PER_STEP, seed=args.seed + k, c=C, edges=True)
-        t = gg.last_timing()
-        for key in tot:
-            tot[key] += t[key]
-        bal += t["balance"] * t["sweep_ms"]
-        print("step %d: %.1f ms sweep" % (k, t["sweep_ms"]), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    G = workload(WORKLOAD)
+    log("%s generated after %.1f s" % (WORKLOAD, time.perf_counter() - t0))
+    gg = pk.Graph.of(G)
+    log("%s resident after %.1f s" % (WORKLOAD, time.perf_counter() - t0))
+    launch = dict(HEADLINE_LAUNCH)
+    if args.slabs > 0:
+        launch["n_slabs"] = args.slabs
+    gg.set_launch(**launch)
+    tuned = gg.get_launch()
+    tot, wall, bal = timed_steps(gg, torch, OPT, R_PER_STEP, args.steps, args.warmup, args.seed)
     pairs = R_PER_STEP * args.steps
-    ms_step = wall * 1e3 / args.steps
-    kern_ms = tot["sweep_ms"] / max(1, tot["launches"])
-    abytes = algorithmic_bytes(tot, C) / max(1, tot["launches"])
-    achieved = abytes / (kern_ms / 1e3) / 1e9
-    traffic = None
-    if TRAFFIC["sweep_sha256"] == sha256(SWEEP_SRC) and TRAFFIC["fetch_bytes_per_launch"]:
-        traffic = TRAFFIC["fetch_bytes_per_launch"] + TRAFFIC["write_bytes_per_launch"]
     out = {
         "metric": METRIC,
         "value": pairs / wall,
@@ -435,41 +602,40 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": wall * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64 counts, f64 sums",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": G.n, "edges": G.m, "ticks": 100000, "optimality": OPT,
-                   "pairs_per_step": R_PER_STEP, "c": C, "edge_betweenness": True},
+        "config": {"workload": WORKLOAD, "n": G.n, "edges": G.m, "ticks": 1_000_000, "optimality": OPT,
+                   "window": "whole span", "pairs_per_step": R_PER_STEP, "c": C, "edge_betweenness": True},
         "temporal_edges_per_s": tot["window_edges"] / wall,
         "mean_window_edges": tot["window_edges"] / pairs,
         "mean_arcs": tot["arcs"] / pairs,
-        "sweep_ms_per_launch": kern_ms,
-        "grid_balance": bal / max(tot["sweep_ms"], 1e-9),
+        "sweep_ms_per_launch": tot["sweep_ms"] / max(1, tot["launches"]),
+        "launches_per_step": tot["launches"] / args.steps,
+        "grid_balance": bal,
         "launch": tuned,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "mantra::k_sweep<0>", "algorithmic_bytes_per_launch": abytes,
-                     "traffic_slabs": TRAFFIC["slabs"] if traffic is not None else None},
+        "roofline": roofline(tot, WORKLOAD, tuned["n_slabs"]),
     }
-    if not args.no_forms:
-        out["forms"] = forms(gg, torch, args.seed, tuned)
-    if not args.no_serve:
-        out["serve"] = serve(gg, G, torch, n_req=args.serve_requests)
-    og = None
+    log("headline: %s" % json.dumps(out))
+    og = one = None
     if not args.no_cpu_baseline:
         import oracle
         og = oracle.Graph.of(G)
-    if not args.no_trk:
-        out["trk"] = trk_step(gg, torch, args.seed)
-    if not args.no_rtb:
-        out["rtb"] = rtb_step(gg, torch, args.seed)
-    if not args.no_distances:
-        out["distances"] = distances(gg, torch, args.seed, og=og)
+        one = OracleOneThread(og, G.n, args.seed, OPT)
+        one.start()
+    if not args.no_optimalities:
+        out["optimalities"] = optimalities(gg, torch, args.seed, (("pfm", 4096), ("sh", 1024), ("fm", 1024)))
+        out["plain"] = plain_fixed(gg, torch, OPT, 16, args.seed, tuned)
+        out["plain"]["speedup_of_step"] = out["value"] / out["plain"]["pairs_per_s"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(G, args.seed)
+        out["cpu_baseline"] = cpu_baseline(og, G.n, args.seed, OPT, one=one)
+        log("cpu_baseline: %s" % json.dumps(out["cpu_baseline"]))
+    del gg, G, og
+    if not args.no_mid:
+        out["mid"] = mid_sections(args, pk, torch)
     print(json.dumps(out), flush=True)
 
 

@@ -296,7 +296,7 @@ int mantra_poll(uint64_t ticket, mantra_result *out, int32_t timeout_ms);
 /* Serving configuration: device bytes the scheduler may use for per-request
  * sums (0: the default, three quarters of the memory left free once the slab
  * pool -- the per-pair node state and arc buffers that every launch shares,
- * 45% of the device -- is reserved), maximum concurrent requests. */
+ * 75% of the device -- is reserved), maximum concurrent requests. */
 int mantra_serve_config(mantra_graph *g, uint64_t mem_budget_bytes, int32_t max_active);
 
 /* Launch configuration of the sweep (it changes how the work is scheduled,
@@ -306,7 +306,7 @@ typedef struct {
                              time (0: as many as fit the device) */
     int64_t arc_cap;      /* appearance-DAG arc records of each workgroup's own
                              buffer (0: 2^18, at most one per edge of the graph);
-                             a pair with more takes chunks of 2^16 arcs from a
+                             a pair with more takes chunks of 2^18 arcs from a
                              pool the launch shares (the rest of the slab
                              budget), and a pair that finds none free is re-run
                              after the launch with room for every edge */
@@ -361,13 +361,15 @@ int mantra_autotune(mantra_graph *g, mantra_opt opt, int64_t sample_pairs, uint6
  * totals over its pairs of swept window edges, recorded appearance-DAG arcs,
  * touched nodes (N(v) > 0) and touched temporal edges (N(e) > 0), the load
  * balance of the persistent grid (busy time of its workgroups over
- * workgroups x launch span, averaged over launch time), and the forward
+ * workgroups x launch span, averaged over launch time), the forward
  * sweep's batches of up to 64 window edges that loaded node state and that
- * were skipped (no reached tail).  Any pointer may be NULL. */
+ * were skipped (no reached tail), and the forward sweeps' share of the
+ * workgroups' time in pairs (the rest: reverse sweeps, walks and the
+ * accumulation).  Any pointer may be NULL. */
 int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launches,
                        int64_t *window_edges, int64_t *arcs, int64_t *touched_nodes,
                        int64_t *touched_edges, double *balance, int64_t *live_batches,
-                       int64_t *skipped_batches);
+                       int64_t *skipped_batches, double *forward_share);
 
 /* Test entry point: sets the pair serial and the long-tick stamp of every
  * workgroup of the graph's slab pool (allocating the pool first), as a pool

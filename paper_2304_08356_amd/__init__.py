@@ -114,13 +114,14 @@ class Graph:
     def last_timing(self):
         ms = ctypes.c_double(); nl = ctypes.c_int64(); w = ctypes.c_int64(); a = ctypes.c_int64()
         tn = ctypes.c_int64(); te = ctypes.c_int64(); bal = ctypes.c_double()
-        lv = ctypes.c_int64(); sk = ctypes.c_int64()
+        lv = ctypes.c_int64(); sk = ctypes.c_int64(); fs = ctypes.c_double()
         _lib.check(_lib._lib.mantra_last_timing(self._h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(w),
                                                 ctypes.byref(a), ctypes.byref(tn), ctypes.byref(te),
-                                                ctypes.byref(bal), ctypes.byref(lv), ctypes.byref(sk)))
+                                                ctypes.byref(bal), ctypes.byref(lv), ctypes.byref(sk),
+                                                ctypes.byref(fs)))
         return {"sweep_ms": ms.value, "launches": nl.value, "window_edges": w.value, "arcs": a.value,
                 "touched_nodes": tn.value, "touched_edges": te.value, "balance": bal.value,
-                "live_batches": lv.value, "skipped_batches": sk.value}
+                "live_batches": lv.value, "skipped_batches": sk.value, "forward_share": fs.value}
 
     def count_pairs(self, opt, s, z, t0=0, t1=T_MAX, graph=None, node_f=False, edge_f=False):
         """Records (and optionally dense per-pair f over nodes / input edges)

@@ -13,15 +13,17 @@ constexpr int kWave = 64;
 #endif
 constexpr int kE = MANTRA_KE;        // edges per lane per batch
 #ifndef MANTRA_SWEEP_WPS
-#define MANTRA_SWEEP_WPS 5               // sweep waves per SIMD the register budget is cut for
+#define MANTRA_SWEEP_WPS 4               // sweep waves per SIMD the register budget is cut for
 #endif
 constexpr int kC = kWave * kE;       // batch capacity (edges or arcs)
 constexpr int kFwN = 2 * kC;         // LDS forwarding / tail table slots
 constexpr int kFwBits = kFwN == 128 ? 7 : (kFwN == 256 ? 8 : (kFwN == 512 ? 9 : 10));
 static_assert((1 << kFwBits) == kFwN, "table size must be a power of two");
+constexpr int kStats = 20;           // launch statistics words (LaunchArgs::stats)
 constexpr int kOrderBuckets = 160;   // log-scale cost buckets of the launch order (4 per octave)
-constexpr int kArcChunkBits = 16;    // arcs per chunk of the shared arc pool: 2^16 (2 MiB)
+constexpr int kArcChunkBits = 18;    // arcs per chunk of the shared arc pool: 2^18 (8 MiB)
 constexpr int64_t kArcChunk = 1ll << kArcChunkBits;
+constexpr int kXtLds = 256;          // chunk-table entries a sweep workgroup keeps in LDS
 constexpr u32 kHInf = 0xFFFFu;       // "unreached" hop count
 constexpr u64 kUMax = ~0ull;
 
@@ -126,9 +128,10 @@ struct LaunchArgs {
     double *node_f;              // dense per-pair node output [npairs][n_total] or null
     double *edge_f;              // dense per-pair edge output [npairs][m] or null
     u32 *work;                   // work counter, zero at launch
-    u64 *stats;                  // [16] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck, touched nodes,
+    u64 *stats;                  // [kStats] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck, touched nodes,
                                  // touched edges, slab busy ticks, last end, ~first start, largest pair serial, largest tick stamp,
-                                 // batches that loaded state, batches skipped
+                                 // batches that loaded state, batches skipped, clock ticks in forward sweeps, clock ticks in
+                                 // reverse sweeps and finalize
     int32_t *retry;              // [1 + npairs] pairs whose arcs did not fit
     int32_t *wide;               // [1 + npairs] pairs whose counts saturated, for the multiword path
                                  // (null: they are reported as saturated)

@@ -240,7 +240,7 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
     HIPCHK(hipEventCreate(&g->ev0));
     HIPCHK(hipEventCreate(&g->ev1));
     HIPCHK(dalloc(&g->dwork, 1));
-    HIPCHK(dalloc(&g->dstats, 16));
+    HIPCHK(dalloc(&g->dstats, kStats));
     *out = g.release();
     return MANTRA_OK;
 }
@@ -304,13 +304,15 @@ static size_t slab_bytes(const mantra_graph *g, int64_t cap) {
 static size_t pool_bytes(const mantra_graph *g, const SlabPool &p) {
     return p.nslabs ? (size_t)p.nslabs * slab_bytes(g, p.cap) + (size_t)p.nchunks * kChunkBytes : 0;
 }
-// 45% of the device, less when other graphs or callers already hold memory
-// (the graph's own pool counts as available)
+// 75% of the device, less when other graphs or callers already hold memory
+// (the graph's own pool counts as available).  The rest holds the graph,
+// the per-request sums of served requests and the re-run pools.
+static constexpr double kPoolShare = 0.75;
 static size_t pool_budget(const mantra_graph *g) {
     size_t fr, tot;
     device_mem(g, &fr, &tot);
     const size_t own = pool_bytes(g, g->pool);
-    return (size_t)std::min(0.45 * (double)tot, 0.7 * (double)(fr + own));
+    return (size_t)std::min(kPoolShare * (double)tot, 0.85 * (double)(fr + own));
 }
 
 // default device bytes the serving scheduler may give to per-request sums:
@@ -321,7 +323,7 @@ size_t serve_sums_budget(const mantra_graph *g) {
     size_t fr, tot;
     device_mem(g, &fr, &tot);
     const size_t own = pool_bytes(g, g->pool);
-    const size_t share = (size_t)(0.45 * (double)tot);
+    const size_t share = (size_t)(kPoolShare * (double)tot);
     const size_t reserve = share > own ? share - own : 0;
     const size_t left = fr > reserve ? fr - reserve : 0;
     return std::max<size_t>((size_t)64 << 20, (size_t)(0.75 * (double)left));
@@ -653,8 +655,8 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
     o.ms += ms;
     o.first_ms = ms;
-    u64 st1[16];
-    HIPCHK(hipMemcpy(st1, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
+    u64 st1[kStats];
+    HIPCHK(hipMemcpy(st1, g->dstats, sizeof(u64) * kStats, hipMemcpyDeviceToHost));
     if ((rc = stamps_after(g, g->pool, st1))) return rc;
     if (nretry > 0) {
         // pairs whose arcs overflowed get slabs that hold every edge of the
@@ -686,15 +688,15 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
         o.ms += ms;
         o.launches += 1;
-        u64 st2[16];
-        HIPCHK(hipMemcpy(st2, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
+        u64 st2[kStats];
+        HIPCHK(hipMemcpy(st2, g->dstats, sizeof(u64) * kStats, hipMemcpyDeviceToHost));
         hipFree(dq);
         g->pool_big.release();  // rare and large: not kept between launches
         int32_t n2 = 0;
         HIPCHK(hipMemcpy(&n2, g->dretry, sizeof(int32_t), hipMemcpyDeviceToHost));
         if (n2 > 0) return fail(MANTRA_E_INTERNAL, "arc buffer of a full window overflowed");
         for (int i = 0; i < 16; ++i)
-            if ((i != 5 && i < 9) || i == 14 || i == 15) st1[i] += st2[i];
+            if ((i != 5 && i < 9) || (i >= 14 && i < 18)) st1[i] += st2[i];
     }
     int32_t nwide = 0;
     if (a.wide) HIPCHK(hipMemcpy(&nwide, g->dwide, sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -722,8 +724,8 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
         HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
         o.ms += ms;
         o.launches += 1;
-        u64 st3[16];
-        HIPCHK(hipMemcpy(st3, g->dstats, sizeof(u64) * 16, hipMemcpyDeviceToHost));
+        u64 st3[kStats];
+        HIPCHK(hipMemcpy(st3, g->dstats, sizeof(u64) * kStats, hipMemcpyDeviceToHost));
         if ((rc = wide_stamps(g, nwide, st3))) return rc;
         st1[2] += st3[2];
         st1[4] += st3[4];
@@ -740,7 +742,7 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
 // blocking calls report their work through mantra_last_timing
 void timing_reset(mantra_graph *g) {
     g->last_ms = 0; g->last_launches = 0; g->last_W = 0; g->last_arcs = 0; g->last_tn = 0; g->last_te = 0;
-    g->last_live = 0; g->last_dead = 0;
+    g->last_live = 0; g->last_dead = 0; g->last_fwd_ticks = 0; g->last_rev_ticks = 0;
     g->last_busy_ms = 0;
 }
 void timing_add(mantra_graph *g, const SweepOut &o) {
@@ -753,6 +755,8 @@ void timing_add(mantra_graph *g, const SweepOut &o) {
     g->last_te += (int64_t)o.st[8];
     g->last_live += (int64_t)o.st[14];
     g->last_dead += (int64_t)o.st[15];
+    g->last_fwd_ticks += (int64_t)o.st[16];
+    g->last_rev_ticks += (int64_t)o.st[17];
 }
 
 // per-block partials of max W, sum B, max R_j
@@ -1336,7 +1340,7 @@ int mantra_debug_stamps(mantra_graph *g, uint32_t serial, uint32_t tick_stamp) {
 
 int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launches, int64_t *window_edges,
                        int64_t *arcs, int64_t *touched_nodes, int64_t *touched_edges, double *balance,
-                       int64_t *live_batches, int64_t *skipped_batches) {
+                       int64_t *live_batches, int64_t *skipped_batches, double *forward_share) {
     if (!g) return fail(MANTRA_E_INVALID, "graph is NULL");
     g_err.clear();
     if (sweep_ms) *sweep_ms = g->last_ms;
@@ -1348,6 +1352,10 @@ int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launche
     if (balance) *balance = g->last_ms > 0 ? g->last_busy_ms / g->last_ms : 1.0;
     if (live_batches) *live_batches = g->last_live;
     if (skipped_batches) *skipped_batches = g->last_dead;
+    if (forward_share) {
+        const double all = (double)g->last_fwd_ticks + (double)g->last_rev_ticks;
+        *forward_share = all > 0 ? (double)g->last_fwd_ticks / all : 0.0;
+    }
     return MANTRA_OK;
 }
 

@@ -174,6 +174,7 @@ struct mantra_graph {
     // timing of the last blocking call
     double last_ms = 0;
     int64_t last_launches = 0, last_W = 0, last_arcs = 0, last_tn = 0, last_te = 0, last_live = 0, last_dead = 0;
+    int64_t last_fwd_ticks = 0, last_rev_ticks = 0;
     double last_busy_ms = 0;
     mantra::ServeState *serve = nullptr;
     mantra::DevGraph dev() const {
@@ -202,7 +203,7 @@ struct LaunchSpec {
 // what one call of run_sweep did: launch statistics (indices as in
 // LaunchArgs::stats), device time of its launches and their count
 struct SweepOut {
-    u64 st[16];
+    u64 st[kStats];
     double ms = 0;
     double first_ms = 0;   // the persistent launch alone (without re-runs)
     int launches = 0;

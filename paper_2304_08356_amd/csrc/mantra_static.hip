@@ -101,7 +101,7 @@ int mantra_count_pairs_static(mantra_graph *g, mantra_opt opt, int32_t t0, int32
     const size_t o_req = head.take<DevReq>(1);
     const size_t o_work = head.take<u32>(1);
     const size_t o_retry = head.take<int32_t>(1 + (size_t)r);
-    const size_t o_stats = head.take<u64>(16);
+    const size_t o_stats = head.take<u64>(kStats);
     const size_t o_ps = head.take<int32_t>((size_t)r);
     const size_t o_pz = head.take<int32_t>((size_t)r);
     const size_t o_pg = head.take<int32_t>((size_t)r);
@@ -211,7 +211,7 @@ int mantra_count_pairs_static(mantra_graph *g, mantra_opt opt, int32_t t0, int32
     HIPCHK(mantra_launch_sweep(&a, (int)ns, lb, g->st));
     HIPCHK(hipEventRecord(g->ev1, g->st));
     HIPCHK(hipMemcpyAsync(out, base + o_rec, sizeof(mantra_pair_record) * r, hipMemcpyDeviceToHost, g->st));
-    u64 st[16];
+    u64 st[kStats];
     HIPCHK(hipMemcpyAsync(st, base + o_stats, sizeof st, hipMemcpyDeviceToHost, g->st));
     HIPCHK(hipStreamSynchronize(g->st));
     float ms = 0;

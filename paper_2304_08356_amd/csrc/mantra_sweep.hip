@@ -200,39 +200,80 @@ struct Pair {
     u64 trk_i;             // TRK: the pair's index in it
 };
 
+// A slab's buffers.  Only the slab's index is held; every address is
+// computed from the launch arguments where it is used (scalar loads from the
+// kernel-argument segment, see launch_args), so that the pointers are not
+// kept live in scalar registers across the sweep loops, which spilled them.
 struct Slab {
-    u64 *F, *R, *N, *AG, *XS;
-    u64 *T;                // RTB: [nmax][2] first arrival {time | hops << 32, count} of each reached node
-    u64 *arcm;             // [cap] head | time << 32
-    u64 *arcx;             // [cap][3] edge | tail << 32, tail count, tl | hl << 16
-    u64 *xarcs;            // the launch's shared arc chunks, each laid out as arcm / arcx of kArcChunk arcs
-    u32 *xt;               // [xmax] the chunks this slab holds, in arc order: arc cap + j is in chunk xt[j / kArcChunk]
-    int64_t cap;           // arcs of the slab's own buffer
-    u32 *AGF, *hdr;
-    int32_t *touched;
-    int32_t id;
+    int64_t id;
+    u32 *xtl;  // LDS: the first kXtLds entries of the slab's chunk table
+    // forward {tag | hops << 32, count} per node; the reverse's state shares the words
+    __device__ __forceinline__ u64 *F() const { KArgs &a = launch_args(); return a.sl.F + id * a.sl.nmax * 2; }
+    __device__ __forceinline__ u64 *R() const { return F(); }
+    __device__ __forceinline__ u64 *N() const { KArgs &a = launch_args(); return a.sl.N + id * a.sl.nmax; }
+    __device__ __forceinline__ int32_t *touched() const {
+        KArgs &a = launch_args();
+        return a.sl.touched + id * a.sl.nmax;
+    }
+    __device__ __forceinline__ u64 *AG() const { KArgs &a = launch_args(); return a.sl.AG + id * a.sl.gmax * 2; }
+    __device__ __forceinline__ u32 *AGF() const { KArgs &a = launch_args(); return a.sl.AGF + id * a.sl.gmax; }
+    __device__ __forceinline__ u64 *XS() const { KArgs &a = launch_args(); return a.sl.XS + id * a.sl.gmax * 2; }
+    // RTB: [nmax][2] first arrival {time | hops << 32, count} of each reached node
+    __device__ __forceinline__ u64 *T() const { KArgs &a = launch_args(); return a.sl.T + id * a.sl.nmax * 2; }
+    // the chunks this slab holds, in arc order: arc cap + j is in chunk
+    // xt(j / kArcChunk); entries below kXtLds in LDS (no global load on the
+    // arc paths), the rest (pairs of more than 2^26 arcs) in global memory
+    __device__ __forceinline__ u32 *xtg() const { KArgs &a = launch_args(); return a.sl.xtab + id * a.sl.xmax; }
+    __device__ __forceinline__ u32 xt(int64_t j) const { return j < kXtLds ? xtl[j] : xtg()[j]; }
+    __device__ __forceinline__ void xt_set(int64_t j, u32 c) const {
+        if (j < kXtLds) xtl[j] = c;
+        else xtg()[j] = c;
+    }
 };
 
-// Arc i of the pair: in the slab's own buffer below cap, else in the shared
-// chunks it took (arc records are written and read only through these).
-__device__ __forceinline__ u64 *arc_m(const Slab &S, int64_t i) {
-    if (i < S.cap) return S.arcm + i;
-    const int64_t j = i - S.cap;
-    return S.xarcs + (int64_t)S.xt[j >> kArcChunkBits] * (4 * kArcChunk) + (j & (kArcChunk - 1));
-}
-__device__ __forceinline__ u64 *arc_x(const Slab &S, int64_t i) {
-    if (i < S.cap) return S.arcx + 3 * i;
-    const int64_t j = i - S.cap;
-    return S.xarcs + (int64_t)S.xt[j >> kArcChunkBits] * (4 * kArcChunk) + kArcChunk + 3 * (j & (kArcChunk - 1));
-}
-
 // forward state of the highest-degree nodes (internal ids below K) in LDS:
-// hops and count, valid where the reached bitmap is set (no pair tag)
+// hops and count, valid where the reached set has the node (no pair tag)
 struct Hub {
     u32 *h;
     u64 *s;
     int32_t K;
 };
+
+// Arc i of the pair: in the slab's own buffer of cap arcs ({head | time << 32}
+// words, then {edge | tail << 32, tail count, tl | hl << 16} triples), else
+// in the shared chunks it took (the same layout per chunk).  Arc records are
+// written and read only through these.
+__device__ __forceinline__ u64 *arc_m(const Slab &S, int64_t i) {
+    KArgs &a = launch_args();
+    const int64_t cap = a.sl.cap;
+    if (i < cap) return a.sl.arcs + S.id * cap * 4 + i;
+    const int64_t j = i - cap;
+    return a.sl.xarcs + (int64_t)S.xt(j >> kArcChunkBits) * (4 * kArcChunk) + (j & (kArcChunk - 1));
+}
+// both words of arc i at once (one address computation)
+struct ArcP { u64 *m, *x; };
+__device__ __forceinline__ ArcP arc_at(const Slab &S, int64_t i) {
+    KArgs &a = launch_args();
+    const int64_t cap = a.sl.cap;
+    ArcP r;
+    if (i < cap) {
+        r.m = a.sl.arcs + S.id * cap * 4 + i;
+        r.x = a.sl.arcs + S.id * cap * 4 + cap + 3 * i;
+    } else {
+        const int64_t j = i - cap;
+        u64 *c = a.sl.xarcs + (int64_t)S.xt(j >> kArcChunkBits) * (4 * kArcChunk);
+        r.m = c + (j & (kArcChunk - 1));
+        r.x = c + kArcChunk + 3 * (j & (kArcChunk - 1));
+    }
+    return r;
+}
+__device__ __forceinline__ u64 *arc_x(const Slab &S, int64_t i) {
+    KArgs &a = launch_args();
+    const int64_t cap = a.sl.cap;
+    if (i < cap) return a.sl.arcs + S.id * cap * 4 + cap + 3 * i;
+    const int64_t j = i - cap;
+    return a.sl.xarcs + (int64_t)S.xt(j >> kArcChunkBits) * (4 * kArcChunk) + kArcChunk + 3 * (j & (kArcChunk - 1));
+}
 
 struct FwdOut {
     bool reached;
@@ -242,7 +283,7 @@ struct FwdOut {
     int64_t arcs;
     int64_t swept;
     u32 flags;
-    int64_t reached_n;    // single source: nodes listed in S.touched
+    int64_t reached_n;    // single source: nodes listed in the slab's touched list
     u32 live, dead;       // batches that loaded state, batches skipped (no reached tail)
     int64_t room;         // arcs the slab's buffer and its chunks hold
     int32_t nch;          // shared chunks the pair holds
@@ -293,9 +334,9 @@ __device__ int32_t chunk_take(KArgs &a, int32_t slab) {
 __device__ bool arc_room(KArgs &a, const Slab &S, FwdOut &o, int64_t need) {
     while (need > o.room) {
         if (o.nch >= a.sl.xmax) return false;
-        const int32_t c = chunk_take(a, S.id);
+        const int32_t c = chunk_take(a, (int32_t)S.id);
         if (c < 0) return false;
-        if (lane_id() == 0) S.xt[o.nch] = (u32)c;
+        if (lane_id() == 0) S.xt_set(o.nch, (u32)c);
         o.nch += 1;
         o.room += kArcChunk;
         __syncthreads();  // every lane's arc addresses read the new table entry
@@ -308,7 +349,7 @@ __device__ void chunks_free(KArgs &a, const Slab &S, int32_t nch) {
     if (nch <= 0) return;
     __threadfence();
     for (int i = lane_id(); i < nch; i += kWave) {
-        const u32 c = S.xt[i];
+        const u32 c = S.xt(i);
         __hip_atomic_fetch_or(&a.sl.xfree[c >> 5], 1u << (c & 31), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -384,6 +425,13 @@ template <int FM, bool GBM>
 __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
                               int64_t g0, int64_t g1, int32_t t, u32 &agstamp, FwdOut &o,
                               u32 &zh, u64 &zS, bool &zhit) {
+    u64 *const Fp = S.F();
+    u64 *const XSp = S.XS();
+    u64 *const AGp = S.AG();
+    u32 *const AGFp = S.AGF();
+    u64 *const Np = S.N();
+    u64 *const Tp = S.T();
+    int32_t *const Tch = S.touched();
     constexpr bool SINGLE = FM != FWD_PAIR;
     const int l = lane_id();
     const int32_t *U = a.g.U, *V = a.g.V;
@@ -413,19 +461,19 @@ __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, c
             if (maybe && u < H.K) {
                 rt = true; hu = H.h[u]; Su = H.s[u];
             } else if (maybe) {
-                u64 th = S.F[2 * (int64_t)u], sv = S.F[2 * (int64_t)u + 1];
+                u64 th = Fp[2 * (int64_t)u], sv = Fp[2 * (int64_t)u + 1];
                 if ((u32)th == P.tag) { rt = true; hu = (u32)(th >> 32) & 0xFFFFu; Su = sv; }
             }
         }
         bool hl = false;
         if (act) {
             // {hops | reached << 32 | run position << 33, count} of the tail
-            S.XS[2 * (idx - g0)] = rt ? ((u64)hu | (1ull << 32) | ((u64)k << 33)) : 0ull;
-            S.XS[2 * (idx - g0) + 1] = Su;
-            if (rs) S.AG[2 * k + 1] = 0ull;
+            XSp[2 * (idx - g0)] = rt ? ((u64)hu | (1ull << 32) | ((u64)k << 33)) : 0ull;
+            XSp[2 * (idx - g0) + 1] = Su;
+            if (rs) AGp[2 * k + 1] = 0ull;
             if (rt) {
                 if (hu + 1 >= kHInf) hl = true;
-                else atomicMin((unsigned long long *)&S.AG[2 * k], (unsigned long long)(hi_key | (hu + 1)));
+                else atomicMin((unsigned long long *)&AGp[2 * k], (unsigned long long)(hi_key | (hu + 1)));
             }
         }
         if (ballot(hl)) o.flags |= REC_HOPS_LIMIT;
@@ -435,15 +483,15 @@ __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, c
     for (int64_t sb = g0; sb < g1; sb += kWave) {
         int64_t idx = sb + l;
         if (idx >= g1) continue;
-        u64 x0 = S.XS[2 * (idx - g0)];
+        u64 x0 = XSp[2 * (idx - g0)];
         if (!(x0 >> 32)) continue;
         u32 hu = (u32)x0;
         const int64_t k = (int64_t)(x0 >> 33);
-        u64 Su = S.XS[2 * (idx - g0) + 1];
-        u64 key = ld_agent(&S.AG[2 * k]);
+        u64 Su = XSp[2 * (idx - g0) + 1];
+        u64 key = ld_agent(&AGp[2 * k]);
         u32 d = (u32)key;
         bool tight = P.level ? (hu + 1 == d) : true;
-        if (tight) glb_sat_add(&S.AG[2 * k + 1], Su);
+        if (tight) glb_sat_add(&AGp[2 * k + 1], Su);
     }
     __syncthreads();
     // pass C: one commit per head run
@@ -460,11 +508,11 @@ __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, c
         u64 nS = 0;
         if (rs) {
             const int64_t k = idx - g0;
-            u64 key = ld_agent(&S.AG[2 * k]);
+            u64 key = ld_agent(&AGp[2 * k]);
             u32 ok = 0;
             if ((key & 0xFFFFFFFF00000000ull) == hi_key) {
                 u32 d = (u32)key;
-                u64 c = ld_agent(&S.AG[2 * k + 1]);
+                u64 c = ld_agent(&AGp[2 * k + 1]);
                 bool rv = false;
                 u32 hv = 0;
                 u64 Sv = 0;
@@ -472,33 +520,33 @@ __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, c
                 if (maybe && v < H.K) {
                     rv = true; hv = H.h[v]; Sv = H.s[v];
                 } else if (maybe) {
-                    u64 th = S.F[2 * (int64_t)v], sv = S.F[2 * (int64_t)v + 1];
+                    u64 th = Fp[2 * (int64_t)v], sv = Fp[2 * (int64_t)v + 1];
                     if ((u32)th == P.tag) { rv = true; hv = (u32)(th >> 32) & 0xFFFFu; Sv = sv; }
                 }
                 if (head_commit(P.opt, rv, hv, Sv, d, c, v, P.z, zh, &nh, &nS)) {
                     ok = agstamp;
                     if (SINGLE && !rv) {  // first arrival: list of reached nodes, hops (fm / sfm / pfm)
-                        if (FM == FWD_DIST && P.opt != OPT_SH) S.N[v] = (u64)nh + 1ull;
+                        if (FM == FWD_DIST && P.opt != OPT_SH) Np[v] = (u64)nh + 1ull;
                         if (FM == FWD_RTB) {
-                            S.T[2 * (int64_t)v] = (u64)(u32)t | ((u64)nh << 32);
-                            S.T[2 * (int64_t)v + 1] = nS;
+                            Tp[2 * (int64_t)v] = (u64)(u32)t | ((u64)nh << 32);
+                            Tp[2 * (int64_t)v + 1] = nS;
                         }
                         fa = true;
                     }
                     if (v < H.K) { H.h[v] = nh; H.s[v] = nS; }
                     else {
-                        S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh << 32);
-                        S.F[2 * (int64_t)v + 1] = nS;
+                        Fp[2 * (int64_t)v] = (u64)P.tag | ((u64)nh << 32);
+                        Fp[2 * (int64_t)v + 1] = nS;
                     }
                     rch_set<GBM>(bm, v);
                     zl = (v == P.z);
                 }
             }
-            S.AGF[k] = ok;
+            AGFp[k] = ok;
         }
         if (SINGLE) {
             const u64 fm_ = ballot(fa);
-            if (fa) S.touched[o.reached_n + mbcnt(fm_)] = v;
+            if (fa) Tch[o.reached_n + mbcnt(fm_)] = v;
             o.reached_n += __popcll(fm_);
         }
         u64 zm = ballot(zl);
@@ -525,17 +573,17 @@ __device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, c
         int32_t v = 0, u = 0;
         u64 su = 0;
         if (idx < g1) {
-            u64 x0 = S.XS[2 * (idx - g0)];
+            u64 x0 = XSp[2 * (idx - g0)];
             if (x0 >> 32) {
                 v = V[idx];
                 const int64_t k = (int64_t)(x0 >> 33);
-                if (S.AGF[k] == agstamp) {
+                if (AGFp[k] == agstamp) {
                     hu = (u32)x0;
-                    d = (u32)ld_agent(&S.AG[2 * k]);
+                    d = (u32)ld_agent(&AGp[2 * k]);
                     if ((!P.level || hu + 1 == d) && FM != FWD_DIST) {
                         rec = true;
                         u = U[idx];
-                        su = S.XS[2 * (idx - g0) + 1];
+                        su = XSp[2 * (idx - g0) + 1];
                     }
                 }
             }
@@ -575,6 +623,10 @@ __device__ __forceinline__ void load_batch(KArgs &a, const Pair &P, int64_t b, i
 template <int FM, bool GBM>
 __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H, FwdLds &L,
                         u32 &agstamp, FwdOut &o) {
+    u64 *const Fp = S.F();
+    u64 *const Np = S.N();
+    u64 *const Tp = S.T();
+    int32_t *const Tch = S.touched();
     constexpr bool SINGLE = FM != FWD_PAIR;
     static_assert(kE == 1, "the forward sweep is written for one edge per lane");
     const int l = lane_id();
@@ -667,10 +719,10 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
             // the others)
             const int64_t iu = (rt && u >= H.K) ? (int64_t)u : (int64_t)P.s;
             const int64_t iv = (hr && v >= H.K) ? (int64_t)v : (int64_t)P.s;
-            thu = S.F[2 * iu];
-            su = S.F[2 * iu + 1];
-            thv = S.F[2 * iv];
-            sv = S.F[2 * iv + 1];
+            thu = Fp[2 * iu];
+            su = Fp[2 * iu + 1];
+            thv = Fp[2 * iv];
+            sv = Fp[2 * iv + 1];
             if (H.K > 0) {
                 const int ju = u < H.K ? u : 0, jv = v < H.K ? v : 0;
                 lhu = H.h[ju]; lsu = H.s[ju];
@@ -800,8 +852,8 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
             if (ok) {
                 if (v < H.K) { H.h[v] = nh2; H.s[v] = nS; }
                 else {
-                    S.F[2 * (int64_t)v] = (u64)P.tag | ((u64)nh2 << 32);
-                    S.F[2 * (int64_t)v + 1] = nS;
+                    Fp[2 * (int64_t)v] = (u64)P.tag | ((u64)nh2 << 32);
+                    Fp[2 * (int64_t)v + 1] = nS;
                 }
                 rch_set<GBM>(bm, v);
             }
@@ -811,12 +863,12 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
                 const bool fa = ok && cur_h == kHInf;
                 const u64 fm_ = ballot(fa);
                 if (fa) {
-                    if (FM == FWD_DIST && opt != OPT_SH) S.N[v] = (u64)nh2 + 1ull;
+                    if (FM == FWD_DIST && opt != OPT_SH) Np[v] = (u64)nh2 + 1ull;
                     if (FM == FWD_RTB) {
-                        S.T[2 * (int64_t)v] = (u64)(u32)t | ((u64)nh2 << 32);
-                        S.T[2 * (int64_t)v + 1] = nS;
+                        Tp[2 * (int64_t)v] = (u64)(u32)t | ((u64)nh2 << 32);
+                        Tp[2 * (int64_t)v + 1] = nS;
                     }
-                    S.touched[o.reached_n + mbcnt(fm_)] = v;
+                    Tch[o.reached_n + mbcnt(fm_)] = v;
                 }
                 o.reached_n += __popcll(fm_);
             }
@@ -892,12 +944,14 @@ __device__ __forceinline__ void alive_set(u32 *bm, int32_t v) {
 
 __device__ __forceinline__ void rev_contrib(KArgs &a, const Pair &P, const Slab &S,
                                             RevCtx &X, bool act, u64 B, u64 tc, int32_t v, u32 k) {
+    u64 *const Np = S.N();
+    int32_t *const Tch = S.touched();
     // N(arc) = tail count * B(head); N(v) += N(arc); f(e) = N(arc) / sigma
     bool first = false, wrap = false;
     if (act && B) {
         u64 na = tc * B;
         if (v != P.s && v != P.z) {
-            u64 old = atomicAdd((unsigned long long *)&S.N[v], (unsigned long long)na);
+            u64 old = atomicAdd((unsigned long long *)&Np[v], (unsigned long long)na);
             first = (old == 0);
             wrap = (old + na < old);
         }
@@ -912,7 +966,7 @@ __device__ __forceinline__ void rev_contrib(KArgs &a, const Pair &P, const Slab 
     u64 m = ballot(first);
     if (m) {
         int64_t pos = X.touched_n + mbcnt(m);
-        if (first) S.touched[pos] = v;
+        if (first) Tch[pos] = v;
         X.touched_n += __popcll(m);
     }
 }
@@ -930,45 +984,49 @@ __device__ __forceinline__ u64 head_B(const Pair &P, const RevCtx &X, int32_t v,
 template <bool GBM>
 __device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, RevCtx &X,
                               int64_t a0, int64_t a1) {
+    u64 *const Rp = S.R();
+    u64 *const XSp = S.XS();
     const int l = lane_id();
     for (int64_t sb = a0; sb < a1; sb += kWave) {
         int64_t i = sb + l;
         bool inr = i < a1;
-        u64 mm = inr ? (*arc_m(S, i)) : 0;
+        const ArcP ap = arc_at(S, inr ? i : a0);
+        u64 mm = inr ? *ap.m : 0;
         int32_t v = (int32_t)(u32)mm;
         bool act = inr && (v == P.z || alive_test<GBM>(bm, v));
         u64 B = 0, tc = 0;
         u32 k = 0;
         if (act) {
-            u64 x0 = arc_x(S, i)[0];
-            tc = arc_x(S, i)[1];
-            u32 hl = (u32)(arc_x(S, i)[2] >> 16) & 0xFFFFu;
+            u64 x0 = ap.x[0];
+            tc = ap.x[1];
+            u32 hl = (u32)(ap.x[2] >> 16) & 0xFFFFu;
             k = (u32)x0;
             bool valid = false;
             u32 lvl = 0;
             u64 acc = 0;
             if (v != P.z) {
-                u64 th = ld_agent(&S.R[2 * (int64_t)v]);
-                if ((u32)th == P.rtag) { valid = true; lvl = (u32)(th >> 32) & 0xFFFFu; acc = ld_agent(&S.R[2 * (int64_t)v + 1]); }
+                u64 th = ld_agent(&Rp[2 * (int64_t)v]);
+                if ((u32)th == P.rtag) { valid = true; lvl = (u32)(th >> 32) & 0xFFFFu; acc = ld_agent(&Rp[2 * (int64_t)v + 1]); }
             }
             B = head_B(P, X, v, hl, valid, lvl, acc);
         }
-        if (inr) S.XS[i - a0] = B;
+        if (inr) XSp[i - a0] = B;
         rev_contrib(a, P, S, X, act, B, tc, v, k);
     }
     __syncthreads();
     for (int64_t sb = a0; sb < a1; sb += kWave) {
         int64_t i = sb + l;
         if (i >= a1) continue;
-        u64 B = S.XS[i - a0];
+        u64 B = XSp[i - a0];
         if (!B) continue;
-        int32_t u = (int32_t)(arc_x(S, i)[0] >> 32);
-        u32 tl = (u32)arc_x(S, i)[2] & 0xFFFFu;
+        const u64 *xp = arc_x(S, i);
+        int32_t u = (int32_t)(xp[0] >> 32);
+        u32 tl = (u32)xp[2] & 0xFFFFu;
         u32 want = P.level ? tl : 0u;
-        u64 th = ld_agent(&S.R[2 * (int64_t)u]);
+        u64 th = ld_agent(&Rp[2 * (int64_t)u]);
         if ((u32)th != P.rtag || ((u32)(th >> 32) & 0xFFFFu) != want) {
-            S.R[2 * (int64_t)u] = (u64)P.rtag | ((u64)want << 32);
-            S.R[2 * (int64_t)u + 1] = 0;
+            Rp[2 * (int64_t)u] = (u64)P.rtag | ((u64)want << 32);
+            Rp[2 * (int64_t)u + 1] = 0;
         }
     }
     __syncthreads();
@@ -976,10 +1034,10 @@ __device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, R
     for (int64_t sb = a0; sb < a1; sb += kWave) {
         int64_t i = sb + l;
         if (i >= a1) continue;
-        u64 B = S.XS[i - a0];
+        u64 B = XSp[i - a0];
         if (!B) continue;
         int32_t u = (int32_t)(arc_x(S, i)[0] >> 32);
-        atomicAdd((unsigned long long *)&S.R[2 * (int64_t)u + 1], (unsigned long long)B);
+        atomicAdd((unsigned long long *)&Rp[2 * (int64_t)u + 1], (unsigned long long)B);
         alive_set<GBM>(bm, u);
     }
     __syncthreads();
@@ -988,6 +1046,7 @@ __device__ void rev_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, R
 template <bool GBM>
 __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t bmw, RevLds &L,
                         u32 &stamp, int64_t narcs, RevCtx &X) {
+    u64 *const Rp = S.R();
     const int l = lane_id();
     // the alive set starts empty (the node bytes' bit 1 already is)
     if (!GBM)
@@ -1057,9 +1116,10 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
             int32_t tp = __shfl_up(tt[j], 1);
             if (l == 0) tp = j > 0 ? rl32(tt[j - 1], kWave - 1) : INT32_MIN;
             gm[j] = ballot(in[j] && (off == cut || tt[j] != tp));
-            u64 x0 = in[j] ? arc_x(S, blo + off)[0] : 0;
-            tc[j] = in[j] ? arc_x(S, blo + off)[1] : 0;
-            u64 x2 = in[j] ? arc_x(S, blo + off)[2] : 0;
+            const u64 *xp = arc_x(S, in[j] ? blo + off : blo);
+            u64 x0 = in[j] ? xp[0] : 0;
+            tc[j] = in[j] ? xp[1] : 0;
+            u64 x2 = in[j] ? xp[2] : 0;
             kk[j] = (u32)x0;
             uu[j] = (int32_t)(x0 >> 32);
             tl[j] = (u32)x2 & 0xFFFFu;
@@ -1067,12 +1127,12 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
             hval[j] = false; hlvl[j] = 0; hacc[j] = 0;
             tval[j] = false; tlvl[j] = 0; tacc[j] = 0;
             if (al[j] && vv[j] != P.z) {
-                u64 th = ld_agent(&S.R[2 * (int64_t)vv[j]]);
-                if ((u32)th == P.rtag) { hval[j] = true; hlvl[j] = (u32)(th >> 32) & 0xFFFFu; hacc[j] = ld_agent(&S.R[2 * (int64_t)vv[j] + 1]); }
+                u64 th = ld_agent(&Rp[2 * (int64_t)vv[j]]);
+                if ((u32)th == P.rtag) { hval[j] = true; hlvl[j] = (u32)(th >> 32) & 0xFFFFu; hacc[j] = ld_agent(&Rp[2 * (int64_t)vv[j] + 1]); }
             }
             if (in[j] && alive_test<GBM>(bm, uu[j])) {
-                u64 th = ld_agent(&S.R[2 * (int64_t)uu[j]]);
-                if ((u32)th == P.rtag) { tval[j] = true; tlvl[j] = (u32)(th >> 32) & 0xFFFFu; tacc[j] = ld_agent(&S.R[2 * (int64_t)uu[j] + 1]); }
+                u64 th = ld_agent(&Rp[2 * (int64_t)uu[j]]);
+                if ((u32)th == P.rtag) { tval[j] = true; tlvl[j] = (u32)(th >> 32) & 0xFFFFu; tacc[j] = ld_agent(&Rp[2 * (int64_t)uu[j] + 1]); }
             }
         }
         stamp += 1;
@@ -1158,8 +1218,8 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
                 if ((u32)(key >> 32) != stamp) continue;
                 u32 node = (u32)key;
                 u32 x = L.tb_lvl[sl];
-                S.R[2 * (int64_t)node] = (u64)P.rtag | ((u64)(x & 0xFFFFu) << 32);
-                S.R[2 * (int64_t)node + 1] = L.tb_acc[sl];
+                Rp[2 * (int64_t)node] = (u64)P.rtag | ((u64)(x & 0xFFFFu) << 32);
+                Rp[2 * (int64_t)node + 1] = L.tb_acc[sl];
             }
         }
         __syncthreads();
@@ -1216,7 +1276,7 @@ __device__ void resolve_pair(A &a, int64_t slot, Pair &P) {
 
 // Distances from a single source after its forward sweep: every node the
 // sweep reached (other than the source; the forward lists them in
-// S.touched at their first arrival) adds one to the bin of its distance.
+// the slab's touched list at their first arrival) adds one to the bin of its distance.
 // sh: fewest hops over all arrivals (the final hop state); fm, sfm and pfm:
 // the hops committed at the first arrival, which the forward keeps in N as
 // hops + 1 (N must be zero again for the next slot, so it is cleared here,
@@ -1225,6 +1285,9 @@ constexpr int kDistBins = 2 * kFwN;  // u32 bins in LDS, over the reverse table'
 static_assert(kDistBins * 4 <= (int)sizeof(u64) * kFwN, "distance bins exceed the table");
 
 __device__ void distance_hist(const Pair &P, const Slab &S, const Hub &H, u32 *lh, int64_t nreached, bool count) {
+    u64 *const Np = S.N();
+    int32_t *const Tch = S.touched();
+    u64 *const Fp = S.F();
     const int l = lane_id();
     const DevReq *R = P.req;
     const u32 last = (u32)R->hist_len - 1u;
@@ -1233,13 +1296,13 @@ __device__ void distance_hist(const Pair &P, const Slab &S, const Hub &H, u32 *l
     __syncthreads();
     u32 dmax = 0;
     for (int64_t i = l; i < nreached; i += kWave) {
-        const int32_t v = S.touched[i];
+        const int32_t v = Tch[i];
         u32 d;
         if (first) {
-            d = (u32)(S.N[v] - 1ull);
-            S.N[v] = 0ull;
+            d = (u32)(Np[v] - 1ull);
+            Np[v] = 0ull;
         } else {
-            d = v < H.K ? H.h[v] : (u32)(S.F[2 * (int64_t)v] >> 32) & 0xFFFFu;
+            d = v < H.K ? H.h[v] : (u32)(Fp[2 * (int64_t)v] >> 32) & 0xFFFFu;
         }
         if (count) {
             const u32 b = d < last ? d : last;
@@ -1283,6 +1346,8 @@ __device__ void distance_hist(const Pair &P, const Slab &S, const Hub &H, u32 *l
 // taken); returns false where it does not.
 __device__ bool trk_walk(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, u32 zh, int32_t t_arr,
                          u64 sigma, RevCtx &X) {
+    u64 *const Np = S.N();
+    int32_t *const Tch = S.touched();
     const int l = lane_id();
     const DevReq *R = P.req;
     int32_t node = P.z;
@@ -1298,14 +1363,15 @@ __device__ bool trk_walk(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, 
         for (int64_t b = 0; b < hi; b += kWave) {
             const int64_t i = b + l;
             if (i >= hi) continue;
-            const u64 mm = (*arc_m(S, i));
+            const ArcP ap = arc_at(S, i);
+            const u64 mm = *ap.m;
             if ((int32_t)(u32)mm != node) continue;
             const int32_t ti = (int32_t)(mm >> 32);
-            const u32 hl = (u32)(arc_x(S, i)[2] >> 16) & 0xFFFFu;
+            const u32 hl = (u32)(ap.x[2] >> 16) & 0xFFFFu;
             bool c;
             if (term) c = P.opt == OPT_SH ? hl == lvl : ti == t_arr;
             else c = ti < tmax && (!P.level || hl == lvl);
-            if (c) part = sat_add(part, arc_x(S, i)[1]);
+            if (c) part = sat_add(part, ap.x[1]);
         }
         for (int o = kWave / 2; o > 0; o >>= 1) part = sat_add(part, shfl64(part, l ^ o));
         u64 W = uni64(part);
@@ -1321,14 +1387,15 @@ __device__ bool trk_walk(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, 
             const int64_t i = b + l;
             u64 wt = 0;
             if (i < hi) {
-                const u64 mm = (*arc_m(S, i));
+                const ArcP ap = arc_at(S, i);
+                const u64 mm = *ap.m;
                 if ((int32_t)(u32)mm == node) {
                     const int32_t ti = (int32_t)(mm >> 32);
-                    const u32 hl = (u32)(arc_x(S, i)[2] >> 16) & 0xFFFFu;
+                    const u32 hl = (u32)(ap.x[2] >> 16) & 0xFFFFu;
                     bool c;
                     if (term) c = P.opt == OPT_SH ? hl == lvl : ti == t_arr;
                     else c = ti < tmax && (!P.level || hl == lvl);
-                    if (c) wt = arc_x(S, i)[1];
+                    if (c) wt = ap.x[1];
                 }
             }
             // inclusive scan of the weights over the wave (no wrap: the
@@ -1344,19 +1411,20 @@ __device__ bool trk_walk(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, 
             else carry += rl64(x, kWave - 1);
         }
         if (pick < 0) return false;
-        const u64 x0 = arc_x(S, pick)[0];
+        const ArcP pp = arc_at(S, pick);
+        const u64 x0 = pp.x[0];
         const int32_t k = (int32_t)(u32)x0;           // stream index of the edge
         const int32_t tail = (int32_t)(x0 >> 32);
-        const u32 tl = (u32)arc_x(S, pick)[2] & 0xFFFFu;
-        const int32_t tp = (int32_t)((*arc_m(S, pick)) >> 32);
-        const u64 tcp = arc_x(S, pick)[1];
+        const u32 tl = (u32)pp.x[2] & 0xFFFFu;
+        const int32_t tp = (int32_t)(*pp.m >> 32);
+        const u64 tcp = pp.x[1];
         // visit counts in the slab's N (zero between pairs) and the list of
         // the distinct internal nodes, as the reverse sweep leaves them
         if (tail != P.s && tail != P.z) {
-            const u64 old = S.N[tail];  // every lane reads the same word
+            const u64 old = Np[tail];  // every lane reads the same word
             if (l == 0) {
-                S.N[tail] = old + 1ull;
-                if (old == 0ull) S.touched[X.touched_n] = tail;
+                Np[tail] = old + 1ull;
+                if (old == 0ull) Tch[X.touched_n] = tail;
             }
             if (old == 0ull) X.touched_n += 1;
         }
@@ -1391,6 +1459,11 @@ __device__ bool trk_walk(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, 
 // value must come out as the number of reached targets.  Returns false if
 // a count on the way saturated.
 __device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, RevCtx &X) {
+    u64 *const Rp = S.R();
+    u64 *const XSp = S.XS();
+    u64 *const Tp = S.T();
+    u64 *const Np = S.N();
+    int32_t *const Tch = S.touched();
     const int l = lane_id();
     const DevReq *R = P.req;
     const double n1 = (double)(P.ng - 1);
@@ -1413,31 +1486,32 @@ __device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, R
             bool first = false, nz = false;
             int32_t v = 0;
             if (i < ac) {
-                const u64 mm = (*arc_m(S, i));
+                const ArcP ap = arc_at(S, i);
+                const u64 mm = *ap.m;
                 v = (int32_t)(u32)mm;
                 const int32_t t = (int32_t)(mm >> 32);
-                const u64 x0 = arc_x(S, i)[0];
+                const u64 x0 = ap.x[0];
                 const u32 k = (u32)x0;
-                const u64 tc = arc_x(S, i)[1];
-                const u32 hl = (u32)(arc_x(S, i)[2] >> 16) & 0xFFFFu;
+                const u64 tc = ap.x[1];
+                const u32 hl = (u32)(ap.x[2] >> 16) & 0xFFFFu;
                 if (tc == kUMax) bad = true;
                 double thru = 0.0;
-                const u64 tw = ld_agent(&S.R[2 * (int64_t)v]);
+                const u64 tw = ld_agent(&Rp[2 * (int64_t)v]);
                 if ((u32)tw == P.rtag && (!P.level || ((u32)(tw >> 32) & 0xFFFFu) == hl))
-                    thru = __longlong_as_double((long long)ld_agent(&S.R[2 * (int64_t)v + 1]));
+                    thru = __longlong_as_double((long long)ld_agent(&Rp[2 * (int64_t)v + 1]));
                 double C = thru;
                 if (v != P.s) {
-                    const u64 fa = S.T[2 * (int64_t)v];
+                    const u64 fa = Tp[2 * (int64_t)v];
                     const bool term = P.opt == OPT_SH ? ((u32)(fa >> 32) & 0xFFFFu) == hl : (int32_t)(u32)fa == t;
                     if (term) {
-                        const u64 sg = S.T[2 * (int64_t)v + 1];
+                        const u64 sg = Tp[2 * (int64_t)v + 1];
                         if (sg == kUMax) bad = true;
                         C += 1.0 / (double)sg;
                     }
                 }
-                S.XS[i - a0] = (u64)__double_as_longlong(C);
+                XSp[i - a0] = (u64)__double_as_longlong(C);
                 if (v != P.s && thru != 0.0) {
-                    const double old = atomicAdd(reinterpret_cast<double *>(&S.N[v]), (double)tc * thru);
+                    const double old = atomicAdd(reinterpret_cast<double *>(&Np[v]), (double)tc * thru);
                     first = old == 0.0;
                 }
                 nz = C != 0.0;
@@ -1449,7 +1523,7 @@ __device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, R
             }
             X.edges_n += __popcll(ballot(nz));
             const u64 m = ballot(first);
-            if (first) S.touched[X.touched_n + mbcnt(m)] = v;
+            if (first) Tch[X.touched_n + mbcnt(m)] = v;
             X.touched_n += __popcll(m);
         }
         __syncthreads();
@@ -1457,23 +1531,24 @@ __device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, R
         for (int64_t sb = a0; sb < ac; sb += kWave) {
             const int64_t i = sb + l;
             if (i >= ac) continue;
-            if (S.XS[i - a0] == 0ull) continue;
-            const int32_t u = (int32_t)(arc_x(S, i)[0] >> 32);
-            const u32 want = P.level ? ((u32)arc_x(S, i)[2] & 0xFFFFu) : 0u;
-            const u64 tw = ld_agent(&S.R[2 * (int64_t)u]);
+            if (XSp[i - a0] == 0ull) continue;
+            const u64 *xp = arc_x(S, i);
+            const int32_t u = (int32_t)(xp[0] >> 32);
+            const u32 want = P.level ? ((u32)xp[2] & 0xFFFFu) : 0u;
+            const u64 tw = ld_agent(&Rp[2 * (int64_t)u]);
             if ((u32)tw != P.rtag || ((u32)(tw >> 32) & 0xFFFFu) != want) {
-                S.R[2 * (int64_t)u] = (u64)P.rtag | ((u64)want << 32);
-                S.R[2 * (int64_t)u + 1] = 0ull;
+                Rp[2 * (int64_t)u] = (u64)P.rtag | ((u64)want << 32);
+                Rp[2 * (int64_t)u + 1] = 0ull;
             }
         }
         __syncthreads();
         for (int64_t sb = a0; sb < ac; sb += kWave) {
             const int64_t i = sb + l;
             if (i >= ac) continue;
-            const u64 cb = S.XS[i - a0];
+            const u64 cb = XSp[i - a0];
             if (cb == 0ull) continue;
             const int32_t u = (int32_t)(arc_x(S, i)[0] >> 32);
-            atomicAdd(reinterpret_cast<double *>(&S.R[2 * (int64_t)u + 1]), __longlong_as_double((long long)cb));
+            atomicAdd(reinterpret_cast<double *>(&Rp[2 * (int64_t)u + 1]), __longlong_as_double((long long)cb));
         }
         __syncthreads();
         ac = a0;
@@ -1485,23 +1560,10 @@ __device__ bool rev_rtb(KArgs &a, const Pair &P, const Slab &S, int64_t narcs, R
 // every slot is a single source; MODE_TRK: pairs, f = visits of one sampled
 // optimal walk.  Each mode is a kernel of its own, so that the pair sweep
 // keeps its register allocation.
-__device__ __forceinline__ Slab slab_of(KArgs &a, int64_t slab) {
+__device__ __forceinline__ Slab slab_of(int64_t slab, u32 *xtl) {
     Slab S;
-    S.F = a.sl.F + slab * a.sl.nmax * 2;
-    S.R = S.F;  // the reverse state shares the forward's words (their tags differ)
-    S.N = a.sl.N + slab * a.sl.nmax;
-    S.AG = a.sl.AG + slab * a.sl.gmax * 2;
-    S.AGF = a.sl.AGF + slab * a.sl.gmax;
-    S.touched = a.sl.touched + slab * a.sl.nmax;
-    S.arcm = a.sl.arcs + slab * a.sl.cap * 4;
-    S.arcx = S.arcm + a.sl.cap;
-    S.cap = a.sl.cap;
-    S.xarcs = a.sl.xarcs;
-    S.xt = a.sl.xtab + slab * a.sl.xmax;
-    S.id = (int32_t)slab;
-    S.XS = a.sl.XS + slab * a.sl.gmax * 2;
-    S.T = a.sl.T ? a.sl.T + slab * a.sl.nmax * 2 : nullptr;
-    S.hdr = a.sl.hdr + slab * 4;
+    S.id = slab;
+    S.xtl = xtl;
     return S;
 }
 
@@ -1529,17 +1591,19 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
     }
     u32 stamp = 1;  // reverse table stamps (0 = empty)
     const u64 t_begin = wall_clock64();
+    u64 fwd_ticks = 0, rev_ticks = 0;  // time in forward sweeps, in the rest of the pairs
     __syncthreads();
     for (;;) {
         KArgs &a = launch_args();
-        const Slab S = slab_of(a, slab);
+        const Slab S = slab_of(slab, reinterpret_cast<u32 *>(lds_raw + sizeof(TabLds)));
         // LDS bitmap words, or the 16-byte words of the node bytes
         const int64_t bmw = GBM ? (a.sl.nmax + 15) / 16 : (a.sl.nmax + 31) / 32;
+        constexpr size_t kHead = sizeof(TabLds) + sizeof(u32) * kXtLds;  // tables, chunk table
         u32 *bm = GBM ? reinterpret_cast<u32 *>(a.sl.BM + slab * bmw * 16)
-                      : reinterpret_cast<u32 *>(lds_raw + sizeof(TabLds));
+                      : reinterpret_cast<u32 *>(lds_raw + kHead);
         Hub H;
         H.K = a.hub_nodes;
-        H.s = reinterpret_cast<u64 *>(lds_raw + sizeof(TabLds) + (GBM ? 0 : ((bmw * 4 + 7) & ~7ll)));
+        H.s = reinterpret_cast<u64 *>(lds_raw + kHead + (GBM ? 0 : ((bmw * 4 + 7) & ~7ll)));
         H.h = reinterpret_cast<u32 *>(H.s + H.K);
         u32 qq = 0;
         if (l == 0) qq = atomicAdd(a.work, 1u);
@@ -1576,7 +1640,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
         FwdOut fo;
         fo.reached = false; fo.zh = kHInf; fo.zS = 0; fo.t_arr = -1; fo.arcs = 0; fo.swept = 0; fo.flags = 0;
         fo.reached_n = 0;
-        fo.room = S.cap;
+        fo.room = a.sl.cap;
         fo.nch = 0;
         fo.live = fo.dead = 0;
         if (ok) {
@@ -1593,13 +1657,15 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
             if (l == 0) {
                 if (P.s < H.K) { H.h[P.s] = 0u; H.s[P.s] = 1ull; }
                 else {
-                    S.F[2 * (int64_t)P.s] = (u64)P.tag;  // h = 0
-                    S.F[2 * (int64_t)P.s + 1] = 1ull;
+                    S.F()[2 * (int64_t)P.s] = (u64)P.tag;  // h = 0
+                    S.F()[2 * (int64_t)P.s + 1] = 1ull;
                 }
                 rch_set<GBM>(bm, P.s);
             }
             __syncthreads();
+            const u64 c0 = wall_clock64();
             forward<SINGLE ? (RTB ? FWD_RTB : FWD_DIST) : FWD_PAIR, GBM>(a, P, S, bm, H, tab.f, agstamp, fo);
+            fwd_ticks += wall_clock64() - c0;
             __syncthreads();
             if (MODE == MODE_DISTANCES)
                 distance_hist(P, S, H, reinterpret_cast<u32 *>(tab.r.tb_key), fo.reached_n,
@@ -1607,12 +1673,12 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
             if (RTB) {
                 // sh: the terminal level and sigma are the final state
                 for (int64_t i = l; i < fo.reached_n; i += kWave) {
-                    const int32_t v = S.touched[i];
-                    const u32 h = v < H.K ? H.h[v] : (u32)(S.F[2 * (int64_t)v] >> 32) & 0xFFFFu;
-                    const u64 sg = v < H.K ? H.s[v] : S.F[2 * (int64_t)v + 1];
+                    const int32_t v = S.touched()[i];
+                    const u32 h = v < H.K ? H.h[v] : (u32)(S.F()[2 * (int64_t)v] >> 32) & 0xFFFFu;
+                    const u64 sg = v < H.K ? H.s[v] : S.F()[2 * (int64_t)v + 1];
                     if (P.opt == OPT_SH) {
-                        S.T[2 * (int64_t)v] = (u64)h << 32;
-                        S.T[2 * (int64_t)v + 1] = sg;
+                        S.T()[2 * (int64_t)v] = (u64)h << 32;
+                        S.T()[2 * (int64_t)v + 1] = sg;
                     }
                 }
             }
@@ -1621,6 +1687,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
             stamp = 1;
             __syncthreads();
         }
+        const u64 c1 = wall_clock64();
         u32 flags = fo.flags;
         bool reach = ok && fo.reached && !(flags & (REC_HOPS_LIMIT | REC_ARCS_LIMIT));
         u64 sigma = reach ? fo.zS : 0;
@@ -1642,10 +1709,10 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
                         a.edge_f[P.qout * a.g.m + (int64_t)(u32)arc_x(S, i)[0]] = 0.0;
             } else {
                 // every reached target contributes exactly one to the origin
-                const u64 tw = ld_agent(&S.R[2 * (int64_t)P.s]);
+                const u64 tw = ld_agent(&S.R()[2 * (int64_t)P.s]);
                 double bo = 0.0;
                 if ((u32)tw == P.rtag && (!P.level || ((u32)(tw >> 32) & 0xFFFFu) == 0u))
-                    bo = __longlong_as_double((long long)ld_agent(&S.R[2 * (int64_t)P.s + 1]));
+                    bo = __longlong_as_double((long long)ld_agent(&S.R()[2 * (int64_t)P.s + 1]));
                 const double want = (double)fo.reached_n;
                 if (!(fabs(bo - want) <= 1e-9 * want)) flags |= REC_SELFCHECK;
             }
@@ -1657,9 +1724,9 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
             reverse<GBM>(a, P, S, bm, bmw, tab.r, stamp, fo.arcs, X);
             __syncthreads();
             // flow conservation at the origin: B(origin) must equal sigma
-            u64 th = ld_agent(&S.R[2 * (int64_t)P.s]);
+            u64 th = ld_agent(&S.R()[2 * (int64_t)P.s]);
             u64 bo = 0;
-            if ((u32)th == P.rtag && (!P.level || ((u32)(th >> 32) & 0xFFFFu) == 0u)) bo = ld_agent(&S.R[2 * (int64_t)P.s + 1]);
+            if ((u32)th == P.rtag && (!P.level || ((u32)(th >> 32) & 0xFFFFu) == 0u)) bo = ld_agent(&S.R()[2 * (int64_t)P.s + 1]);
             if (bo != sigma) flags |= REC_SELFCHECK;
         }
         if (X.ovf) {
@@ -1675,8 +1742,8 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
         bool accum = do_rev && !(flags & REC_OVERFLOW);
         const DevReq *R = P.req;
         for (int64_t i = l; i < X.touched_n; i += kWave) {
-            int32_t v = S.touched[i];
-            u64 nv = atomicExch((unsigned long long *)&S.N[v], 0ull);
+            int32_t v = S.touched()[i];
+            u64 nv = atomicExch((unsigned long long *)&S.N()[v], 0ull);
             if (!accum) continue;
             double f = TRK ? (double)nv
                            : RTB ? __longlong_as_double((long long)nv) / (double)(P.ng - 1) : (double)nv / (double)sigma;
@@ -1693,6 +1760,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
         }
         // the pair's arcs are read no more: its shared chunks go back
         chunks_free(a, S, fo.nch);
+        rev_ticks += wall_clock64() - c1;
         if (l == 0) {
             if (a.rec) {
                 int32_t *rr = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(a.rec) + P.qout * 24);
@@ -1751,6 +1819,8 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
         // the slab's pair serial and tick stamp, for the host's wrap guard
         atomicMax((unsigned long long *)&a.stats[12], (unsigned long long)serial);
         atomicMax((unsigned long long *)&a.stats[13], (unsigned long long)agstamp);
+        atomicAdd((unsigned long long *)&a.stats[16], (unsigned long long)fwd_ticks);
+        atomicAdd((unsigned long long *)&a.stats[17], (unsigned long long)rev_ticks);
     }
 }
 
@@ -2326,10 +2396,12 @@ hipError_t mantra_launch_order(const mantra::LaunchArgs *a, mantra::u32 *bucket,
 hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u32 *wide, mantra::u64 *stats,
                                hipStream_t st) {
     hipLaunchKernelGGL(mantra::k_zero_u32, dim3(1), dim3(64), 0, st, work, retry, wide);
-    hipLaunchKernelGGL(mantra::k_fill_u64, dim3(1), dim3(64), 0, st, stats, 0ull, (int64_t)16);
+    hipLaunchKernelGGL(mantra::k_fill_u64, dim3(1), dim3(64), 0, st, stats, 0ull, (int64_t)mantra::kStats);
     return hipGetLastError();
 }
-size_t mantra_tab_lds_bytes(void) { return sizeof(mantra::TabLds); }
+// LDS of a sweep workgroup ahead of its bitmap and hub state: the tables of
+// the forward and reverse sweeps, and the chunk table's first entries
+size_t mantra_tab_lds_bytes(void) { return sizeof(mantra::TabLds) + sizeof(mantra::u32) * mantra::kXtLds; }
 // resident sweep workgroups per CU for a given dynamic LDS size (gbm: the
 // instance with the reached set in global node bytes)
 int mantra_sweep_occupancy(size_t lds_bytes, int gbm) {
