@@ -371,12 +371,12 @@ int mantra_last_timing(const mantra_graph *g, double *sweep_ms, int64_t *launche
                        int64_t *touched_edges, double *balance, int64_t *live_batches,
                        int64_t *skipped_batches, double *forward_share);
 
-/* Test entry point: sets the pair serial and the long-tick stamp of every
- * workgroup of the graph's slab pool (allocating the pool first), as a pool
- * in use for billions of pairs would hold them.  Slab state words are tagged
- * with these 32-bit counters; the library clears the pool's tagged state
- * before either could wrap, so results never depend on them. */
-int mantra_debug_stamps(mantra_graph *g, uint32_t serial, uint32_t tick_stamp);
+/* Test entry point: sets the pair serial of every workgroup of the graph's
+ * slab pool (allocating the pool first), as a pool in use for billions of
+ * pairs would hold it.  Slab state words are tagged with this 32-bit
+ * counter; the library clears the pool's tagged state before it could wrap,
+ * so results never depend on it. */
+int mantra_debug_stamps(mantra_graph *g, uint32_t serial);
 
 const char *mantra_last_error(void);
 

@@ -91,7 +91,7 @@ SIGNATURES = {
     "mantra_get_launch": (I32, [P, P]),
     "mantra_autotune": (I32, [P, I32, I64, U64, P]),
     "mantra_last_timing": (I32, [P, P, P, P, P, P, P, P, P, P, P]),
-    "mantra_debug_stamps": (I32, [P, U32, U32]),
+    "mantra_debug_stamps": (I32, [P, U32]),
     "mantra_last_error": (ctypes.c_char_p, []),
 }
 

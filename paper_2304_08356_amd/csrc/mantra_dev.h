@@ -97,18 +97,17 @@ struct DevReq {
 struct DevSlabs {
     u64 *F;           // [ns][nmax][2]  forward {tag | h<<32, S}, then reverse {rtag | lvl<<32, acc}
     u64 *N;           // [ns][nmax]     zero between pairs
-    u64 *AG;          // [ns][gmax][2]  big-tick aggregation per head run {~stamp<<32 | dmin, sum}
-    u32 *AGF;         // [ns][gmax]     big-tick commit stamp per head run
+    u64 *AG;          // [ns][gmax][2]  long ticks: each head run's decision, at the run's first edge
     int32_t *touched; // [ns][nmax]
     u64 *arcs;        // [ns][cap][4]   per slab: cap x {head | t<<32}, then cap x {k | u<<32, tail count, tl | hl<<16}
     u64 *xarcs;       // [nchunks][4 kArcChunk] the shared arc chunks (same layout), taken by pairs beyond cap
     u32 *xfree;       // [xwords] bit c set: chunk c is free
     u32 *xtab;        // [ns][xmax] chunk ids a slab's pair holds, in arc order
     int64_t xwords, xmax;
-    u64 *XS;          // [ns][gmax][2]  big-tick scratch
+    u64 *XS;          // [ns][gmax][2]  long ticks: each edge's tail state
     u64 *T;           // [ns][nmax][2]  RTB sources: first arrival of each reached node (allocated for them)
     unsigned char *BM;// [ns][nmax rounded up to 16] reached / alive node bytes (graphs whose bitmap is not in LDS)
-    u32 *hdr;         // [ns][4]        pair serial, tick stamp
+    u32 *hdr;         // [ns][4]        pair serial
     int64_t nmax, cap, gmax;
 };
 
@@ -129,7 +128,7 @@ struct LaunchArgs {
     double *edge_f;              // dense per-pair edge output [npairs][m] or null
     u32 *work;                   // work counter, zero at launch
     u64 *stats;                  // [kStats] window edges, arcs, overflow, reachable, hops-limit, retries, selfcheck, touched nodes,
-                                 // touched edges, slab busy ticks, last end, ~first start, largest pair serial, largest tick stamp,
+                                 // touched edges, slab busy ticks, last end, ~first start, largest pair serial, (unused),
                                  // batches that loaded state, batches skipped, clock ticks in forward sweeps, clock ticks in
                                  // reverse sweeps and finalize
     int32_t *retry;              // [1 + npairs] pairs whose arcs did not fit

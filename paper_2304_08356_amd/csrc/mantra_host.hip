@@ -266,10 +266,10 @@ size_t lds_bytes(const mantra_graph *g) {
 
 // device bytes of one slab's per-node state (F: 16 B, shared by the forward
 // and the reverse; N: 8 B; touched: 4 B; the reached byte where the bitmap
-// is not in LDS) and of its per-tick scratch (XS and AG: 16 B, AGF: 4 B per
-// edge of the longest tick)
+// is not in LDS) and of its per-tick scratch (XS and AG: 16 B each per edge
+// of the longest tick)
 static size_t slab_state_bytes(const mantra_graph *g) {
-    return (size_t)g->nmax * 28 + node_bytes_per_slab(g->nmax) + (size_t)g->gmax * 36 + 16;
+    return (size_t)g->nmax * 28 + node_bytes_per_slab(g->nmax) + (size_t)g->gmax * 32 + 16;
 }
 
 // device memory and the share of it the slab pool (state and arc buffers)
@@ -375,7 +375,7 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap, in
     size_t ns = (size_t)nslabs;
     const int64_t xm = xmax_of(g, cap), xwords = (nchunks + 31) / 32;
     if (dalloc(&p.F, ns * nmax * 2) || dalloc(&p.N, ns * nmax) ||
-        dalloc(&p.AG, ns * (size_t)gmax * 2) || dalloc(&p.AGF, ns * (size_t)gmax) || dalloc(&p.touched, ns * nmax) ||
+        dalloc(&p.AG, ns * (size_t)gmax * 2) || dalloc(&p.touched, ns * nmax) ||
         dalloc(&p.arcs, ns * (size_t)cap * 4) || dalloc(&p.XS, ns * (size_t)gmax * 2) ||
         dalloc(&p.hdr, ns * 4) || (node_bytes_per_slab(nmax) && dalloc(&p.BM, ns * node_bytes_per_slab(nmax))) ||
         (nchunks > 0 && (dalloc(&p.xarcs, (size_t)nchunks * 4 * (size_t)kArcChunk) ||
@@ -395,8 +395,6 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap, in
     }
     HIPCHK(hipMemsetAsync(p.F, 0, sizeof(u64) * ns * nmax * 2, g->st));
     HIPCHK(hipMemsetAsync(p.N, 0, sizeof(u64) * ns * nmax, g->st));
-    HIPCHK(hipMemsetAsync(p.AG, 0xFF, sizeof(u64) * ns * gmax * 2, g->st));
-    HIPCHK(hipMemsetAsync(p.AGF, 0, sizeof(u32) * ns * gmax, g->st));
     HIPCHK(hipMemsetAsync(p.hdr, 0, sizeof(u32) * ns * 4, g->st));
     if (p.BM) HIPCHK(hipMemsetAsync(p.BM, 0, ns * node_bytes_per_slab(nmax), g->st));
     HIPCHK(hipStreamSynchronize(g->st));
@@ -466,32 +464,27 @@ static int pool_for(mantra_graph *g, int ns) {
 }
 
 // Slab state words carry their pair's tag (the slab's pair serial, +2 per
-// pair) and the long-tick scratch a tick stamp (+1 per long tick); both are
-// u32 that a slab carries across launches.  Before either could wrap -- a
-// word left by a pair 2^31 pairs earlier would then read as current -- the
-// pool's tagged words and stamps are cleared and the slabs start over.  The
-// kernels report each slab's serial and stamp; a launch advances a serial
-// by at most 2 per pair it holds, and a stamp by one per tick of more than
-// 64 edges (a launch would need 2^31 of them on one slab to wrap).
+// pair), a u32 that a slab carries across launches.  Before it could wrap --
+// a word left by a pair 2^31 pairs earlier would then read as current -- the
+// pool's tagged words and serials are cleared and the slabs start over.  The
+// kernels report each slab's serial; a launch advances it by at most 2 per
+// pair it holds.
 static constexpr u64 kStampLimit = 1ull << 31;
 static int stamps_clear(mantra_graph *g, SlabPool &p) {
     const size_t ns = (size_t)p.nslabs;
     HIPCHK(hipMemsetAsync(p.F, 0, sizeof(u64) * ns * (size_t)p.nmax * 2, g->st));
-    HIPCHK(hipMemsetAsync(p.AG, 0xFF, sizeof(u64) * ns * (size_t)p.gmax * 2, g->st));
-    HIPCHK(hipMemsetAsync(p.AGF, 0, sizeof(u32) * ns * (size_t)p.gmax, g->st));
     HIPCHK(hipMemsetAsync(p.hdr, 0, sizeof(u32) * ns * 4, g->st));
     HIPCHK(hipStreamSynchronize(g->st));
-    p.serial_hi = p.tick_hi = 0;
+    p.serial_hi = 0;
     return MANTRA_OK;
 }
 static int stamps_before(mantra_graph *g, SlabPool &p, int64_t slots) {
-    if (p.serial_hi + 2 * (u64)(slots + 1) >= 2 * kStampLimit || p.tick_hi >= kStampLimit) return stamps_clear(g, p);
+    if (p.serial_hi + 2 * (u64)(slots + 1) >= 2 * kStampLimit) return stamps_clear(g, p);
     return MANTRA_OK;
 }
 static int stamps_after(mantra_graph *g, SlabPool &p, const u64 *st) {
     p.serial_hi = std::max(p.serial_hi, st[12]);
-    p.tick_hi = std::max(p.tick_hi, st[13]);
-    if (p.serial_hi >= kStampLimit || p.tick_hi >= kStampLimit) return stamps_clear(g, p);
+    if (p.serial_hi >= kStampLimit) return stamps_clear(g, p);
     return MANTRA_OK;
 }
 static int wide_stamps(mantra_graph *g, int64_t slots, const u64 *st) {
@@ -1318,17 +1311,16 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {
     return MANTRA_OK;
 }
 
-int mantra_debug_stamps(mantra_graph *g, uint32_t serial, uint32_t tick_stamp) {
+int mantra_debug_stamps(mantra_graph *g, uint32_t serial) {
     if (!g) return fail(MANTRA_E_INVALID, "graph is NULL");
     std::lock_guard<std::mutex> lk(g->mu);
     hipSetDevice(g->device);
     int rc = pool_for(g, auto_slabs(g));
     if (rc) return rc;
     std::vector<u32> h((size_t)g->pool.nslabs * 4, 0u);
-    for (size_t i = 0; i < (size_t)g->pool.nslabs; ++i) { h[4 * i] = serial; h[4 * i + 1] = tick_stamp; }
+    for (size_t i = 0; i < (size_t)g->pool.nslabs; ++i) h[4 * i] = serial;
     HIPCHK(hipMemcpy(g->pool.hdr, h.data(), sizeof(u32) * h.size(), hipMemcpyHostToDevice));
     g->pool.serial_hi = serial;
-    g->pool.tick_hi = tick_stamp;
     if (g->wide.nslabs) {
         std::vector<u32> w((size_t)g->wide.nslabs * 4, 0u);
         for (size_t i = 0; i < (size_t)g->wide.nslabs; ++i) w[4 * i] = serial;

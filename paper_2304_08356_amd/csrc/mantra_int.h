@@ -70,28 +70,28 @@ struct SlabPool {
     u64 *F = nullptr, *N = nullptr, *AG = nullptr, *arcs = nullptr, *XS = nullptr;
     u64 *T = nullptr;  // RTB launches only: first arrivals, [nslabs][nmax][2]
     unsigned char *BM = nullptr;  // reached node bytes (graphs whose bitmap is not in LDS)
-    u32 *AGF = nullptr, *hdr = nullptr;
+    u32 *hdr = nullptr;
     int32_t *touched = nullptr;
     // shared arc chunks for pairs whose arcs pass the slab's own buffer
     u64 *xarcs = nullptr;
     u32 *xfree = nullptr, *xtab = nullptr;
     int64_t nchunks = 0, xmax = 0;
-    // largest pair serial and tick stamp of any slab (the wrap guard)
-    u64 serial_hi = 0, tick_hi = 0;
+    // largest pair serial of any slab (the wrap guard)
+    u64 serial_hi = 0;
     void release() {
         hipFree(F); hipFree(N); hipFree(AG); hipFree(arcs); hipFree(XS); hipFree(T); hipFree(BM);
-        hipFree(AGF); hipFree(hdr); hipFree(touched); hipFree(xarcs); hipFree(xfree); hipFree(xtab);
+        hipFree(hdr); hipFree(touched); hipFree(xarcs); hipFree(xfree); hipFree(xtab);
         F = N = AG = arcs = XS = T = xarcs = nullptr;
         BM = nullptr;
-        AGF = hdr = xfree = xtab = nullptr;
+        hdr = xfree = xtab = nullptr;
         touched = nullptr;
         nslabs = 0;
         nchunks = xmax = 0;
-        serial_hi = tick_hi = 0;
+        serial_hi = 0;
     }
     DevSlabs view() const {
         DevSlabs s;
-        s.F = F; s.N = N; s.T = T; s.AG = AG; s.AGF = AGF; s.touched = touched; s.arcs = arcs;
+        s.F = F; s.N = N; s.T = T; s.AG = AG; s.touched = touched; s.arcs = arcs;
         s.XS = XS; s.BM = BM; s.hdr = hdr; s.nmax = nmax; s.cap = cap; s.gmax = gmax;
         s.xarcs = xarcs; s.xfree = xfree; s.xtab = xtab; s.xwords = (nchunks + 31) / 32; s.xmax = xmax;
         return s;

@@ -53,7 +53,7 @@ struct Carve {
 
 // the slab pieces of ns slabs for graph g, own arc room cap (offsets into the array)
 struct SlabOffsets {
-    size_t F, N, AG, AGF, touched, arcs, XS, hdr, BM;
+    size_t F, N, AG, touched, arcs, XS, hdr, BM;
 };
 SlabOffsets carve_slabs(Carve &c, const mantra_graph *g, size_t ns, int64_t cap) {
     SlabOffsets o;
@@ -61,7 +61,6 @@ SlabOffsets carve_slabs(Carve &c, const mantra_graph *g, size_t ns, int64_t cap)
     o.F = c.take<u64>(ns * n * 2);
     o.N = c.take<u64>(ns * n);
     o.AG = c.take<u64>(ns * gm * 2);
-    o.AGF = c.take<u32>(ns * gm + 1);  // cleared in 8-byte words
     o.touched = c.take<int32_t>(ns * n);
     o.arcs = c.take<u64>(ns * (size_t)cap * 4);
     o.XS = c.take<u64>(ns * gm * 2);
@@ -156,12 +155,10 @@ int mantra_count_pairs_static(mantra_graph *g, mantra_opt opt, int32_t t0, int32
         HIPCHK(hipStreamSynchronize(g->st));
     }
     // what must start at zero (the previous call's contents are still there):
-    // pair tags and counts, N, the tick scratch stamps, slab serials, counters
-    const size_t n = (size_t)g->nmax, gm = (size_t)g->gmax;
+    // pair tags and counts, N, slab serials, counters
+    const size_t n = (size_t)g->nmax;
     HIPCHK(mantra_launch_fill(reinterpret_cast<u64 *>(base + so.F), 0ull, (int64_t)(ns * n * 2), g->st));
     HIPCHK(mantra_launch_fill(reinterpret_cast<u64 *>(base + so.N), 0ull, (int64_t)(ns * n), g->st));
-    HIPCHK(mantra_launch_fill(reinterpret_cast<u64 *>(base + so.AG), ~0ull, (int64_t)(ns * gm * 2), g->st));
-    HIPCHK(mantra_launch_fill(reinterpret_cast<u64 *>(base + so.AGF), 0ull, (int64_t)((ns * gm + 1) / 2), g->st));
     HIPCHK(mantra_launch_fill(reinterpret_cast<u64 *>(base + so.hdr), 0ull, (int64_t)(ns * 2), g->st));
     HIPCHK(mantra_launch_clear(reinterpret_cast<u32 *>(base + o_work), reinterpret_cast<u32 *>(base + o_retry),
                                nullptr, reinterpret_cast<u64 *>(base + o_stats), g->st));
@@ -171,7 +168,6 @@ int mantra_count_pairs_static(mantra_graph *g, mantra_opt opt, int32_t t0, int32
     a.sl.F = reinterpret_cast<u64 *>(base + so.F);
     a.sl.N = reinterpret_cast<u64 *>(base + so.N);
     a.sl.AG = reinterpret_cast<u64 *>(base + so.AG);
-    a.sl.AGF = reinterpret_cast<u32 *>(base + so.AGF);
     a.sl.touched = reinterpret_cast<int32_t *>(base + so.touched);
     a.sl.arcs = reinterpret_cast<u64 *>(base + so.arcs);
     a.sl.XS = reinterpret_cast<u64 *>(base + so.XS);

@@ -216,7 +216,6 @@ struct Slab {
         return a.sl.touched + id * a.sl.nmax;
     }
     __device__ __forceinline__ u64 *AG() const { KArgs &a = launch_args(); return a.sl.AG + id * a.sl.gmax * 2; }
-    __device__ __forceinline__ u32 *AGF() const { KArgs &a = launch_args(); return a.sl.AGF + id * a.sl.gmax; }
     __device__ __forceinline__ u64 *XS() const { KArgs &a = launch_args(); return a.sl.XS + id * a.sl.gmax * 2; }
     // RTB: [nmax][2] first arrival {time | hops << 32, count} of each reached node
     __device__ __forceinline__ u64 *T() const { KArgs &a = launch_args(); return a.sl.T + id * a.sl.nmax * 2; }
@@ -412,188 +411,347 @@ __device__ __forceinline__ bool head_commit(int opt, bool rv, u32 hv, u64 Sv, u3
 }
 
 // ------------------------------------------------------------ forward: long tick
-// A tick with more edges than one row (64): aggregation by head through the
-// slab's global per-node scratch (AG), four passes, commits after all reads.
-// Such a tick always forms a batch of its own.
+// A tick of more edges than one row of 64 forms a batch of its own.  Every
+// edge of a tick reads the state from before the tick, so the reads of all
+// its rows can go out at once, and the tick's commits follow once every read
+// is done.  The tick's edges are sorted by head, so the edges of one head
+// form one contiguous run; a run's candidate (min hops, count) is reduced by a
+// segmented scan across the lanes, row after row, with the partial of a run
+// that continues into the next row carried in wave-uniform registers.  Ticks
+// of up to two rows are held in registers (fwd_tick2); longer ones keep the
+// per-edge tail state and the per-run decisions in the slab's scratch XS / AG
+// between a read pass and a commit pass (fwd_long_tick).
 
 // forward modes: a pair (arcs, stop at z); a source's distances (no arcs,
 // first-arrival hops in N); a source for the RTB estimator (arcs, and each
 // node's first arrival {time | hops << 32, count} in T)
 enum { FWD_PAIR = 0, FWD_DIST = 1, FWD_RTB = 2 };
 
-template <int FM, bool GBM>
-__device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
-                              int64_t g0, int64_t g1, int32_t t, u32 &agstamp, FwdOut &o,
-                              u32 &zh, u64 &zS, bool &zhit) {
-    u64 *const Fp = S.F();
-    u64 *const XSp = S.XS();
-    u64 *const AGp = S.AG();
-    u32 *const AGFp = S.AGF();
-    u64 *const Np = S.N();
-    u64 *const Tp = S.T();
-    int32_t *const Tch = S.touched();
-    constexpr bool SINGLE = FM != FWD_PAIR;
+__device__ __forceinline__ u64 shfl_up64(u64 x, int off) {
+    const u32 lo = (u32)__shfl_up((int)(u32)x, off);
+    const u32 hi = (u32)__shfl_up((int)(u32)(x >> 32), off);
+    return ((u64)hi << 32) | lo;
+}
+
+// (d, c) <- (d, c) + (d2, c2) over one head's candidates: the fewest hops d and
+// the count of the walks that reach the head with them (sh / sfm), or the
+// fewest hops and the count over every reached tail (fm / pfm)
+__device__ __forceinline__ void cand_join(bool level, u32 &d, u64 &c, u32 d2, u64 c2) {
+    if (!level) { d = d2 < d ? d2 : d; c = sat_add(c, c2); return; }
+    if (d2 < d) { d = d2; c = c2; }
+    else if (d2 == d) c = sat_add(c, c2);
+}
+
+// Segmented inclusive scan of (d, c) over the lanes of one row: st = lane of
+// my run's start in the row (-1: the run started in an earlier row, whose
+// partial (cd, cc) is joined).  A run-end lane then holds its run's total.
+__device__ __forceinline__ void run_scan(bool level, bool multi, int st, u32 cd, u64 cc, u32 &d, u64 &c) {
     const int l = lane_id();
-    const int32_t *U = a.g.U, *V = a.g.V;
-    agstamp += 1;
-    const u64 hi_key = (u64)(~agstamp) << 32;
+    if (multi) {
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const u32 d2 = (u32)__shfl_up((int)d, off);
+            const u64 c2 = shfl_up64(c, off);
+            if (l - off >= st && l >= off) cand_join(level, d, c, d2, c2);
+        }
+    }
+    if (st < 0) cand_join(level, d, c, cd, cc);
+}
+
+// the tail state (hops, count) of a lane from its loaded words (hops kHInf:
+// not reached); the hub's LDS copy for hub nodes
+__device__ __forceinline__ void state_of(const Pair &P, const Hub &H, bool maybe, int32_t x, u64 th, u64 ts,
+                                         u32 lh, u64 ls, u32 &h, u64 &c) {
+    const bool hub = x < H.K;
+    h = !maybe ? kHInf : hub ? lh : ((u32)th == P.tag) ? ((u32)(th >> 32) & 0xFFFFu) : kHInf;
+    c = hub ? ls : ts;
+}
+
+// a committed head: its new state and the reached set
+template <bool GBM>
+__device__ __forceinline__ void head_store(const Pair &P, const Slab &S, u32 *bm, const Hub &H, int32_t v,
+                                           u32 nh, u64 nS) {
+    if (v < H.K) { H.h[v] = nh; H.s[v] = nS; }
+    else {
+        u64 *const Fp = S.F();
+        Fp[2 * (int64_t)v] = (u64)P.tag | ((u64)nh << 32);
+        Fp[2 * (int64_t)v + 1] = nS;
+    }
+    rch_set<GBM>(bm, v);
+}
+// single source: the first arrivals of a row (the list of reached nodes, and
+// the hops (distances) or the first arrival (RTB) committed there)
+template <int FM>
+__device__ __forceinline__ void first_arrivals(const Pair &P, const Slab &S, FwdOut &o, bool fa, int32_t v,
+                                               int32_t t, u32 nh, u64 nS) {
+    if (FM == FWD_PAIR) return;
+    const u64 fm_ = ballot(fa);
+    if (fa) {
+        if (FM == FWD_DIST && P.opt != OPT_SH) S.N()[v] = (u64)nh + 1ull;
+        if (FM == FWD_RTB) {
+            u64 *const Tp = S.T();
+            Tp[2 * (int64_t)v] = (u64)(u32)t | ((u64)nh << 32);
+            Tp[2 * (int64_t)v + 1] = nS;
+        }
+        S.touched()[o.reached_n + mbcnt(fm_)] = v;
+    }
+    o.reached_n += __popcll(fm_);
+}
+
+// a tick of 65..128 edges at g0 (ur / vr: tail and head of edge g0 + 64 r +
+// lane; head -1 past g1)
+template <int FM, bool GBM>
+__device__ void fwd_tick2(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
+                          int64_t g0, int64_t g1, int32_t t, const int32_t (&ur)[2], const int32_t (&vr)[2],
+                          FwdOut &o, u32 &zh, u64 &zS, bool &zhit) {
+    constexpr int R = 2;
+    u64 *const Fp = S.F();
+    const int l = lane_id();
+    const int opt = P.opt;
     const u64 le = (l == kWave - 1) ? kUMax : ((2ull << l) - 1ull);  // lanes <= l
-    // The tick's edges are sorted by head, so each head's edges form one run.
-    // A run is aggregated in the slab's scratch at the position of its first
-    // edge (k, counted from g0), not at its node: the scratch is as long as
-    // the longest tick, not the node count.
-    int64_t carry = g0;  // start of the run that continues into a sub-batch
-    // pass A: tails, candidate minima, zero the sums
-    for (int64_t sb = g0; sb < g1; sb += kWave) {
-        int64_t idx = sb + l;
-        bool act = idx < g1;
-        int32_t u = act ? U[idx] : 0, v = act ? V[idx] : 0;
-        const bool rs = act && ((idx == g0) || V[idx - 1] != v);
-        const u64 rm = ballot(rs);
-        const u64 mine = rm & le;
-        const int64_t k = (mine ? sb + (63 - __clzll((long long)mine)) : carry) - g0;
-        if (rm) carry = sb + (63 - __clzll((long long)rm));
-        bool rt = false;
-        u32 hu = 0;
-        u64 Su = 0;
-        if (act) {
-            const bool maybe = rch_test<GBM>(bm, u);
-            if (maybe && u < H.K) {
-                rt = true; hu = H.h[u]; Su = H.s[u];
-            } else if (maybe) {
-                u64 th = Fp[2 * (int64_t)u], sv = Fp[2 * (int64_t)u + 1];
-                if ((u32)th == P.tag) { rt = true; hu = (u32)(th >> 32) & 0xFFFFu; Su = sv; }
-            }
-        }
-        bool hl = false;
-        if (act) {
-            // {hops | reached << 32 | run position << 33, count} of the tail
-            XSp[2 * (idx - g0)] = rt ? ((u64)hu | (1ull << 32) | ((u64)k << 33)) : 0ull;
-            XSp[2 * (idx - g0) + 1] = Su;
-            if (rs) AGp[2 * k + 1] = 0ull;
-            if (rt) {
-                if (hu + 1 >= kHInf) hl = true;
-                else atomicMin((unsigned long long *)&AGp[2 * k], (unsigned long long)(hi_key | (hu + 1)));
-            }
-        }
-        if (ballot(hl)) o.flags |= REC_HOPS_LIMIT;
+    const u64 ge = ~((1ull << l) - 1ull);                             // lanes >= l
+    const u32 kBig = 0xFFFFFFFFu;
+    bool rs[R], re[R], rt[R], hr[R];
+    u64 any = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool act = g0 + r * kWave + l < g1;
+        int32_t vp = __shfl_up(vr[r], 1);
+        int32_t vn = __shfl_down(vr[r], 1);
+        if (l == 0) vp = r == 0 ? -2 : rl32(vr[r - 1 < 0 ? 0 : r - 1], kWave - 1);
+        if (l == kWave - 1) vn = r + 1 < R ? rl32(vr[r + 1 < R ? r + 1 : r], 0) : -1;
+        rs[r] = act && vr[r] != vp;
+        re[r] = act && vr[r] != vn;
+        const bool dead = opt == OPT_PFM && act && rch_test<GBM>(bm, vr[r]);
+        rt[r] = act && !dead && rch_test<GBM>(bm, ur[r]);
+        hr[r] = re[r] && !dead && rch_test<GBM>(bm, vr[r]);
+        any |= ballot(rt[r]);
     }
-    __syncthreads();
-    // pass B: sums over the tight tails
-    for (int64_t sb = g0; sb < g1; sb += kWave) {
-        int64_t idx = sb + l;
-        if (idx >= g1) continue;
-        u64 x0 = XSp[2 * (idx - g0)];
-        if (!(x0 >> 32)) continue;
-        u32 hu = (u32)x0;
-        const int64_t k = (int64_t)(x0 >> 33);
-        u64 Su = XSp[2 * (idx - g0) + 1];
-        u64 key = ld_agent(&AGp[2 * k]);
-        u32 d = (u32)key;
-        bool tight = P.level ? (hu + 1 == d) : true;
-        if (tight) glb_sat_add(&AGp[2 * k + 1], Su);
+    if (!any) { o.dead += 1; return; }
+    o.live += 1;
+    // the state before the tick: every lane loads (see the batch path), both
+    // rows at once, then each word is decoded
+    u64 thu[R], tsu[R], thv[R], tsv[R];
+    u32 lhu[R], lhv[R];
+    u64 lsu[R], lsv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t iu = (rt[r] && ur[r] >= H.K) ? (int64_t)ur[r] : (int64_t)P.s;
+        const int64_t iv = (hr[r] && vr[r] >= H.K) ? (int64_t)vr[r] : (int64_t)P.s;
+        thu[r] = Fp[2 * iu];
+        tsu[r] = Fp[2 * iu + 1];
+        thv[r] = Fp[2 * iv];
+        tsv[r] = Fp[2 * iv + 1];
+        lhu[r] = 0; lhv[r] = 0; lsu[r] = 0; lsv[r] = 0;
+        if (H.K > 0) {
+            const int ju = ur[r] < H.K ? ur[r] : 0, jv = (vr[r] >= 0 && vr[r] < H.K) ? vr[r] : 0;
+            lhu[r] = H.h[ju]; lsu[r] = H.s[ju];
+            lhv[r] = H.h[jv]; lsv[r] = H.s[jv];
+        }
     }
-    __syncthreads();
-    // pass C: one commit per head run
+    u32 hu[R], hv[R];
+    u64 su[R], sv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        state_of(P, H, rt[r], ur[r], thu[r], tsu[r], lhu[r], lsu[r], hu[r], su[r]);
+        state_of(P, H, hr[r], vr[r], thv[r], tsv[r], lhv[r], lsv[r], hv[r], sv[r]);
+    }
+    if (ballot((hu[0] != kHInf && hu[0] + 1 >= kHInf) || (hu[1] != kHInf && hu[1] + 1 >= kHInf))) {
+        o.flags |= REC_HOPS_LIMIT;
+        return;
+    }
+    // per run: the candidate over its tails, then its head's decision; every
+    // read of the tick is done, so a run's commit follows at once
+    u32 mine[R];   // at run ends: d | commit << 31
+    u32 cd = kBig;
+    u64 cc = 0;
     u32 zh_new = zh;
     u64 zS_new = zS;
     bool zany = false;
-    for (int64_t sb = g0; sb < g1; sb += kWave) {
-        int64_t idx = sb + l;
-        bool act = idx < g1;
-        int32_t v = act ? V[idx] : 0;
-        bool rs = act && ((idx == g0) || V[idx - 1] != v);
-        bool zl = false, fa = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        u32 d = hu[r] != kHInf ? hu[r] + 1 : kBig;
+        u64 c = hu[r] != kHInf ? su[r] : 0ull;
+        const u64 below = ballot(rs[r]) & le;
+        const int st = below ? 63 - __clzll((long long)below) : -1;
+        const bool multi = ballot((g0 + r * kWave + l < g1) && !(rs[r] && re[r])) != 0;
+        run_scan(P.level, multi, st, cd, cc, d, c);
+        // the row's last run continues into the next row
+        if (g0 + r * kWave + kWave - 1 < g1 && !(ballot(re[r]) >> (kWave - 1))) {
+            cd = (u32)rl32((int)d, kWave - 1);
+            cc = rl64(c, kWave - 1);
+        } else { cd = kBig; cc = 0; }
         u32 nh = 0;
         u64 nS = 0;
-        if (rs) {
-            const int64_t k = idx - g0;
-            u64 key = ld_agent(&AGp[2 * k]);
-            u32 ok = 0;
-            if ((key & 0xFFFFFFFF00000000ull) == hi_key) {
-                u32 d = (u32)key;
-                u64 c = ld_agent(&AGp[2 * k + 1]);
-                bool rv = false;
-                u32 hv = 0;
-                u64 Sv = 0;
-                const bool maybe = rch_test<GBM>(bm, v);
-                if (maybe && v < H.K) {
-                    rv = true; hv = H.h[v]; Sv = H.s[v];
-                } else if (maybe) {
-                    u64 th = Fp[2 * (int64_t)v], sv = Fp[2 * (int64_t)v + 1];
-                    if ((u32)th == P.tag) { rv = true; hv = (u32)(th >> 32) & 0xFFFFu; Sv = sv; }
-                }
-                if (head_commit(P.opt, rv, hv, Sv, d, c, v, P.z, zh, &nh, &nS)) {
-                    ok = agstamp;
-                    if (SINGLE && !rv) {  // first arrival: list of reached nodes, hops (fm / sfm / pfm)
-                        if (FM == FWD_DIST && P.opt != OPT_SH) Np[v] = (u64)nh + 1ull;
-                        if (FM == FWD_RTB) {
-                            Tp[2 * (int64_t)v] = (u64)(u32)t | ((u64)nh << 32);
-                            Tp[2 * (int64_t)v + 1] = nS;
-                        }
-                        fa = true;
-                    }
-                    if (v < H.K) { H.h[v] = nh; H.s[v] = nS; }
-                    else {
-                        Fp[2 * (int64_t)v] = (u64)P.tag | ((u64)nh << 32);
-                        Fp[2 * (int64_t)v + 1] = nS;
-                    }
-                    rch_set<GBM>(bm, v);
-                    zl = (v == P.z);
-                }
-            }
-            AGFp[k] = ok;
-        }
-        if (SINGLE) {
-            const u64 fm_ = ballot(fa);
-            if (fa) Tch[o.reached_n + mbcnt(fm_)] = v;
-            o.reached_n += __popcll(fm_);
-        }
-        u64 zm = ballot(zl);
+        const bool ok = re[r] && d != kBig &&
+                        head_commit(opt, hv[r] != kHInf, hv[r], sv[r], d, c, vr[r], P.z, zh, &nh, &nS);
+        if (ok) head_store<GBM>(P, S, bm, H, vr[r], nh, nS);
+        first_arrivals<FM>(P, S, o, ok && hv[r] == kHInf, vr[r], t, nh, nS);
+        const u64 zm = ballot(ok && vr[r] == P.z);
         if (zm) {
-            int zlane = __ffsll((long long)zm) - 1;
-            zh_new = (u32)rl32((int)nh, zlane);
-            zS_new = rl64(nS, zlane);
+            const int zl = __ffsll((long long)zm) - 1;
+            zh_new = (u32)rl32((int)nh, zl);
+            zS_new = rl64(nS, zl);
             zany = true;
+        }
+        mine[r] = ok ? (d | 0x80000000u) : 0u;
+    }
+    // each edge learns its run's decision (d, commit) from the run's end
+    // lane, in its row or, for a run that continues, in the next one
+    u32 okd[R];
+    u32 back = 0;
+#pragma unroll
+    for (int r = R - 1; r >= 0; --r) {
+        const u64 m = ballot(re[r]) & ge;
+        const int src = m ? __ffsll((long long)m) - 1 : l;
+        u32 x = (u32)__shfl((int)mine[r], src);
+        if (!m) x = back;
+        okd[r] = x;
+        back = (u32)rl32((int)x, 0);
+    }
+    // arcs in edge order
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const u32 dd = okd[r] & 0x7FFFFFFFu;
+        const bool rec = FM != FWD_DIST && hu[r] != kHInf && (okd[r] >> 31) && (!P.level || hu[r] + 1 == dd);
+        const u64 m = ballot(rec);
+        if (m) {
+            if (!arc_room(a, S, o, o.arcs + __popcll(m))) { o.flags |= REC_ARCS_LIMIT; return; }
+            if (rec) put_arc(S, o.arcs + mbcnt(m), vr[r], t, (u32)(g0 + r * kWave + l), ur[r], su[r], hu[r], dd);
+            o.arcs += __popcll(m);
         }
     }
     if (zany) {
-        if (P.opt == OPT_SH) { if (zh_new < zh) o.t_arr = t; }
+        if (opt == OPT_SH) { if (zh_new < zh) o.t_arr = t; }
         else o.t_arr = t;
         zh = zh_new;
         zS = zS_new;
         zhit = true;
     }
-    __syncthreads();
-    // pass D: arcs
+}
+
+// a tick of more than 128 edges [g0, g1): a read pass that keeps each edge's
+// tail state {hops | reached << 32 | run start << 33, count} in XS and each
+// run's decision {d | new hops << 32 | first arrival << 62 | commit << 63,
+// new count} in AG at the run's first edge, then a commit pass
+template <int FM, bool GBM>
+__device__ void fwd_long_tick(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H,
+                              int64_t g0, int64_t g1, int32_t t, FwdOut &o, u32 &zh, u64 &zS, bool &zhit) {
+    u64 *const Fp = S.F();
+    u64 *const XSp = S.XS();
+    u64 *const AGp = S.AG();
+    const int l = lane_id();
+    const int opt = P.opt;
+    const int32_t *U = a.g.U, *V = a.g.V;
+    const u64 le = (l == kWave - 1) ? kUMax : ((2ull << l) - 1ull);  // lanes <= l
+    const u32 kBig = 0xFFFFFFFFu;
+    u32 cd = kBig;       // partial of the run that continues into the row
+    u64 cc = 0;
+    int64_t cs = g0;     // its first edge
+    int32_t cv = -2;     // head of the previous row's last edge
+    bool any = false;
     for (int64_t sb = g0; sb < g1; sb += kWave) {
-        int64_t idx = sb + l;
-        bool rec = false;
-        u32 hu = 0, d = 0;
-        int32_t v = 0, u = 0;
-        u64 su = 0;
-        if (idx < g1) {
-            u64 x0 = XSp[2 * (idx - g0)];
-            if (x0 >> 32) {
-                v = V[idx];
-                const int64_t k = (int64_t)(x0 >> 33);
-                if (AGFp[k] == agstamp) {
-                    hu = (u32)x0;
-                    d = (u32)ld_agent(&AGp[2 * k]);
-                    if ((!P.level || hu + 1 == d) && FM != FWD_DIST) {
-                        rec = true;
-                        u = U[idx];
-                        su = XSp[2 * (idx - g0) + 1];
-                    }
-                }
-            }
+        const int64_t idx = sb + l;
+        const bool act = idx < g1;
+        const int32_t u = act ? U[idx] : 0, v = act ? V[idx] : -1;
+        const int32_t vnx = sb + kWave < g1 ? V[sb + kWave] : -1;
+        int32_t vp = __shfl_up(v, 1);
+        int32_t vn = __shfl_down(v, 1);
+        if (l == 0) vp = cv;
+        if (l == kWave - 1) vn = vnx;
+        const bool rs = act && v != vp, re = act && v != vn;
+        const bool dead = opt == OPT_PFM && act && rch_test<GBM>(bm, v);
+        const bool rt = act && !dead && rch_test<GBM>(bm, u);
+        const bool hr = re && !dead && rch_test<GBM>(bm, v);
+        const int64_t iu = (rt && u >= H.K) ? (int64_t)u : (int64_t)P.s;
+        const int64_t iv = (hr && v >= H.K) ? (int64_t)v : (int64_t)P.s;
+        const u64 thu = Fp[2 * iu], tsu = Fp[2 * iu + 1], thv = Fp[2 * iv], tsv = Fp[2 * iv + 1];
+        u32 lhu = 0, lhv = 0;
+        u64 lsu = 0, lsv = 0;
+        if (H.K > 0) {
+            const int ju = u < H.K ? u : 0, jv = (v >= 0 && v < H.K) ? v : 0;
+            lhu = H.h[ju]; lsu = H.s[ju];
+            lhv = H.h[jv]; lsv = H.s[jv];
         }
-        u64 m = ballot(rec);
+        u32 hu, hv;
+        u64 su, sv;
+        state_of(P, H, rt, u, thu, tsu, lhu, lsu, hu, su);
+        if (ballot(hu != kHInf && hu + 1 >= kHInf)) { o.flags |= REC_HOPS_LIMIT; return; }
+        u32 d = hu != kHInf ? hu + 1 : kBig;
+        u64 c = hu != kHInf ? su : 0ull;
+        const u64 below = ballot(rs) & le;
+        const int st = below ? 63 - __clzll((long long)below) : -1;
+        run_scan(P.level, ballot(act && !(rs && re)) != 0, st, cd, cc, d, c);
+        state_of(P, H, hr, v, thv, tsv, lhv, lsv, hv, sv);
+        u32 nh = 0;
+        u64 nS = 0;
+        const bool ok = re && d != kBig && head_commit(opt, hv != kHInf, hv, sv, d, c, v, P.z, zh, &nh, &nS);
+        const int64_t k = (st >= 0 ? sb + st : cs) - g0;
+        if (re)
+            AGp[2 * k] = (u64)d | ((u64)nh << 32) | ((u64)(ok && hv == kHInf) << 62) | ((u64)ok << 63);
+        if (re) AGp[2 * k + 1] = nS;
+        if (act) {
+            XSp[2 * (idx - g0)] = (u64)hu | ((u64)(hu != kHInf) << 32) | ((u64)rs << 33);
+            XSp[2 * (idx - g0) + 1] = su;
+        }
+        any = any || ballot(ok) != 0;
+        const int st63 = rl32(st, kWave - 1);
+        if (ballot(l == kWave - 1 && act && !re)) {
+            cd = (u32)rl32((int)d, kWave - 1);
+            cc = rl64(c, kWave - 1);
+            if (st63 >= 0) cs = sb + st63;
+        } else { cd = kBig; cc = 0; }
+        cv = rl32(v, kWave - 1);
+    }
+    if (!any) { o.dead += 1; return; }
+    o.live += 1;
+    __syncthreads();
+    u32 zh_new = zh;
+    u64 zS_new = zS;
+    bool zany = false;
+    u64 cr0 = 0, cr1 = 0;  // decision of the run that continues into the row
+    for (int64_t sb = g0; sb < g1; sb += kWave) {
+        const int64_t idx = sb + l;
+        const bool act = idx < g1;
+        const int64_t i = act ? idx - g0 : 0;
+        const u64 x0 = act ? XSp[2 * i] : 0ull, su = act ? XSp[2 * i + 1] : 0ull;
+        const u64 a0 = act ? AGp[2 * i] : 0ull, a1 = act ? AGp[2 * i + 1] : 0ull;
+        const int32_t u = act ? U[idx] : 0, v = act ? V[idx] : 0;
+        const bool rs = act && ((x0 >> 33) & 1ull);
+        const u64 below = ballot(rs) & le;
+        const int st = below ? 63 - __clzll((long long)below) : 0;
+        u64 r0 = shfl64(a0, st), r1 = shfl64(a1, st);
+        if (!below) { r0 = cr0; r1 = cr1; }
+        const bool okr = act && (r0 >> 63);
+        const u32 dd = (u32)r0;
+        const u32 nh = (u32)(r0 >> 32) & 0xFFFFu;
+        const bool ok = rs && okr;
+        if (ok) head_store<GBM>(P, S, bm, H, v, nh, r1);
+        first_arrivals<FM>(P, S, o, ok && ((r0 >> 62) & 1ull), v, t, nh, r1);
+        const u64 zm = ballot(ok && v == P.z);
+        if (zm) {
+            const int zl = __ffsll((long long)zm) - 1;
+            zh_new = (u32)rl32((int)nh, zl);
+            zS_new = rl64(r1, zl);
+            zany = true;
+        }
+        const u32 hu = (u32)x0;
+        const bool rec = FM != FWD_DIST && okr && ((x0 >> 32) & 1ull) && (!P.level || hu + 1 == dd);
+        const u64 m = ballot(rec);
         if (m) {
             if (!arc_room(a, S, o, o.arcs + __popcll(m))) { o.flags |= REC_ARCS_LIMIT; return; }
-            if (rec) put_arc(S, o.arcs + mbcnt(m), v, t, (u32)idx, u, su, hu, d);
+            if (rec) put_arc(S, o.arcs + mbcnt(m), v, t, (u32)idx, u, su, hu, dd);
             o.arcs += __popcll(m);
         }
+        cr0 = rl64(r0, kWave - 1);
+        cr1 = rl64(r1, kWave - 1);
+    }
+    if (zany) {
+        if (opt == OPT_SH) { if (zh_new < zh) o.t_arr = t; }
+        else o.t_arr = t;
+        zh = zh_new;
+        zS = zS_new;
+        zhit = true;
     }
     __syncthreads();
 }
@@ -615,14 +773,14 @@ __device__ __forceinline__ void load_batch(KArgs &a, const Pair &P, int64_t b, i
 
 // Forward sweep of one pair over its window [P.lo, P.hi), in batches of up to
 // 64 edges (one per lane) that hold whole ticks; a tick longer than 64 edges
-// is a batch of its own (fwd_long_tick).  Within a batch, the edges of tick
+// is a batch of its own (fwd_tick2, fwd_long_tick).  Within a batch, the edges of tick
 // tau read the state committed before tau: the state at batch start (loaded
 // from the slab) or the commit of an earlier tick of the same batch, passed
 // from the committing lane's registers.  Maximal runs of ticks that read no
 // commit made inside the run ("segments") are processed together.
 template <int FM, bool GBM>
 __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const Hub &H, FwdLds &L,
-                        u32 &agstamp, FwdOut &o) {
+                        FwdOut &o) {
     u64 *const Fp = S.F();
     u64 *const Np = S.N();
     u64 *const Tp = S.T();
@@ -653,19 +811,30 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
             if (tnext == tlast) {
                 const int first = __ffsll((long long)ballot(t == tlast)) - 1;
                 if (first == 0) {
-                    // one tick longer than a batch
-                    int64_t g1 = P.hi;
-                    for (int64_t i = b0 + kWave; i < P.hi; i += kWave) {
-                        const int64_t idx = i + l;
-                        const u64 m = ballot(idx < P.hi && a.g.T[idx] != tlast);
-                        if (m) { g1 = i + (__ffsll((long long)m) - 1); break; }
+                    // one tick longer than a batch: its second row, and its end
+                    const int64_t i1 = b0 + kWave + l;
+                    const bool in1 = i1 < P.hi;
+                    const int32_t t1 = in1 ? a.g.T[i1] : INT32_MAX;
+                    int32_t ur[2] = {u, in1 ? a.g.U[i1] : 0};
+                    int32_t vr[2] = {v, in1 ? a.g.V[i1] : -1};
+                    const u64 mt = ballot(t1 == tlast);
+                    int64_t g1;
+                    if (~mt) {
+                        g1 = b0 + kWave + (__ffsll((long long)~mt) - 1);
+                        if (t1 != tlast) { ur[1] = 0; vr[1] = -1; }
+                    } else {
+                        // no tick is longer than the graph's longest one
+                        const int64_t lim = b0 + a.sl.gmax + 1 < P.hi ? b0 + a.sl.gmax + 1 : P.hi;
+                        g1 = wave_upper_bound(a.g.T, b0 + 2 * kWave, lim, tlast);
                     }
                     __syncthreads();
-                    fwd_long_tick<FM, GBM>(a, P, S, bm, H, b0, g1, tlast, agstamp, o, zh, zS, zhit);
+                    if (g1 - b0 <= 2 * kWave) fwd_tick2<FM, GBM>(a, P, S, bm, H, b0, g1, tlast, ur, vr, o, zh, zS, zhit);
+                    else fwd_long_tick<FM, GBM>(a, P, S, bm, H, b0, g1, tlast, o, zh, zS, zhit);
                     o.swept = g1 - P.lo;
                     b0 = g1;
                     if (o.flags & (REC_HOPS_LIMIT | REC_ARCS_LIMIT)) return;
                     if (zhit && opt != OPT_SH) done = true;
+                    __syncthreads();
                     load_batch(a, P, b0, t, u, v, tnext);
                     continue;
                 }
@@ -1580,13 +1749,12 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
     (void)a_arg;
     TabLds &tab = *reinterpret_cast<TabLds *>(lds_raw);
     for (int i = l; i < kFwN; i += kWave) { tab.r.tb_key[i] = 0; }
-    u32 serial, agstamp;
+    u32 serial;
     int64_t np;
     {
         KArgs &a = launch_args();
         const u32 *hdr = a.sl.hdr + slab * 4;
         serial = hdr[0];
-        agstamp = hdr[1];
         np = a.npairs_dev ? *a.npairs_dev : a.npairs;
     }
     u32 stamp = 1;  // reverse table stamps (0 = empty)
@@ -1664,7 +1832,7 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
             }
             __syncthreads();
             const u64 c0 = wall_clock64();
-            forward<SINGLE ? (RTB ? FWD_RTB : FWD_DIST) : FWD_PAIR, GBM>(a, P, S, bm, H, tab.f, agstamp, fo);
+            forward<SINGLE ? (RTB ? FWD_RTB : FWD_DIST) : FWD_PAIR, GBM>(a, P, S, bm, H, tab.f, fo);
             fwd_ticks += wall_clock64() - c0;
             __syncthreads();
             if (MODE == MODE_DISTANCES)
@@ -1809,16 +1977,14 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
     if (l == 0) {
         u32 *hdr = a.sl.hdr + slab * 4;
         hdr[0] = serial;
-        hdr[1] = agstamp;
         // load balance of the persistent grid: busy time of this slab, the
         // last finish and the first start (constant-rate wall clock)
         const u64 t_end = wall_clock64();
         atomicAdd((unsigned long long *)&a.stats[9], (unsigned long long)(t_end - t_begin));
         atomicMax((unsigned long long *)&a.stats[10], (unsigned long long)t_end);
         atomicMax((unsigned long long *)&a.stats[11], (unsigned long long)~t_begin);
-        // the slab's pair serial and tick stamp, for the host's wrap guard
+        // the slab's pair serial, for the host's wrap guard
         atomicMax((unsigned long long *)&a.stats[12], (unsigned long long)serial);
-        atomicMax((unsigned long long *)&a.stats[13], (unsigned long long)agstamp);
         atomicAdd((unsigned long long *)&a.stats[16], (unsigned long long)fwd_ticks);
         atomicAdd((unsigned long long *)&a.stats[17], (unsigned long long)rev_ticks);
     }

@@ -91,6 +91,15 @@ def test_tiny_workload(tiny_workload, opt):
 
 
 @pytest.mark.parametrize("opt", OPTS)
+def test_two_row_ticks(lib, opt):
+    """Ticks of 57..168 edges: one row, two rows (in registers), longer."""
+    for n, m, T, seed in ((12, 1000, 10, 61), (30, 1300, 10, 64), (20, 1800, 12, 65)):
+        gg, og = both(lib, uniform_graph(n, m, T, seed=seed))
+        check(gg, og, opt, 60, seed, ctx="rows%d" % seed)
+        check(gg, og, opt, 60, seed, t0=2, t1=T - 2, ctx="rows-win%d" % seed)
+
+
+@pytest.mark.parametrize("opt", OPTS)
 def test_long_ticks_and_star(lib, opt):
     """Ticks far longer than a batch (the global-scratch tick) and a head
     with 600 in-edges at one time."""

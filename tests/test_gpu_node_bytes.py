@@ -83,6 +83,22 @@ def test_padded_long_ticks_and_hubs(lib, opt):
         gg.set_launch(hub_nodes=0)
 
 
+@pytest.mark.parametrize("opt", OPTS)
+def test_padded_two_row_ticks(lib, opt):
+    """Ticks of 57..168 edges (one row, two rows in registers, longer)."""
+    from synthgen import uniform_graph
+    for n, m, T, seed in ((12, 1000, 10, 61), (20, 1800, 12, 65)):
+        U = uniform_graph(n, m, T, seed=seed)
+        G, gg, og = padded(lib, U.src, U.dst, U.t)
+        S, Z = oracle.draw_pairs(seed, 0, n, 0, 120)
+        compare_pairs(gg, og, opt, S, Z, ctx="pad-rows%d" % seed)
+        gg.set_launch(hub_nodes=8)
+        try:
+            compare_pairs(gg, og, opt, S, Z, ctx="pad-rows-hub%d" % seed)
+        finally:
+            gg.set_launch(hub_nodes=0)
+
+
 def test_padded_trk_walks(lib):
     from oracle import trk
     for seed in range(6):

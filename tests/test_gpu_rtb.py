@@ -85,6 +85,16 @@ def test_tiny_workload_sources(tiny_workload, opt):
 
 
 @pytest.mark.parametrize("opt", OPTS)
+def test_two_row_ticks(lib, opt):
+    """Ticks of 57..168 edges: one row, two rows (in registers), longer."""
+    for n, m, T, seed in ((12, 1000, 10, 61), (30, 1300, 10, 64), (20, 1800, 12, 65)):
+        gg, og = both(lib, uniform_graph(n, m, T, seed=seed))
+        compare_sources(gg, og, opt, np.arange(0, n, 3), ctx="rows%d" % seed)
+        gg.set_launch(hub_nodes=8)
+        compare_sources(gg, og, opt, np.arange(1, n, 4), ctx="rows-hub%d" % seed)
+
+
+@pytest.mark.parametrize("opt", OPTS)
 def test_long_ticks_and_hubs(lib, opt):
     G = uniform_graph(80, 4000, 6, seed=77)
     gg, og = both(lib, G)

@@ -78,6 +78,15 @@ def test_tiny_workload_walks(tiny_workload, opt):
 
 
 @pytest.mark.parametrize("opt", OPTS)
+def test_two_row_ticks(lib, opt):
+    """Ticks of 57..168 edges: one row, two rows (in registers), longer."""
+    for n, m, T, seed in ((12, 1000, 10, 61), (30, 1300, 10, 64), (20, 1800, 12, 65)):
+        gg, og = both(lib, uniform_graph(n, m, T, seed=seed))
+        S, Z = oracle.draw_pairs(seed, 0, n, 0, 80)
+        compare_walks(gg, og, opt, S, Z, seed, ctx="rows%d" % seed)
+
+
+@pytest.mark.parametrize("opt", OPTS)
 def test_long_ticks_star_and_hubs(lib, opt):
     G = uniform_graph(80, 4000, 6, seed=77)
     gg, og = both(lib, G)
