@@ -801,6 +801,14 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
     o.t_arr = -1;
     int32_t t, u, v, tnext;
     load_batch(a, P, b0, t, u, v, tnext);
+    // Node bytes (GBM): the reached bytes of a batch's tails and heads are
+    // loaded during the batch before it, ahead of that batch's commits (pref),
+    // and the nodes those commits reached first are patched in from
+    // registers (pu, pv): the reached test of a batch then waits for no load.
+    // (One wave's memory operations are performed in order, so bytes stored
+    // by earlier batches are seen.)
+    u32 bu = 0, bv = 0;
+    bool pref = false, pu = false, pv = false;
     while (b0 < P.hi && !done) {
         // ---- batch: up to 64 edges, whole ticks
         const int64_t avail = P.hi - b0;
@@ -828,6 +836,7 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
                         g1 = wave_upper_bound(a.g.T, b0 + 2 * kWave, lim, tlast);
                     }
                     __syncthreads();
+                    pref = false;  // the bytes of the batch after the tick are loaded there
                     if (g1 - b0 <= 2 * kWave) fwd_tick2<FM, GBM>(a, P, S, bm, H, b0, g1, tlast, ur, vr, o, zh, zS, zhit);
                     else fwd_long_tick<FM, GBM>(a, P, S, bm, H, b0, g1, tlast, o, zh, zS, zhit);
                     o.swept = g1 - P.lo;
@@ -862,9 +871,25 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
         // pfm: a node's state is final at its first arrival, so an edge
         // whose head was reached before the batch can neither commit nor lie
         // on an optimal walk (its whole run is dead); its tail needs no load.
-        const bool dead = opt == OPT_PFM && in && rch_test<GBM>(bm, v);
-        const bool rt = in && !dead && rch_test<GBM>(bm, u);
-        const bool hr = rs && rch_test<GBM>(bm, v);
+        bool ru, rv;
+        if (GBM) {
+            const unsigned char *B = reinterpret_cast<const unsigned char *>(bm);
+            if (!pref) {
+                // loaded now: complete, no patch
+                bu = in ? (u32)B[u] : 0u;
+                bv = in ? (u32)B[v] : 0u;
+                pu = false; pv = false;
+            }
+            ru = (bu & 1u) || pu;
+            rv = (bv & 1u) || pv;
+        } else {
+            ru = in && rch_test<GBM>(bm, u);
+            rv = in && rch_test<GBM>(bm, v);
+        }
+        pref = false;
+        const bool dead = opt == OPT_PFM && in && rv;
+        const bool rt = in && !dead && ru;
+        const bool hr = rs && rv;
         u64 thu = 0, thv = 0, su = 0, sv = 0;
         u32 lhu = 0, lhv = 0;
         u64 lsu = 0, lsv = 0;
@@ -873,6 +898,14 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
         load_batch(a, P, b0 + nbat, t2, u2, v2, tn2);
         // no tail reached at batch start: no tick of the batch can commit
         if (!ballot(rt)) {
+            if (GBM) {
+                // nothing is committed: the next batch's bytes need no patch
+                const unsigned char *B = reinterpret_cast<const unsigned char *>(bm);
+                bu = v2 >= 0 ? (u32)B[u2] : 0u;
+                bv = v2 >= 0 ? (u32)B[v2] : 0u;
+                pu = false; pv = false;
+                pref = true;
+            }
             b0 += nbat;
             o.swept = b0 - P.lo;
             t = t2; u = u2; v = v2; tnext = tn2;
@@ -932,6 +965,14 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
                 }
             }
         }
+        // the next batch's reached bytes, in flight while this one commits
+        u32 bu2 = 0, bv2 = 0;
+        if (GBM) {
+            const unsigned char *B = reinterpret_cast<const unsigned char *>(bm);
+            bu2 = v2 >= 0 ? (u32)B[u2] : 0u;
+            bv2 = v2 >= 0 ? (u32)B[v2] : 0u;
+        }
+        bool nw = false;  // my run head was reached first in this batch
         // tick of the latest lane I depend on (-1: none)
         const int dj = pred > hpred ? pred : hpred;
         const int dtk = dj >= 0 ? __popcll(gm & ((2ull << dj) - 1ull)) - 1 : -1;
@@ -1018,6 +1059,7 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
             }
             const bool keep = tid < cut;
             ok = ok && keep;
+            nw = nw || (ok && cur_h == kHInf);
             if (ok) {
                 if (v < H.K) { H.h[v] = nh2; H.s[v] = nS; }
                 else {
@@ -1070,6 +1112,21 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
             ta = tb;
         }
         if (!done) o.swept = (b0 + nbat) - P.lo;
+        if (GBM && !done) {
+            // the next batch's bytes were loaded before this batch's commits:
+            // the nodes it reached first
+            u64 mn = ballot(nw);
+            pu = false; pv = false;
+            while (mn) {
+                const int j = __ffsll((long long)mn) - 1;
+                mn &= mn - 1;
+                const int32_t w = rl32(v, j);
+                pu = pu || u2 == w;
+                pv = pv || v2 == w;
+            }
+            bu = bu2; bv = bv2;
+            pref = true;
+        }
         __syncthreads();
         b0 += nbat;
         t = t2; u = u2; v = v2; tnext = tn2;

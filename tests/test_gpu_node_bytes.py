@@ -87,7 +87,7 @@ def test_padded_long_ticks_and_hubs(lib, opt):
 def test_padded_two_row_ticks(lib, opt):
     """Ticks of 57..168 edges (one row, two rows in registers, longer)."""
     from synthgen import uniform_graph
-    for n, m, T, seed in ((12, 1000, 10, 61), (20, 1800, 12, 65)):
+    for n, m, T, seed in ((12, 1000, 10, 61), (40, 700, 10, 62), (20, 1800, 12, 65), (60, 900, 16, 66)):
         U = uniform_graph(n, m, T, seed=seed)
         G, gg, og = padded(lib, U.src, U.dst, U.t)
         S, Z = oracle.draw_pairs(seed, 0, n, 0, 120)
