@@ -522,13 +522,20 @@ __device__ void fwd_tick2(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const
         if (l == kWave - 1) vn = r + 1 < R ? rl32(vr[r + 1 < R ? r + 1 : r], 0) : -1;
         rs[r] = act && vr[r] != vp;
         re[r] = act && vr[r] != vn;
-        const bool dead = opt == OPT_PFM && act && rch_test<GBM>(bm, vr[r]);
-        rt[r] = act && !dead && rch_test<GBM>(bm, ur[r]);
-        hr[r] = re[r] && !dead && rch_test<GBM>(bm, vr[r]);
-        any |= ballot(rt[r]);
+        if (GBM) {
+            // node bytes: no byte loads here; every lane loads its nodes'
+            // state words, whose pair tag (or, for hubs, hops kHInf: cleared
+            // at the pair's start) decides whether the node was reached
+            rt[r] = act;
+            hr[r] = re[r];
+        } else {
+            const bool dead = opt == OPT_PFM && act && rch_test<GBM>(bm, vr[r]);
+            rt[r] = act && !dead && rch_test<GBM>(bm, ur[r]);
+            hr[r] = re[r] && !dead && rch_test<GBM>(bm, vr[r]);
+            any |= ballot(rt[r]);
+        }
     }
-    if (!any) { o.dead += 1; return; }
-    o.live += 1;
+    if (!GBM && !any) { o.dead += 1; return; }
     // the state before the tick: every lane loads (see the batch path), both
     // rows at once, then each word is decoded
     u64 thu[R], tsu[R], thv[R], tsv[R];
@@ -560,6 +567,8 @@ __device__ void fwd_tick2(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const
         o.flags |= REC_HOPS_LIMIT;
         return;
     }
+    if (GBM && !ballot(hu[0] != kHInf || hu[1] != kHInf)) { o.dead += 1; return; }
+    o.live += 1;
     // per run: the candidate over its tails, then its head's decision; every
     // read of the tick is done, so a run's commit follows at once
     u32 mine[R];   // at run ends: d | commit << 31
@@ -1871,13 +1880,15 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
         if (ok) {
             P.lo = wave_lower_bound(a.g.T, P.elo, P.ehi, dep);
             P.hi = wave_upper_bound(a.g.T, P.lo, P.ehi, lin);
-            // reset the reached set, seed the origin
+            // reset the reached set and the hub hops (unreached: kHInf), seed
+            // the origin
             if (GBM) {
                 uint4 *w4 = reinterpret_cast<uint4 *>(bm);
                 for (int64_t w = l; w < bmw; w += kWave) w4[w] = make_uint4(0u, 0u, 0u, 0u);
             } else {
                 for (int64_t w = l; w < bmw; w += kWave) bm[w] = 0;
             }
+            for (int i = l; i < H.K; i += kWave) H.h[i] = kHInf;
             __syncthreads();
             if (l == 0) {
                 if (P.s < H.K) { H.h[P.s] = 0u; H.s[P.s] = 1ull; }
