@@ -57,10 +57,9 @@ HBM_PEAK_GBS = 8000.0
 SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip")
 
 # Launch configuration of the headline step: 2,048 hub nodes' state in LDS,
-# the grid the device keeps resident with that LDS (1,536 single-wave
+# the grid the device keeps resident with that LDS (1,280 single-wave
 # workgroups), the rest automatic.  Taken from a sweep of grids and hub
-# counts on this graph (the design notes give it); the autotuner itself
-# would take minutes here.
+# counts on this graph; the autotuner itself would take minutes here.
 HEADLINE_LAUNCH = {"n_slabs": 0, "hub_nodes": 2048}
 
 # DRAM traffic of the sweep kernel (rocprofv3 --pmc FETCH_SIZE, then
@@ -141,7 +140,7 @@ def timed_steps(gg, torch, opt, r, steps, warmup, seed, c=C):
     return tot, wall, bal / max(tot["sweep_ms"], 1e-9)
 
 
-def roofline(tot, workload, slabs, kernel="mantra::k_sweep<0>"):
+def roofline(tot, workload, slabs, kernel):
     kern_ms = tot["sweep_ms"] / max(1, tot["launches"])
     abytes = algorithmic_bytes(tot, C) / max(1, tot["launches"])
     achieved = abytes / (kern_ms / 1e3) / 1e9
@@ -429,14 +428,19 @@ def mid_sections(args, pk, torch):
     G = workload(MID)
     gg = pk.Graph.of(G)
     log("%s resident" % MID)
-    tuned = gg.autotune(OPT, sample_pairs=MID_R, seed=args.seed + 7)
+    if args.mid_slabs > 0:
+        # a fixed grid (profiling runs): no autotuner launches in the profile
+        gg.set_launch(n_slabs=args.mid_slabs, hub_nodes=0)
+        tuned = gg.get_launch()
+    else:
+        tuned = gg.autotune(OPT, sample_pairs=MID_R, seed=args.seed + 7)
     tot, wall, bal = timed_steps(gg, torch, OPT, MID_R, max(3, args.steps // 4), 1, args.seed)
     steps = max(3, args.steps // 4)
     out = {"workload": MID, "n": G.n, "edges": G.m, "optimality": OPT, "pairs_per_step": MID_R, "c": C,
            "steps": steps, "pairs_per_s": MID_R * steps / wall, "ms_per_step": wall * 1e3 / steps,
            "temporal_edges_per_s": tot["window_edges"] / wall, "mean_window_edges": tot["window_edges"] / (MID_R * steps),
            "mean_arcs": tot["arcs"] / (MID_R * steps), "grid_balance": bal, "launch": tuned,
-           "roofline": roofline(tot, MID, tuned["n_slabs"])}
+           "roofline": roofline(tot, MID, tuned["n_slabs"], "mantra::k_sweep<0, false> (LDS bitmap)")}
     log("mid: %s" % json.dumps(out))
     if not args.no_forms:
         out["forms"] = forms(gg, torch, args.seed, tuned)
@@ -558,6 +562,8 @@ def main():
                     help="only the batching workloads (n = 10^6 Algorithm 1, packed-256; prints {\"batching\": ...})")
     ap.add_argument("--slabs", type=int, default=0,
                     help="fixed number of persistent workgroups for the headline step (profiling runs)")
+    ap.add_argument("--mid-slabs", type=int, default=0,
+                    help="fixed grid for the mid-size step instead of the autotuner's (profiling runs)")
     ap.add_argument("--seed", type=int, default=2005)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -617,7 +623,7 @@ def main():
         "launches_per_step": tot["launches"] / args.steps,
         "grid_balance": bal,
         "launch": tuned,
-        "roofline": roofline(tot, WORKLOAD, tuned["n_slabs"]),
+        "roofline": roofline(tot, WORKLOAD, tuned["n_slabs"], "mantra::k_sweep<0, true> (node bytes)"),
     }
     log("headline: %s" % json.dumps(out))
     og = one = None
