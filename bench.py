@@ -623,7 +623,7 @@ def main():
         "launches_per_step": tot["launches"] / args.steps,
         "grid_balance": bal,
         "launch": tuned,
-        "roofline": roofline(tot, WORKLOAD, tuned["n_slabs"], "mantra::k_sweep<0, true> (node bytes)"),
+        "roofline": roofline(tot, WORKLOAD, tuned["n_slabs"], "mantra::k_sweep<0, true> (reached set in global memory)"),
     }
     log("headline: %s" % json.dumps(out))
     og = one = None

@@ -106,7 +106,7 @@ struct DevSlabs {
     int64_t xwords, xmax;
     u64 *XS;          // [ns][gmax][2]  long ticks: each edge's tail state
     u64 *T;           // [ns][nmax][2]  RTB sources: first arrival of each reached node (allocated for them)
-    unsigned char *BM;// [ns][nmax rounded up to 16] reached / alive node bytes (graphs whose bitmap is not in LDS)
+    unsigned char *BM;// [ns][nmax bits, in 16-byte words] reached / alive set (graphs whose bitmap is not in LDS)
     u32 *hdr;         // [ns][4]        pair serial
     int64_t nmax, cap, gmax;
 };
@@ -116,7 +116,7 @@ struct LaunchArgs {
     DevSlabs sl;
     const DevReq *reqs;
     int32_t nreq;
-    int32_t lds_bitmap;      // 1: reached bitmap of nmax bits in LDS; 0: reached node bytes in the slabs' BM
+    int32_t lds_bitmap;      // 1: reached bitmap of nmax bits in LDS; 0: in the slabs' BM (global memory)
     int32_t hub_nodes;       // forward state of nodes < hub_nodes lives in LDS
     int64_t npairs;              // launch slots (grid sizes); the pairs are slots qbase..np-1
     const int64_t *npairs_dev;   // np read from device memory (graph replays), or null: np = npairs

@@ -247,13 +247,11 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
 
 // ------------------------------------------------------------------ slabs
 
-// A reached-bitmap in LDS lets a batch skip the state loads of unreached
-// tails; beyond 8 KB it costs more occupancy than it saves, and the reached
-// set is a byte per node in the slab's global memory instead.
-// the pair's reached set: a bitmap in LDS up to 65,536 nodes, else one byte
-// per node in the slab (global memory)
+// A reached-set bitmap in LDS lets a batch skip the state loads of unreached
+// tails; beyond 8 KB it costs more occupancy than it saves, and the bitmap
+// is in the slab's global memory instead (in 16-byte words).
 int lds_bitmap_ok(int64_t nmax) { return ((nmax + 31) / 32) * 4 <= 8 * 1024; }
-size_t node_bytes_per_slab(int64_t nmax) { return lds_bitmap_ok(nmax) ? 0 : (size_t)((nmax + 15) / 16) * 16; }
+size_t node_bytes_per_slab(int64_t nmax) { return lds_bitmap_ok(nmax) ? 0 : (size_t)((nmax + 127) / 128) * 16; }
 // forward state of the top hub nodes in LDS
 static int hub_nodes(const mantra_graph *g) { return (int)std::min<int64_t>(g->hub_nodes, g->nmax); }
 size_t lds_bytes(const mantra_graph *g) {
@@ -265,9 +263,9 @@ size_t lds_bytes(const mantra_graph *g) {
 }
 
 // device bytes of one slab's per-node state (F: 16 B, shared by the forward
-// and the reverse; N: 8 B; touched: 4 B; the reached byte where the bitmap
-// is not in LDS) and of its per-tick scratch (XS and AG: 16 B each per edge
-// of the longest tick)
+// and the reverse; N: 8 B; touched: 4 B; the reached set's bit where the
+// bitmap is not in LDS) and of its per-tick scratch (XS and AG: 16 B each per
+// edge of the longest tick)
 static size_t slab_state_bytes(const mantra_graph *g) {
     return (size_t)g->nmax * 28 + node_bytes_per_slab(g->nmax) + (size_t)g->gmax * 32 + 16;
 }

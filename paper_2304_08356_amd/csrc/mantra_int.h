@@ -69,7 +69,7 @@ struct SlabPool {
     int64_t nmax = 0, cap = 0, gmax = 0;
     u64 *F = nullptr, *N = nullptr, *AG = nullptr, *arcs = nullptr, *XS = nullptr;
     u64 *T = nullptr;  // RTB launches only: first arrivals, [nslabs][nmax][2]
-    unsigned char *BM = nullptr;  // reached node bytes (graphs whose bitmap is not in LDS)
+    unsigned char *BM = nullptr;  // reached-set bitmaps (graphs whose bitmap is not in LDS)
     u32 *hdr = nullptr;
     int32_t *touched = nullptr;
     // shared arc chunks for pairs whose arcs pass the slab's own buffer
@@ -232,8 +232,8 @@ int reduce_blocks(int64_t n);
 int reduce_part_ensure(mantra_graph *g, int c);
 // persistent workgroups of a launch on this graph
 int auto_slabs(const mantra_graph *g);
-// the reached set of a pair: an LDS bitmap (graphs of up to 65,536 nodes),
-// else node bytes in the slab; bytes of those per slab (0 with the bitmap)
+// the reached set of a pair: a bitmap in LDS (graphs of up to 65,536 nodes),
+// else in the slab's global memory; bytes of that per slab (0 with LDS)
 int lds_bitmap_ok(int64_t nmax);
 size_t node_bytes_per_slab(int64_t nmax);
 // dynamic LDS of a sweep workgroup on this graph (its hub setting included)

@@ -353,21 +353,27 @@ __device__ void chunks_free(KArgs &a, const Slab &S, int32_t nch) {
     }
 }
 
-// The pair's reached set (forward) and alive set (reverse).  On graphs of
-// up to 65,536 nodes it is a bitmap in LDS (bit v, LDS atomics).  Larger
-// graphs keep one byte per node in the slab's global memory instead (GBM):
-// bit 0 = reached in the forward, bit 1 = alive in the reverse, written with
-// plain byte stores (a node's byte is written only by the lane that commits
-// the node, and a wave sees its own stores after the batch barrier, as it
-// does for the node state); the map is cleared at the start of each pair.
+// The pair's reached set (forward), then its alive set (reverse): a bitmap
+// of the nodes, bit v of word v / 32.  On graphs of up to 65,536 nodes it is
+// in LDS.  Larger graphs keep it in the slab's global memory (GBM), set with
+// atomic ORs (performed in L2) and read with loads that bypass L1 (so a
+// line L1 holds can never hide a bit the wave set); a wave's memory
+// operations are performed in order, so it sees its own bits.  At 2*10^6
+// nodes the map is 256 KB per slab, and the words of the nodes most windows
+// touch stay in L2.  Cleared at the start of each pair and before each
+// reverse sweep.
+template <bool GBM>
+__device__ __forceinline__ u32 bm_word(const u32 *bm, int32_t v) {
+    if (GBM) return ld_agent32(&bm[v >> 5]);
+    return bm[v >> 5];
+}
 template <bool GBM>
 __device__ __forceinline__ bool rch_test(const u32 *bm, int32_t v) {
-    if (GBM) return reinterpret_cast<const unsigned char *>(bm)[v] & 1u;
-    return (bm[v >> 5] >> (v & 31)) & 1u;
+    return (bm_word<GBM>(bm, v) >> (v & 31)) & 1u;
 }
 template <bool GBM>
 __device__ __forceinline__ void rch_set(u32 *bm, int32_t v) {
-    if (GBM) reinterpret_cast<unsigned char *>(bm)[v] = 1u;
+    if (GBM) __hip_atomic_fetch_or(&bm[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else atomicOr(&bm[v >> 5], 1u << (v & 31));
 }
 
@@ -523,9 +529,10 @@ __device__ void fwd_tick2(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const
         rs[r] = act && vr[r] != vp;
         re[r] = act && vr[r] != vn;
         if (GBM) {
-            // node bytes: no byte loads here; every lane loads its nodes'
-            // state words, whose pair tag (or, for hubs, hops kHInf: cleared
-            // at the pair's start) decides whether the node was reached
+            // reached set in global memory: no bitmap loads here; every lane
+            // loads its nodes' state words, whose pair tag (or, for hubs,
+            // hops kHInf: cleared at the pair's start) decides whether the
+            // node was reached
             rt[r] = act;
             hr[r] = re[r];
         } else {
@@ -810,12 +817,12 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
     o.t_arr = -1;
     int32_t t, u, v, tnext;
     load_batch(a, P, b0, t, u, v, tnext);
-    // Node bytes (GBM): the reached bytes of a batch's tails and heads are
-    // loaded during the batch before it, ahead of that batch's commits (pref),
-    // and the nodes those commits reached first are patched in from
-    // registers (pu, pv): the reached test of a batch then waits for no load.
-    // (One wave's memory operations are performed in order, so bytes stored
-    // by earlier batches are seen.)
+    // Reached set in global memory (GBM): the bitmap words of a batch's tails
+    // and heads are loaded during the batch before it, ahead of that batch's
+    // commits (pref), and the nodes those commits reached first are patched
+    // in from registers (pu, pv): the reached test of a batch then waits for
+    // no load.  (One wave's memory operations are performed in order, so bits
+    // set by earlier batches are seen.)
     u32 bu = 0, bv = 0;
     bool pref = false, pu = false, pv = false;
     while (b0 < P.hi && !done) {
@@ -845,7 +852,7 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
                         g1 = wave_upper_bound(a.g.T, b0 + 2 * kWave, lim, tlast);
                     }
                     __syncthreads();
-                    pref = false;  // the bytes of the batch after the tick are loaded there
+                    pref = false;  // the batch after the tick loads its own words
                     if (g1 - b0 <= 2 * kWave) fwd_tick2<FM, GBM>(a, P, S, bm, H, b0, g1, tlast, ur, vr, o, zh, zS, zhit);
                     else fwd_long_tick<FM, GBM>(a, P, S, bm, H, b0, g1, tlast, o, zh, zS, zhit);
                     o.swept = g1 - P.lo;
@@ -882,15 +889,14 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
         // on an optimal walk (its whole run is dead); its tail needs no load.
         bool ru, rv;
         if (GBM) {
-            const unsigned char *B = reinterpret_cast<const unsigned char *>(bm);
             if (!pref) {
                 // loaded now: complete, no patch
-                bu = in ? (u32)B[u] : 0u;
-                bv = in ? (u32)B[v] : 0u;
+                bu = in ? bm_word<GBM>(bm, u) : 0u;
+                bv = in ? bm_word<GBM>(bm, v) : 0u;
                 pu = false; pv = false;
             }
-            ru = (bu & 1u) || pu;
-            rv = (bv & 1u) || pv;
+            ru = ((bu >> (u & 31)) & 1u) || pu;
+            rv = ((bv >> (v & 31)) & 1u) || pv;
         } else {
             ru = in && rch_test<GBM>(bm, u);
             rv = in && rch_test<GBM>(bm, v);
@@ -908,10 +914,9 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
         // no tail reached at batch start: no tick of the batch can commit
         if (!ballot(rt)) {
             if (GBM) {
-                // nothing is committed: the next batch's bytes need no patch
-                const unsigned char *B = reinterpret_cast<const unsigned char *>(bm);
-                bu = v2 >= 0 ? (u32)B[u2] : 0u;
-                bv = v2 >= 0 ? (u32)B[v2] : 0u;
+                // nothing is committed: the next batch's words need no patch
+                bu = v2 >= 0 ? bm_word<GBM>(bm, u2) : 0u;
+                bv = v2 >= 0 ? bm_word<GBM>(bm, v2) : 0u;
                 pu = false; pv = false;
                 pref = true;
             }
@@ -974,12 +979,11 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
                 }
             }
         }
-        // the next batch's reached bytes, in flight while this one commits
+        // the next batch's reached-set words, in flight while this one commits
         u32 bu2 = 0, bv2 = 0;
         if (GBM) {
-            const unsigned char *B = reinterpret_cast<const unsigned char *>(bm);
-            bu2 = v2 >= 0 ? (u32)B[u2] : 0u;
-            bv2 = v2 >= 0 ? (u32)B[v2] : 0u;
+            bu2 = v2 >= 0 ? bm_word<GBM>(bm, u2) : 0u;
+            bv2 = v2 >= 0 ? bm_word<GBM>(bm, v2) : 0u;
         }
         bool nw = false;  // my run head was reached first in this batch
         // tick of the latest lane I depend on (-1: none)
@@ -1122,7 +1126,7 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
         }
         if (!done) o.swept = (b0 + nbat) - P.lo;
         if (GBM && !done) {
-            // the next batch's bytes were loaded before this batch's commits:
+            // the next batch's words were loaded before this batch's commits:
             // the nodes it reached first
             u64 mn = ballot(nw);
             pu = false; pv = false;
@@ -1164,18 +1168,11 @@ struct RevCtx {
 };
 
 // alive set: nodes with a non-zero dependency accumulator for this pair
-// (the LDS bitmap, emptied before the reverse; or bit 1 of the node bytes,
-// clear since the pair started)
+// (the reached set's bitmap, emptied before the reverse)
 template <bool GBM>
-__device__ __forceinline__ bool alive_test(const u32 *bm, int32_t v) {
-    if (GBM) return reinterpret_cast<const unsigned char *>(bm)[v] & 2u;
-    return (bm[v >> 5] >> (v & 31)) & 1u;
-}
+__device__ __forceinline__ bool alive_test(const u32 *bm, int32_t v) { return rch_test<GBM>(bm, v); }
 template <bool GBM>
-__device__ __forceinline__ void alive_set(u32 *bm, int32_t v) {
-    if (GBM) reinterpret_cast<unsigned char *>(bm)[v] = 2u;
-    else atomicOr(&bm[v >> 5], 1u << (v & 31));
-}
+__device__ __forceinline__ void alive_set(u32 *bm, int32_t v) { rch_set<GBM>(bm, v); }
 
 __device__ __forceinline__ void rev_contrib(KArgs &a, const Pair &P, const Slab &S,
                                             RevCtx &X, bool act, u64 B, u64 tc, int32_t v, u32 k) {
@@ -1283,9 +1280,13 @@ __device__ void reverse(KArgs &a, const Pair &P, const Slab &S, u32 *bm, int64_t
                         u32 &stamp, int64_t narcs, RevCtx &X) {
     u64 *const Rp = S.R();
     const int l = lane_id();
-    // the alive set starts empty (the node bytes' bit 1 already is)
-    if (!GBM)
+    // the alive set starts empty
+    if (GBM) {
+        uint4 *w4 = reinterpret_cast<uint4 *>(bm);
+        for (int64_t w = l; w < bmw; w += kWave) w4[w] = make_uint4(0u, 0u, 0u, 0u);
+    } else {
         for (int64_t w = l; w < bmw; w += kWave) bm[w] = 0;
+    }
     __syncthreads();
     int64_t ac = narcs;
     while (ac > 0) {
@@ -1802,8 +1803,8 @@ __device__ __forceinline__ Slab slab_of(int64_t slab, u32 *xtl) {
     return S;
 }
 
-// GBM: the reached set in the slab's node bytes (graphs of more than 65,536
-// nodes) instead of an LDS bitmap
+// GBM: the reached set in a bitmap in the slab's global memory (graphs of
+// more than 65,536 nodes) instead of in LDS
 template <int MODE, bool GBM>
 __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg) {
     constexpr bool RTB = MODE == MODE_RTB;
@@ -1830,8 +1831,8 @@ __global__ void __launch_bounds__(64, MANTRA_SWEEP_WPS) k_sweep(LaunchArgs a_arg
     for (;;) {
         KArgs &a = launch_args();
         const Slab S = slab_of(slab, reinterpret_cast<u32 *>(lds_raw + sizeof(TabLds)));
-        // LDS bitmap words, or the 16-byte words of the node bytes
-        const int64_t bmw = GBM ? (a.sl.nmax + 15) / 16 : (a.sl.nmax + 31) / 32;
+        // LDS bitmap words, or the 16-byte words of the bitmap in global memory
+        const int64_t bmw = GBM ? (a.sl.nmax + 127) / 128 : (a.sl.nmax + 31) / 32;
         constexpr size_t kHead = sizeof(TabLds) + sizeof(u32) * kXtLds;  // tables, chunk table
         u32 *bm = GBM ? reinterpret_cast<u32 *>(a.sl.BM + slab * bmw * 16)
                       : reinterpret_cast<u32 *>(lds_raw + kHead);
@@ -2637,7 +2638,7 @@ hipError_t mantra_launch_clear(mantra::u32 *work, mantra::u32 *retry, mantra::u3
 // the forward and reverse sweeps, and the chunk table's first entries
 size_t mantra_tab_lds_bytes(void) { return sizeof(mantra::TabLds) + sizeof(mantra::u32) * mantra::kXtLds; }
 // resident sweep workgroups per CU for a given dynamic LDS size (gbm: the
-// instance with the reached set in global node bytes)
+// instance with the reached set in global memory)
 int mantra_sweep_occupancy(size_t lds_bytes, int gbm) {
     int nb = 0;
     const hipError_t e =
