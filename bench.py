@@ -66,8 +66,16 @@ HEADLINE_LAUNCH = {"n_slabs": 0, "hub_nodes": 2048}
 # WRITE_SIZE, summed over the k_sweep dispatches of the profiled run, divided
 # by their count, and scaled by the ratio of bytes to counter bytes that the
 # same counters give for a plain copy of known size), per workload, valid for
-# the kernel source with the given SHA-256 at the given grid only.
-TRAFFIC = {}
+# the kernel source with the given SHA-256 at the given grid and hub count
+# only.
+TRAFFIC = {
+    "serve-chunglu-n2m": {"slabs": 1280, "hub_nodes": 2048,
+                          "sweep_sha256": "eb1b3110af77d001792238426aa9efaf25b73f767fd5394216d6e61f4bda998c",
+                          "fetch_bytes_per_launch": 1.1070e+13, "write_bytes_per_launch": 9.1544e+11},
+    "mid-chunglu-n50k": {"slabs": 2880, "hub_nodes": 0,
+                         "sweep_sha256": "eb1b3110af77d001792238426aa9efaf25b73f767fd5394216d6e61f4bda998c",
+                         "fetch_bytes_per_launch": 4.9425e+11, "write_bytes_per_launch": 7.8702e+10},
+}
 
 
 def sha256(path):
@@ -111,9 +119,10 @@ def hbm_frac(t, c):
     return algorithmic_bytes(t, c) / (t["sweep_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
 
 
-def traffic_of(workload, slabs):
+def traffic_of(workload, launch):
     tr = TRAFFIC.get(workload)
-    if not tr or tr["sweep_sha256"] != sha256(SWEEP_SRC) or tr["slabs"] != slabs:
+    if (not tr or tr["sweep_sha256"] != sha256(SWEEP_SRC) or tr["slabs"] != launch["n_slabs"]
+            or tr["hub_nodes"] != launch["hub_nodes"]):
         return None
     return tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
 
@@ -140,11 +149,11 @@ def timed_steps(gg, torch, opt, r, steps, warmup, seed, c=C):
     return tot, wall, bal / max(tot["sweep_ms"], 1e-9)
 
 
-def roofline(tot, workload, slabs, kernel):
+def roofline(tot, workload, launch, kernel):
     kern_ms = tot["sweep_ms"] / max(1, tot["launches"])
     abytes = algorithmic_bytes(tot, C) / max(1, tot["launches"])
     achieved = abytes / (kern_ms / 1e3) / 1e9
-    traffic = traffic_of(workload, slabs)
+    traffic = traffic_of(workload, launch)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
             "algorithmic_bytes_per_launch": abytes, "sweep_ms_per_launch": kern_ms,
@@ -440,7 +449,7 @@ def mid_sections(args, pk, torch):
            "steps": steps, "pairs_per_s": MID_R * steps / wall, "ms_per_step": wall * 1e3 / steps,
            "temporal_edges_per_s": tot["window_edges"] / wall, "mean_window_edges": tot["window_edges"] / (MID_R * steps),
            "mean_arcs": tot["arcs"] / (MID_R * steps), "grid_balance": bal, "launch": tuned,
-           "roofline": roofline(tot, MID, tuned["n_slabs"], "mantra::k_sweep<0, false> (LDS bitmap)")}
+           "roofline": roofline(tot, MID, tuned, "mantra::k_sweep<0, false> (LDS bitmap)")}
     log("mid: %s" % json.dumps(out))
     if not args.no_forms:
         out["forms"] = forms(gg, torch, args.seed, tuned)
@@ -623,7 +632,7 @@ def main():
         "launches_per_step": tot["launches"] / args.steps,
         "grid_balance": bal,
         "launch": tuned,
-        "roofline": roofline(tot, WORKLOAD, tuned["n_slabs"], "mantra::k_sweep<0, true> (reached set in global memory)"),
+        "roofline": roofline(tot, WORKLOAD, tuned, "mantra::k_sweep<0, true> (reached set in global memory)"),
     }
     log("headline: %s" % json.dumps(out))
     og = one = None
