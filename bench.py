@@ -316,7 +316,7 @@ def trk_step(gg, torch, seed, r, steps=3):
     wall = time.perf_counter() - t0
     return {"steps": steps, "pairs_per_s": r * steps / wall, "ms_per_step": wall * 1e3 / steps,
             "sweep_ms_per_launch": tot["sweep_ms"] / max(1, tot["launches"]), "hbm_frac": hbm_frac(tot, C),
-            "kernel": "mantra::k_sweep<2>"}
+            "kernel": "mantra::k_sweep<2, false>"}
 
 
 def rtb_step(gg, torch, seed, r=0, steps=2):
@@ -341,7 +341,7 @@ def rtb_step(gg, torch, seed, r=0, steps=2):
     return {"steps": steps, "sources_per_step": r, "sources_per_s": r * steps / wall,
             "ms_per_step": wall * 1e3 / steps, "sweep_ms_per_launch": tot["sweep_ms"] / max(1, tot["launches"]),
             "temporal_edges_per_s": tot["window_edges"] / (tot["sweep_ms"] / 1e3),
-            "hbm_frac": hbm_frac(tot, C), "kernel": "mantra::k_sweep<3>"}
+            "hbm_frac": hbm_frac(tot, C), "kernel": "mantra::k_sweep<3, false>"}
 
 
 def distances(gg, torch, seed, r=256, og=None):
@@ -594,6 +594,8 @@ def main():
         t0 = time.perf_counter()
         G = workload(args.serve_workload)
         gg = pk.Graph.of(G)
+        if args.serve_workload == WORKLOAD:
+            gg.set_launch(**HEADLINE_LAUNCH)
         log("graph %s resident after %.1f s" % (args.serve_workload, time.perf_counter() - t0))
         print(json.dumps({"serve": serve(gg, G, torch, n_req=args.serve_requests, rate=args.serve_rate,
                                          seed=args.seed + 2000, workload_name=args.serve_workload)}), flush=True)

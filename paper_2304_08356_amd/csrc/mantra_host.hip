@@ -286,11 +286,26 @@ static size_t device_bytes(const mantra_graph *g) {
 // Arc records (32 B each).  Each slab has a buffer of its own (own_cap
 // arcs); a pair with more arcs takes chunks of kArcChunk arcs from a pool the
 // launch shares, so that the arc room follows the pairs in flight rather
-// than the largest pair times the grid.
+// than the largest pair times the grid.  The own buffer holds 2^18 arcs, or
+// up to 2^20 where the resident grid's slabs with it still fit half of the
+// pool's share of the device: pairs whose arcs run into the shared chunks
+// are slower (on the 50k graph, 2^18 arcs cost the step about 10% against
+// 6*10^5 or more, which only its longest pairs pass).
 static const size_t kChunkBytes = (size_t)kArcChunk * 32;
+static int resident_slabs(const mantra_graph *g);
+static size_t slab_state_bytes(const mantra_graph *g);
+static constexpr double kPoolShare = 0.75;
 static int64_t own_cap(const mantra_graph *g) {
     if (g->user_cap > 0) return std::min<int64_t>(g->user_cap, g->m + 1);
-    return std::min<int64_t>(g->m + 1, (int64_t)1 << 18);
+    int64_t cap = (int64_t)1 << 18;
+    const int64_t rs = resident_slabs(g);
+    const size_t half = (size_t)(kPoolShare * (double)device_bytes(g)) / 2;
+    const size_t st = slab_state_bytes(g);
+    if (rs > 0 && half / (size_t)rs > st) {
+        const int64_t fit = (int64_t)((half / (size_t)rs - st) / 33);
+        cap = std::max<int64_t>(cap, std::min<int64_t>(fit, (int64_t)1 << 20));
+    }
+    return std::min<int64_t>(g->m + 1, cap);
 }
 // chunk-table entries per slab: enough for a pair with an arc per edge
 static int64_t xmax_of(const mantra_graph *g, int64_t cap) {
@@ -305,7 +320,6 @@ static size_t pool_bytes(const mantra_graph *g, const SlabPool &p) {
 // 75% of the device, less when other graphs or callers already hold memory
 // (the graph's own pool counts as available).  The rest holds the graph,
 // the per-request sums of served requests and the re-run pools.
-static constexpr double kPoolShare = 0.75;
 static size_t pool_budget(const mantra_graph *g) {
     size_t fr, tot;
     device_mem(g, &fr, &tot);
