@@ -66,13 +66,13 @@ HEADLINE_LAUNCH = {"n_slabs": 0, "hub_nodes": 2048}
 # WRITE_SIZE, summed over the k_sweep dispatches of the profiled run, divided
 # by their count, and scaled by the ratio of bytes to counter bytes that the
 # same counters give for a plain copy of known size), per workload, valid for
-# the kernel source with the given SHA-256 at the given grid and hub count
-# only.
+# the kernel source with the given SHA-256 at the given grid, hub count and
+# own arc buffer only.
 TRAFFIC = {
-    "serve-chunglu-n2m": {"slabs": 1280, "hub_nodes": 2048,
+    "serve-chunglu-n2m": {"slabs": 1280, "hub_nodes": 2048, "arc_cap": 262144,
                           "sweep_sha256": "eb1b3110af77d001792238426aa9efaf25b73f767fd5394216d6e61f4bda998c",
                           "fetch_bytes_per_launch": 1.1070e+13, "write_bytes_per_launch": 9.1544e+11},
-    "mid-chunglu-n50k": {"slabs": 2880, "hub_nodes": 0,
+    "mid-chunglu-n50k": {"slabs": 2880, "hub_nodes": 0, "arc_cap": 262144,
                          "sweep_sha256": "eb1b3110af77d001792238426aa9efaf25b73f767fd5394216d6e61f4bda998c",
                          "fetch_bytes_per_launch": 4.9425e+11, "write_bytes_per_launch": 7.8702e+10},
 }
@@ -122,7 +122,7 @@ def hbm_frac(t, c):
 def traffic_of(workload, launch):
     tr = TRAFFIC.get(workload)
     if (not tr or tr["sweep_sha256"] != sha256(SWEEP_SRC) or tr["slabs"] != launch["n_slabs"]
-            or tr["hub_nodes"] != launch["hub_nodes"]):
+            or tr["hub_nodes"] != launch["hub_nodes"] or tr["arc_cap"] != launch["arc_cap"]):
         return None
     return tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
 
@@ -373,11 +373,13 @@ def distances(gg, torch, seed, r=256, og=None):
     return out
 
 
-def serve(gg, G, torch, n_req=24, rate=50.0, seed=4002, workload_name=MID):
+def serve(gg, G, torch, n_req=24, rate=50.0, seed=4002, workload_name=MID, deadline_s=0.0):
     """Poisson arrivals at `rate` req/s; each request a random window of
     5-100% of the span, a uniform optimality and eps in {0.01, 0.005}.
     Latencies are reported over every finished request (a request that fails
-    finishes too) and over the completed ones, with their counts."""
+    finishes too) and over the completed ones, with their counts.  With a
+    deadline, requests still running deadline_s after the first arrival are
+    counted as unfinished (they fail when the graph is destroyed)."""
     import numpy as np
     from synthgen import request_stream
     reqs = request_stream(n_req, rate, int(G.t.min()), int(G.t.max()), seed)
@@ -389,8 +391,13 @@ def serve(gg, G, torch, n_req=24, rate=50.0, seed=4002, workload_name=MID):
 
     def waiter(i, tk):
         ok = True
+        res = None
         try:
-            res = tk.poll(timeout_ms=-1)
+            while res is None:
+                if deadline_s > 0 and time.perf_counter() - t_start > deadline_s:
+                    log("request %d unfinished at the deadline" % i)
+                    return
+                res = tk.poll(timeout_ms=1000 if deadline_s > 0 else -1)
         except Exception:  # noqa: BLE001 - a failed request finishes too (saturated fm counts)
             res = tk.result
             ok = False
@@ -415,8 +422,10 @@ def serve(gg, G, torch, n_req=24, rate=50.0, seed=4002, workload_name=MID):
         threads.append(th)
     for th in threads:
         th.join()
-    torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    if deadline_s <= 0:
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
     La = np.array([x for x in lat if x is not None])
     Lc = np.array([x for x, o in zip(lat, ok_) if x is not None and o])
 
@@ -424,7 +433,9 @@ def serve(gg, G, torch, n_req=24, rate=50.0, seed=4002, workload_name=MID):
         return float(np.percentile(L, q)) if L.size else None
 
     return {"requests": n_req, "offered_req_per_s": rate, "finished": int(La.size), "completed": int(Lc.size),
-            "failed": int(La.size - Lc.size), "wall_s": wall, "completed_req_per_s": Lc.size / wall,
+            "failed": int(La.size - Lc.size), "unfinished": n_req - int(La.size),
+            "deadline_s": deadline_s if deadline_s > 0 else None, "wall_s": wall,
+            "completed_req_per_s": Lc.size / wall,
             "pairs_per_s": sum(pairs) / wall,
             "p50_ms": pct(La, 50), "p99_ms": pct(La, 99), "latency_of": "every finished request (failed ones too)",
             "p50_ms_completed": pct(Lc, 50), "p99_ms_completed": pct(Lc, 99),
@@ -566,6 +577,8 @@ def main():
     ap.add_argument("--serve-workload", default=MID)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-deadline", type=float, default=0.0,
+                    help="seconds after the first arrival at which running requests count as unfinished")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--batching", action="store_true",
                     help="only the batching workloads (n = 10^6 Algorithm 1, packed-256; prints {\"batching\": ...})")
@@ -597,8 +610,11 @@ def main():
         if args.serve_workload == WORKLOAD:
             gg.set_launch(**HEADLINE_LAUNCH)
         log("graph %s resident after %.1f s" % (args.serve_workload, time.perf_counter() - t0))
-        print(json.dumps({"serve": serve(gg, G, torch, n_req=args.serve_requests, rate=args.serve_rate,
-                                         seed=args.seed + 2000, workload_name=args.serve_workload)}), flush=True)
+        out = serve(gg, G, torch, n_req=args.serve_requests, rate=args.serve_rate, seed=args.seed + 2000,
+                    workload_name=args.serve_workload, deadline_s=args.serve_deadline)
+        print(json.dumps({"serve": out}), flush=True)
+        # requests still running fail here (the graph is destroyed)
+        del gg
         return
     t0 = time.perf_counter()
     G = workload(WORKLOAD)
