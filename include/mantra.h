@@ -305,11 +305,15 @@ typedef struct {
     int32_t n_slabs;      /* persistent workgroups per launch, each one pair at a
                              time (0: as many as fit the device) */
     int64_t arc_cap;      /* appearance-DAG arc records of each workgroup's own
-                             buffer (0: 2^18, at most one per edge of the graph);
+                             buffer (0: 2^18, or up to 2^20 where the grid the
+                             device keeps resident still fits half of the slab
+                             budget with it; at most one per edge of the graph);
                              a pair with more takes chunks of 2^18 arcs from a
                              pool the launch shares (the rest of the slab
-                             budget), and a pair that finds none free is re-run
-                             after the launch with room for every edge */
+                             budget).  A pair that finds none free is re-run
+                             after the launch, alone with the other such pairs
+                             on the same pool, and if it again finds none, with
+                             room for every edge */
     int32_t order;        /* MANTRA_ORDER_*: the order pairs are handed out in */
     int32_t graph_rounds; /* 1: the progressive rounds of a blocking request
                              replay one captured HIP graph (counters, order,
@@ -322,6 +326,8 @@ typedef struct {
                              256-bit words (dependency estimator): MANTRA_WIDE_* */
     int32_t no_arc_chunks; /* 1: no shared arc chunks (every pair beyond its
                               workgroup's own buffer is re-run) */
+    int64_t arc_chunks;   /* > 0: at most this many shared arc chunks (0: the
+                             rest of the slab budget) */
 } mantra_launch_config;
 
 #define MANTRA_WIDE_NONE 0    /* reported as saturated */

@@ -88,7 +88,7 @@ class Graph:
                 "t_max": t1.value, "n_graphs": G.value}
 
     def set_launch(self, n_slabs=0, arc_cap=0, order="longest", graph_rounds=False, per_pair_launch=False,
-                   hub_nodes=0, wide_counts=1, no_arc_chunks=False):
+                   hub_nodes=0, wide_counts=1, no_arc_chunks=False, arc_chunks=0):
         """Launch configuration: scheduling (results do not change), and which
         saturated pairs are counted again in 256-bit words (wide_counts: 0
         none, 1 all but fm, 2 all)."""
@@ -96,7 +96,8 @@ class Graph:
                                 order=_lib.ORDER[order] if isinstance(order, str) else int(order),
                                 graph_rounds=1 if graph_rounds else 0,
                                 per_pair_launch=1 if per_pair_launch else 0, hub_nodes=int(hub_nodes),
-                                wide_counts=int(wide_counts), no_arc_chunks=1 if no_arc_chunks else 0)
+                                wide_counts=int(wide_counts), no_arc_chunks=1 if no_arc_chunks else 0,
+                                arc_chunks=int(arc_chunks))
         _lib.check(_lib._lib.mantra_set_launch(self._h, ctypes.byref(cfg)))
 
     def autotune(self, opt, sample_pairs=0, seed=0):

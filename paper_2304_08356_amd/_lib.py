@@ -44,7 +44,7 @@ class Request(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("n_slabs", I32), ("arc_cap", I64), ("order", I32), ("graph_rounds", I32), ("per_pair_launch", I32),
-                ("hub_nodes", I32), ("wide_counts", I32), ("no_arc_chunks", I32)]
+                ("hub_nodes", I32), ("wide_counts", I32), ("no_arc_chunks", I32), ("arc_chunks", I64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -374,7 +374,8 @@ static int64_t auto_chunks(const mantra_graph *g, int ns, int64_t cap) {
     if (xm == 0 || g->no_chunks) return 0;
     const size_t bud = pool_budget(g), slabs = (size_t)ns * slab_bytes(g, cap);
     const int64_t fit = bud > slabs ? (int64_t)((bud - slabs) / kChunkBytes) : 0;
-    return std::min<int64_t>(fit, (int64_t)ns * xm);
+    const int64_t n = std::min<int64_t>(fit, (int64_t)ns * xm);
+    return g->max_chunks > 0 ? std::min<int64_t>(n, g->max_chunks) : n;
 }
 
 static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap, int64_t nchunks) {
@@ -663,6 +664,42 @@ int run_sweep(mantra_graph *g, const LaunchSpec &sp, SweepOut &o, RoundGraph *rg
     u64 st1[kStats];
     HIPCHK(hipMemcpy(st1, g->dstats, sizeof(u64) * kStats, hipMemcpyDeviceToHost));
     if ((rc = stamps_after(g, g->pool, st1))) return rc;
+    if (nretry > 0 && g->pool.nchunks > 0 && !g->per_pair) {
+        // pairs that found no free shared chunk run again on the same pool,
+        // alone: every chunk is free again, and they are few
+        o.reduced = false;
+        std::vector<int32_t> q((size_t)nretry + 1);
+        HIPCHK(hipMemcpy(q.data(), g->dretry, sizeof(int32_t) * (nretry + 1), hipMemcpyDeviceToHost));
+        int32_t *dq = nullptr;
+        HIPCHK(dalloc(&dq, (size_t)nretry));
+        HIPCHK(hipMemcpy(dq, q.data() + 1, sizeof(int32_t) * nretry, hipMemcpyHostToDevice));
+        if ((rc = stamps_before(g, g->pool, nretry))) { hipFree(dq); return rc; }
+        HIPCHK(mantra_launch_clear(g->dwork, (u32 *)g->dretry, nullptr, g->dstats, g->st));  // keeps the
+        a.sl = g->pool.view();                                                                  // multiword list
+        a.npairs = nretry;
+        a.npairs_dev = nullptr;
+        a.qbase = 0;
+        a.pq = dq;
+        const int nsr = (int)std::min<int64_t>(std::min<int64_t>(nretry, g->pool.nslabs), g->pool.nchunks);
+        HIPCHK(hipEventRecord(g->ev0, g->st));
+        HIPCHK(launch_sweep(a, sp.mode, nsr, lb, g->st));
+        HIPCHK(hipEventRecord(g->ev1, g->st));
+        HIPCHK(hipStreamSynchronize(g->st));
+        HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+        o.ms += ms;
+        o.launches += 1;
+        u64 st2[kStats];
+        HIPCHK(hipMemcpy(st2, g->dstats, sizeof(u64) * kStats, hipMemcpyDeviceToHost));
+        if ((rc = stamps_after(g, g->pool, st2))) { hipFree(dq); return rc; }
+        for (int i = 0; i < 16; ++i)
+            if ((i != 5 && i < 9) || (i >= 14 && i < 18)) st1[i] += st2[i];
+        // the ones still without room (the list holds their original slots)
+        // go to the next stage
+        int32_t n2 = 0;
+        HIPCHK(hipMemcpy(&n2, g->dretry, sizeof(int32_t), hipMemcpyDeviceToHost));
+        hipFree(dq);
+        nretry = n2;
+    }
     if (nretry > 0) {
         // pairs whose arcs overflowed get slabs that hold every edge of the
         // graph, as many as a fifth of device memory allows
@@ -1212,6 +1249,7 @@ static int autotune(mantra_graph *g, mantra_opt opt, int64_t sample, uint64_t se
         best->n_slabs = best_slabs;
         best->arc_cap = own_cap(g);
         best->no_arc_chunks = g->no_chunks;
+        best->arc_chunks = g->max_chunks;
         best->order = best_order;
         best->graph_rounds = g->graph_rounds;
         best->per_pair_launch = g->per_pair;
@@ -1280,18 +1318,21 @@ int mantra_graph_info(const mantra_graph *g, int32_t *n, int64_t *m_unique, int6
 
 int mantra_set_launch(mantra_graph *g, const mantra_launch_config *cfg) {
     if (!g || !cfg) return fail(MANTRA_E_INVALID, "graph or config is NULL");
-    if (cfg->n_slabs < 0 || cfg->arc_cap < 0) return fail(MANTRA_E_INVALID, "negative launch setting");
+    if (cfg->n_slabs < 0 || cfg->arc_cap < 0 || cfg->arc_chunks < 0)
+        return fail(MANTRA_E_INVALID, "negative launch setting");
     if (cfg->order != MANTRA_ORDER_LONGEST_FIRST && cfg->order != MANTRA_ORDER_DRAWN)
         return fail(MANTRA_E_INVALID, "unknown pair order %d", cfg->order);
     if (cfg->hub_nodes < 0 || cfg->hub_nodes > 4096) return fail(MANTRA_E_INVALID, "hub_nodes outside 0..4096");
     if (cfg->wide_counts < MANTRA_WIDE_NONE || cfg->wide_counts > MANTRA_WIDE_ALL)
         return fail(MANTRA_E_INVALID, "unknown wide_counts %d", cfg->wide_counts);
     std::lock_guard<std::mutex> lk(g->mu);
-    if (g->user_slabs != cfg->n_slabs || g->user_cap != cfg->arc_cap || g->no_chunks != (cfg->no_arc_chunks ? 1 : 0))
+    if (g->user_slabs != cfg->n_slabs || g->user_cap != cfg->arc_cap || g->no_chunks != (cfg->no_arc_chunks ? 1 : 0) ||
+        g->max_chunks != cfg->arc_chunks)
         g->pool.release();
     g->user_slabs = cfg->n_slabs;
     g->user_cap = cfg->arc_cap;
     g->no_chunks = cfg->no_arc_chunks ? 1 : 0;
+    g->max_chunks = cfg->arc_chunks;
     g->order_mode = cfg->order;
     g->graph_rounds = cfg->graph_rounds ? 1 : 0;
     g->per_pair = cfg->per_pair_launch ? 1 : 0;
@@ -1315,6 +1356,7 @@ int mantra_get_launch(const mantra_graph *g, mantra_launch_config *cfg) {
     cfg->n_slabs = auto_slabs(g);
     cfg->arc_cap = own_cap(g);
     cfg->no_arc_chunks = g->no_chunks;
+    cfg->arc_chunks = g->max_chunks;
     cfg->order = g->order_mode;
     cfg->graph_rounds = g->graph_rounds;
     cfg->per_pair_launch = g->per_pair;

@@ -150,6 +150,7 @@ struct mantra_graph {
     int user_slabs = 0;
     int64_t user_cap = 0;
     int no_chunks = 0;              // no shared arc chunks (launch option)
+    int64_t max_chunks = 0;         // > 0: at most this many shared arc chunks (launch option)
     int order_mode = MANTRA_ORDER_LONGEST_FIRST;
     int hub_nodes = 0;              // forward state of nodes below this id in LDS
     int wide_mode = MANTRA_WIDE_NOT_FM;  // which saturated pairs take the multiword path

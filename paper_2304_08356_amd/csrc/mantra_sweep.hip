@@ -887,22 +887,26 @@ __device__ void forward(KArgs &a, const Pair &P, const Slab &S, u32 *bm, const H
         // pfm: a node's state is final at its first arrival, so an edge
         // whose head was reached before the batch can neither commit nor lie
         // on an optimal walk (its whole run is dead); its tail needs no load.
-        bool ru, rv;
+        bool ru, rv, tagm = false;
         if (GBM) {
-            if (!pref) {
-                // loaded now: complete, no patch
-                bu = in ? bm_word<GBM>(bm, u) : 0u;
-                bv = in ? bm_word<GBM>(bm, v) : 0u;
-                pu = false; pv = false;
+            if (pref) {
+                ru = ((bu >> (u & 31)) & 1u) || pu;
+                rv = ((bv >> (v & 31)) & 1u) || pv;
+            } else {
+                // no words loaded ahead (a pair's first batch, or the batch
+                // after a long tick): every lane loads its nodes' state words,
+                // whose pair tag (hub nodes: hops kHInf) tells whether the
+                // node was reached -- one round trip instead of two
+                tagm = true;
+                ru = in;
+                rv = in;
             }
-            ru = ((bu >> (u & 31)) & 1u) || pu;
-            rv = ((bv >> (v & 31)) & 1u) || pv;
         } else {
             ru = in && rch_test<GBM>(bm, u);
             rv = in && rch_test<GBM>(bm, v);
         }
         pref = false;
-        const bool dead = opt == OPT_PFM && in && rv;
+        const bool dead = opt == OPT_PFM && in && rv && !tagm;
         const bool rt = in && !dead && ru;
         const bool hr = rs && rv;
         u64 thu = 0, thv = 0, su = 0, sv = 0;

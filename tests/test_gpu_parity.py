@@ -165,18 +165,21 @@ def test_duplicates_and_validation(lib):
 
 def test_arc_chunks_and_retry(tiny_workload):
     """Pairs whose DAG arcs exceed the workgroup's own buffer take chunks of
-    the launch's shared arc pool (one launch); with no shared chunks they are
-    re-run after the launch with a full-window buffer (two launches).
-    Results are unchanged either way."""
+    the launch's shared arc pool (one launch).  With 4 shared chunks for 32
+    workgroups, the pairs that find none free run again after the launch on
+    the same pool, no more of them at once than there are chunks (two
+    launches).  With no shared chunks they are re-run with a full-window
+    buffer (two launches).  Results are unchanged in every case."""
     G, gg, og = tiny_workload
     S, Z = oracle.draw_pairs(11, 0, G.n, 0, 300)
     try:
-        for no_chunks, launches in ((False, 1), (True, 2)):
-            gg.set_launch(n_slabs=32, arc_cap=64, no_arc_chunks=no_chunks)
-            assert gg.get_launch()["arc_cap"] == 64 and gg.get_launch()["no_arc_chunks"] == int(no_chunks)
-            compare_pairs(gg, og, "sh", S, Z, ctx="chunks%d" % no_chunks)
-            assert gg.last_timing()["launches"] == launches, no_chunks
-            compare_pairs(gg, og, "fm", S, Z, ctx="chunks-fm%d" % no_chunks)
+        for no_chunks, nch, launches in ((False, 0, 1), (False, 4, 2), (True, 0, 2)):
+            gg.set_launch(n_slabs=32, arc_cap=64, no_arc_chunks=no_chunks, arc_chunks=nch)
+            L = gg.get_launch()
+            assert L["arc_cap"] == 64 and L["no_arc_chunks"] == int(no_chunks) and L["arc_chunks"] == nch
+            compare_pairs(gg, og, "sh", S, Z, ctx="chunks%d-%d" % (no_chunks, nch))
+            assert gg.last_timing()["launches"] == launches, (no_chunks, nch)
+            compare_pairs(gg, og, "fm", S, Z, ctx="chunks-fm%d-%d" % (no_chunks, nch))
     finally:
         gg.set_launch(0, 0)
 
