@@ -477,6 +477,51 @@ def mid_sections(args, pk, torch):
         out["rtb"] = rtb_step(gg, torch, args.seed)
     if not args.no_distances:
         out["distances"] = distances(gg, torch, args.seed, og=og)
+    if og is not None:
+        out["cpu_baseline"] = cpu_baseline(og, G.n, args.seed, OPT, t_budget=15.0)
+        log("mid cpu_baseline: %s" % json.dumps(out["cpu_baseline"]))
+    return out
+
+
+def tiny_section(args, pk, torch):
+    """The plain method on tiny-uniform-n100 (n = 100, |E| = 2,000): exact
+    all-pairs sh (9,900 pairs) and 500 sampled pairs on the GPU, and the
+    oracle on the same all pairs on every host thread and on one."""
+    import numpy as np
+    from synthgen import workload
+    G = workload("tiny-uniform-n100")
+    gg = pk.Graph.of(G)
+    n = G.n
+    S = np.array([s for s in range(n) for z in range(n) if s != z], dtype=np.int32)
+    Z = np.array([z for s in range(n) for z in range(n) if s != z], dtype=np.int32)
+    gg.count_pairs("sh", S[:64], Z[:64])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gg.count_pairs("sh", S, Z)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gg.run("sh", fixed_r=500, seed=args.seed, c=C, edges=True)
+    torch.cuda.synchronize()
+    t_500 = time.perf_counter() - t0
+    out = {"workload": "tiny-uniform-n100", "n": n, "edges": G.m, "optimality": "sh",
+           "all_pairs": int(S.size), "all_pairs_s": t_all, "all_pairs_per_s": S.size / t_all,
+           "sampled_500_s": t_500}
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Graph.of(G)
+        th = host_threads()
+        t0 = time.perf_counter()
+        oracle.accumulate(og, "sh", S, Z, mode=1, nthreads=th)
+        dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.accumulate(og, "sh", S, Z, mode=1, nthreads=1)
+        dt1 = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": S.size / dt, "unit": "pairs/s", "cores": th, "kind": "oracle",
+                               "cpu_model": cpu_model(), "value_1_thread": S.size / dt1,
+                               "sample": "all %d ordered pairs (records and node sums), %.2f s on %d threads, "
+                                         "%.2f s on one" % (S.size, dt, th, dt1)}
+    log("tiny: %s" % json.dumps(out))
     return out
 
 
@@ -669,6 +714,7 @@ def main():
     del gg, G, og
     if not args.no_mid:
         out["mid"] = mid_sections(args, pk, torch)
+        out["tiny"] = tiny_section(args, pk, torch)
     print(json.dumps(out), flush=True)
 
 
