@@ -56,11 +56,13 @@ MID_R = 20_000
 HBM_PEAK_GBS = 8000.0
 SWEEP_SRC = os.path.join(ROOT, "paper_2304_08356_amd", "csrc", "mantra_sweep.hip")
 
-# Launch configuration of the headline step: 2,048 hub nodes' state in LDS,
-# the grid the device keeps resident with that LDS (1,280 single-wave
-# workgroups), the rest automatic.  Taken from a sweep of grids and hub
-# counts on this graph; the autotuner itself would take minutes here.
-HEADLINE_LAUNCH = {"n_slabs": 0, "hub_nodes": 2048}
+# Launch configuration of the headline step: 2,048 hub nodes' state in LDS
+# and 1,100 single-wave workgroups (the device keeps 1,280 resident with that
+# LDS; fewer pairs in flight load the memory system less), the rest
+# automatic.  Taken from a sweep of grids and hub counts on this graph (sfm,
+# 4,096 pairs: 1,024-4,096 hubs, 800-1,793 workgroups); the autotuner itself
+# would take minutes here.
+HEADLINE_LAUNCH = {"n_slabs": 1100, "hub_nodes": 2048}
 
 # DRAM traffic of the sweep kernel (rocprofv3 --pmc FETCH_SIZE, then
 # WRITE_SIZE, summed over the k_sweep dispatches of the profiled run, divided
