@@ -71,12 +71,12 @@ HEADLINE_LAUNCH = {"n_slabs": 1100, "hub_nodes": 2048}
 # the kernel source with the given SHA-256 at the given grid, hub count and
 # own arc buffer only.
 TRAFFIC = {
-    "serve-chunglu-n2m": {"slabs": 1280, "hub_nodes": 2048, "arc_cap": 262144,
-                          "sweep_sha256": "eb1b3110af77d001792238426aa9efaf25b73f767fd5394216d6e61f4bda998c",
-                          "fetch_bytes_per_launch": 1.1070e+13, "write_bytes_per_launch": 9.1544e+11},
-    "mid-chunglu-n50k": {"slabs": 2880, "hub_nodes": 0, "arc_cap": 262144,
-                         "sweep_sha256": "eb1b3110af77d001792238426aa9efaf25b73f767fd5394216d6e61f4bda998c",
-                         "fetch_bytes_per_launch": 4.9425e+11, "write_bytes_per_launch": 7.8702e+10},
+    "serve-chunglu-n2m": {"slabs": 1100, "hub_nodes": 2048, "arc_cap": 1040577,
+                          "sweep_sha256": "0d36c97e6b258bdd124064d52e060c30ff5d2d5633625e8a1aee9d9f4071ed25",
+                          "fetch_bytes_per_launch": 1.0628e+13, "write_bytes_per_launch": 9.1761e+11},
+    "mid-chunglu-n50k": {"slabs": 2880, "hub_nodes": 0, "arc_cap": 815414,
+                         "sweep_sha256": "0d36c97e6b258bdd124064d52e060c30ff5d2d5633625e8a1aee9d9f4071ed25",
+                         "fetch_bytes_per_launch": 4.9429e+11, "write_bytes_per_launch": 7.8774e+10},
 }
 
 
