@@ -73,13 +73,13 @@ HEADLINE_LAUNCH = {"n_slabs": 0, "hub_nodes": 2048}
 # WRITE_SIZE, summed over the k_sweep dispatches of the profiled run, divided
 # by their count, and scaled by the ratio of bytes to counter bytes that the
 # same counters give for a plain copy of known size), per workload, valid for
-# the kernel source with the given SHA-256 at the given grid, hub count and
-# own arc buffer only.
+# the kernel source with the given SHA-256 at the given grid, hub count, own
+# arc buffer and pairs per launch only.
 TRAFFIC = {
-    "serve-chunglu-n2m": {"slabs": 1100, "hub_nodes": 2048, "arc_cap": 1040577,
+    "serve-chunglu-n2m": {"slabs": 1280, "hub_nodes": 2048, "arc_cap": 1040577, "pairs_per_launch": 8192,
                           "sweep_sha256": "0d36c97e6b258bdd124064d52e060c30ff5d2d5633625e8a1aee9d9f4071ed25",
-                          "fetch_bytes_per_launch": 1.0628e+13, "write_bytes_per_launch": 9.1761e+11},
-    "mid-chunglu-n50k": {"slabs": 2880, "hub_nodes": 0, "arc_cap": 815414,
+                          "fetch_bytes_per_launch": 2.2094e+13, "write_bytes_per_launch": 1.8402e+12},
+    "mid-chunglu-n50k": {"slabs": 2880, "hub_nodes": 0, "arc_cap": 815414, "pairs_per_launch": 20000,
                          "sweep_sha256": "0d36c97e6b258bdd124064d52e060c30ff5d2d5633625e8a1aee9d9f4071ed25",
                          "fetch_bytes_per_launch": 4.9429e+11, "write_bytes_per_launch": 7.8774e+10},
 }
@@ -126,10 +126,11 @@ def hbm_frac(t, c):
     return algorithmic_bytes(t, c) / (t["sweep_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
 
 
-def traffic_of(workload, launch):
+def traffic_of(workload, launch, pairs):
     tr = TRAFFIC.get(workload)
     if (not tr or tr["sweep_sha256"] != sha256(SWEEP_SRC) or tr["slabs"] != launch["n_slabs"]
-            or tr["hub_nodes"] != launch["hub_nodes"] or tr["arc_cap"] != launch["arc_cap"]):
+            or tr["hub_nodes"] != launch["hub_nodes"] or tr["arc_cap"] != launch["arc_cap"]
+            or tr["pairs_per_launch"] != pairs):
         return None
     return tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
 
@@ -156,11 +157,11 @@ def timed_steps(gg, torch, opt, r, steps, warmup, seed, c=C):
     return tot, wall, bal / max(tot["sweep_ms"], 1e-9)
 
 
-def roofline(tot, workload, launch, kernel):
+def roofline(tot, workload, launch, kernel, pairs):
     kern_ms = tot["sweep_ms"] / max(1, tot["launches"])
     abytes = algorithmic_bytes(tot, C) / max(1, tot["launches"])
     achieved = abytes / (kern_ms / 1e3) / 1e9
-    traffic = traffic_of(workload, launch)
+    traffic = traffic_of(workload, launch, pairs)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
             "algorithmic_bytes_per_launch": abytes, "sweep_ms_per_launch": kern_ms,
@@ -467,7 +468,7 @@ def mid_sections(args, pk, torch):
            "steps": steps, "pairs_per_s": MID_R * steps / wall, "ms_per_step": wall * 1e3 / steps,
            "temporal_edges_per_s": tot["window_edges"] / wall, "mean_window_edges": tot["window_edges"] / (MID_R * steps),
            "mean_arcs": tot["arcs"] / (MID_R * steps), "grid_balance": bal, "launch": tuned,
-           "roofline": roofline(tot, MID, tuned, "mantra::k_sweep<0, false> (LDS bitmap)")}
+           "roofline": roofline(tot, MID, tuned, "mantra::k_sweep<0, false> (LDS bitmap)", MID_R)}
     log("mid: %s" % json.dumps(out))
     if not args.no_forms:
         out["forms"] = forms(gg, torch, args.seed, tuned)
@@ -702,7 +703,8 @@ def main():
         "launches_per_step": tot["launches"] / args.steps,
         "grid_balance": bal,
         "launch": tuned,
-        "roofline": roofline(tot, WORKLOAD, tuned, "mantra::k_sweep<0, true> (reached set in global memory)"),
+        "roofline": roofline(tot, WORKLOAD, tuned, "mantra::k_sweep<0, true> (reached set in global memory)",
+                             R_PER_STEP),
     }
     tot_s, wall_s, bal_s = timed_steps(gg, torch, OPT, R_SMALL, 3, 0, args.seed)
     out["steps_of_%d_pairs" % R_SMALL] = {
