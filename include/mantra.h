@@ -125,8 +125,8 @@ int mantra_count_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t1, 
  * counters, the pairs and the records -- lives in one device array of the
  * library, 256 MiB, that each GPU holds from the library's load until the
  * process ends.  A workgroup holds an arc record for every edge of the
- * graph, so the graph must fit: one workgroup needs 28 B per node (+1 B per
- * node above 65,536 nodes) + 36 B per edge of the longest tick + 32 B per
+ * graph, so the graph must fit: one workgroup needs 28 B per node (+1 bit
+ * per node above 65,536 nodes) + 32 B per edge of the longest tick + 32 B per
  * edge, and the pairs 36 B each; beyond the array MANTRA_E_TOO_LARGE.  Pairs
  * whose counts pass 2^64 carry MANTRA_REC_OVERFLOW (no 256-bit re-count: that
  * path allocates).  Calls on one GPU share the array and would race; the
