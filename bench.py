@@ -136,17 +136,19 @@ def traffic_of(workload, launch, pairs):
 
 
 def timed_steps(gg, torch, opt, r, steps, warmup, seed, c=C):
-    """warmup + steps fixed samples of r pairs (node and edge sums); totals of
-    the timed steps."""
+    """warmup + steps fixed samples of r pairs (node and edge sums, written to
+    the same host arrays every step); totals of the timed steps."""
+    import numpy as np
+    out = (np.zeros(gg.n), np.zeros(gg.m_input))
     for i in range(warmup):
-        gg.run(opt, fixed_r=r, seed=seed + 1000 + i, c=c, edges=True)
+        gg.run(opt, fixed_r=r, seed=seed + 1000 + i, c=c, edges=True, out=out)
     torch.cuda.synchronize()
     tot = {"sweep_ms": 0.0, "launches": 0, "window_edges": 0, "arcs": 0, "touched_nodes": 0,
            "touched_edges": 0}
     bal = 0.0
     t0 = time.perf_counter()
     for k in range(steps):
-        _, _, res = gg.run(opt, fixed_r=r, seed=seed + k, c=c, edges=True)
+        _, _, res = gg.run(opt, fixed_r=r, seed=seed + k, c=c, edges=True, out=out)
         t = gg.last_timing()
         for key in tot:
             tot[key] += t[key]

@@ -165,9 +165,20 @@ class Graph:
                                                         _p(rec), _p(nf), _p(ef)))
         return rec, nf, ef
 
-    def _request(self, opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges, trk=False, rtb=False):
-        node_bc = np.zeros(self.n, dtype=np.float64)
-        edge_bc = np.zeros(self.m_input, dtype=np.float64) if edges else None
+    @staticmethod
+    def _out_array(a, size, what):
+        if a is None:
+            return np.zeros(size, dtype=np.float64)
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.ndim == 1 and a.size == size
+                and a.flags.c_contiguous and a.flags.writeable):
+            raise ValueError("%s must be a writeable contiguous float64 array of %d values" % (what, size))
+        return a
+
+    def _request(self, opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges, trk=False, rtb=False,
+                 out=None):
+        node_out, edge_out = out if out is not None else (None, None)
+        node_bc = self._out_array(node_out, self.n, "node output")
+        edge_bc = self._out_array(edge_out, self.m_input, "edge output") if edges else None
         flags = (F_EDGE_BC if edges else 0) | (F_TRK if trk else 0) | (F_RTB if rtb else 0)
         rq = Request(opt=_opt(opt), t0=int(t0), t1=int(t1), eps=float(eps), delta=float(delta),
                      seed=int(seed), c=int(c), s1=int(s1), max_samples=int(max_samples), fixed_r=int(fixed_r),
@@ -175,13 +186,16 @@ class Graph:
         return rq, node_bc, edge_bc
 
     def run(self, opt, eps=0.01, delta=0.1, seed=0, c=25, t0=0, t1=T_MAX, s1=0, max_samples=0, fixed_r=0,
-            edges=False, raise_on_error=True, trk=False, rtb=False):
+            edges=False, raise_on_error=True, trk=False, rtb=False, out=None):
         """Algorithm 1 (or a fixed sample of ``fixed_r`` pairs), with the ob
         estimator, the TRK estimator (trk=True) or the RTB estimator
         (rtb=True, samples are sources): returns (node_bc, edge_bc or None,
-        result dict)."""
+        result dict).  ``out = (node_array, edge_array or None)`` gives the
+        float64 arrays the estimates are written to (reused across calls;
+        a call that fails other than by overflow leaves them as they were);
+        by default fresh ones are allocated."""
         rq, node_bc, edge_bc = self._request(opt, eps, delta, seed, c, t0, t1, s1, max_samples, fixed_r, edges,
-                                             trk, rtb)
+                                             trk, rtb, out)
         res = Result()
         rc = _lib._lib.mantra_run(self._h, ctypes.byref(rq), ctypes.byref(res))
         if raise_on_error:

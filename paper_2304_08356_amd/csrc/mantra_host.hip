@@ -227,6 +227,14 @@ static int build_graph(int32_t G, const int32_t *node_count, const int64_t *edge
     HIPCHK(dalloc(&g->dseg_noff, G + 1));
     HIPCHK(dalloc(&g->dperm, ntot));
     HIPCHK(hipMemcpy(g->dperm, g->perm.data(), sizeof(int32_t) * ntot, hipMemcpyHostToDevice));
+    {
+        // internal edge ids are below m < 2^32
+        std::vector<uint32_t> ik((size_t)(g->m_in ? g->m_in : 1));
+        for (int64_t i = 0; i < g->m_in; ++i) ik[(size_t)i] = (uint32_t)g->in2k[(size_t)i];
+        HIPCHK(dalloc(&g->din2k, g->m_in));
+        HIPCHK(hipMemcpy(g->din2k, ik.data(), sizeof(uint32_t) * ik.size(), hipMemcpyHostToDevice));
+    }
+    HIPCHK(dalloc(&g->dout, kOutChunk));
     HIPCHK(hipMemcpy(g->dU, U.data(), sizeof(int32_t) * mu, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->dV, V.data(), sizeof(int32_t) * mu, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->dT, T.data(), sizeof(int32_t) * mu, hipMemcpyHostToDevice));
@@ -909,20 +917,49 @@ static void norm_window(mantra_request &rq) {
     if (rq.t1 < rq.t0) { rq.t0 = 0; rq.t1 = INT32_MAX; }
 }
 
-static int finish_outputs(mantra_graph *g, const mantra_request &rq, Acc &acc, int64_t r) {
-    std::vector<double> hb((size_t)g->n_total);
-    HIPCHK(hipMemcpyAsync(hb.data(), acc.B, sizeof(double) * g->n_total, hipMemcpyDeviceToHost, g->st));
-    std::vector<double> he;
-    if (rq.edge_bc && acc.E) {
-        he.resize((size_t)g->m);
-        HIPCHK(hipMemcpyAsync(he.data(), acc.E, sizeof(double) * g->m, hipMemcpyDeviceToHost, g->st));
+// Outputs in the caller's order: rows of `nin` values (input node or edge
+// order), value i of row q being src[q * nsrc + idx[i]] / r, the value of the
+// internal node or edge that input id i became, divided by the sample size
+// (r = 0: the value itself).  This launch writes the flattened outputs
+// o .. o + len - 1 to dst[0 .. len - 1], one thread per output.
+template <typename I>
+__global__ void __launch_bounds__(256) k_out(const double *src, const I *idx, int64_t nin, int64_t nsrc, int64_t o,
+                                             int64_t len, double r, double *dst) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+        const int64_t j = o + i;
+        const int64_t q = j < nin ? 0 : j / nin;
+        const double x = src[q * nsrc + idx[j - q * nin]];
+        dst[i] = r > 0 ? x / r : x;
     }
-    HIPCHK(hipStreamSynchronize(g->st));
-    double rr = (double)r;
-    for (int64_t v = 0; v < g->n_total; ++v) rq.node_bc[g->iperm[(size_t)v]] = r ? hb[(size_t)v] / rr : 0.0;
-    if (rq.edge_bc && acc.E)
-        for (int64_t i = 0; i < g->m_in; ++i) rq.edge_bc[i] = r ? he[(size_t)g->in2k[(size_t)i]] / rr : 0.0;
+}
+
+// host[q * nin + i] = src[q * nsrc + idx[i]] / r for rows q < rows, written on
+// the device in the caller's order and copied out a piece at a time through
+// the graph's staging buffer (callers hold the graph's lock)
+template <typename I>
+static int copy_out(mantra_graph *g, double *host, const double *src, const I *idx, int64_t nin, int64_t nsrc,
+                    int64_t rows, double r) {
+    const int64_t n = nin * rows;
+    for (int64_t o = 0; o < n; o += kOutChunk) {
+        const int64_t len = std::min(kOutChunk, n - o);
+        const int blocks = (int)std::min<int64_t>((len + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_out<I>, dim3(blocks), dim3(256), 0, g->st, src, idx, nin, nsrc, o, len, r, g->dout);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(host + o, g->dout, sizeof(double) * len, hipMemcpyDeviceToHost, g->st));
+    }
     return MANTRA_OK;
+}
+
+static int finish_outputs(mantra_graph *g, const mantra_request &rq, Acc &acc, int64_t r) {
+    if (r <= 0) {
+        std::fill(rq.node_bc, rq.node_bc + g->n_total, 0.0);
+        if (rq.edge_bc && acc.E) std::fill(rq.edge_bc, rq.edge_bc + g->m_in, 0.0);
+        return MANTRA_OK;
+    }
+    int rc = copy_out(g, rq.node_bc, acc.B, g->dperm, g->n_total, g->n_total, 1, (double)r);
+    if (!rc && rq.edge_bc && acc.E) rc = copy_out(g, rq.edge_bc, acc.E, g->din2k, g->m_in, g->m, 1, (double)r);
+    HIPCHK(hipStreamSynchronize(g->st));
+    return rc;
 }
 
 size_t req_mem_bytes(const mantra_graph *g, const mantra_request &rq) {
@@ -1296,6 +1333,7 @@ void mantra_graph_destroy(mantra_graph *g) {
     hipFree(g->dwide);
     hipFree(g->dU); hipFree(g->dV); hipFree(g->dT); hipFree(g->dout_t); hipFree(g->din_t);
     hipFree(g->dout_off); hipFree(g->din_off); hipFree(g->dseg_eoff); hipFree(g->dseg_noff); hipFree(g->dperm);
+    hipFree(g->din2k); hipFree(g->dout);
     hipFree(g->dwork); hipFree(g->dstats); hipFree(g->dretry); hipFree(g->dpart); hipFree(g->dreqs);
     hipFree(g->dbucket); hipFree(g->dorder); hipFree(g->dhist); hipFree(g->dnp);
     if (g->ev0) hipEventDestroy(g->ev0);
@@ -1477,24 +1515,9 @@ static int explicit_pairs(mantra_graph *g, mantra_opt opt, int32_t t0, int32_t t
     timing_add(g, so);
     if (!rc) {
         if (hipMemcpy(out, drec, (size_t)r * 24, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(MANTRA_E_INTERNAL, "copy records");
-        if (!rc && node_f) {
-            std::vector<double> tmp((size_t)(r * g->n_total));
-            if (hipMemcpy(tmp.data(), dnf, sizeof(double) * r * g->n_total, hipMemcpyDeviceToHost) != hipSuccess)
-                rc = fail(MANTRA_E_INTERNAL, "copy node_f");
-            else
-                for (int64_t q = 0; q < r; ++q)
-                    for (int64_t v = 0; v < g->n_total; ++v)
-                        node_f[q * g->n_total + g->iperm[(size_t)v]] = tmp[(size_t)(q * g->n_total + v)];
-        }
-        if (!rc && edge_f) {
-            std::vector<double> tmp((size_t)(r * g->m));
-            if (hipMemcpy(tmp.data(), def, sizeof(double) * r * g->m, hipMemcpyDeviceToHost) != hipSuccess)
-                rc = fail(MANTRA_E_INTERNAL, "copy edge_f");
-            else
-                for (int64_t q = 0; q < r; ++q)
-                    for (int64_t i = 0; i < g->m_in; ++i)
-                        edge_f[q * g->m_in + i] = tmp[(size_t)(q * g->m + g->in2k[(size_t)i])];
-        }
+        if (!rc && node_f) rc = copy_out(g, node_f, dnf, g->dperm, g->n_total, g->n_total, r, 0.0);
+        if (!rc && edge_f) rc = copy_out(g, edge_f, def, g->din2k, g->m_in, g->m, r, 0.0);
+        if (!rc && hipStreamSynchronize(g->st) != hipSuccess) rc = fail(MANTRA_E_INTERNAL, "copy per-pair outputs");
     }
     cleanup();
     return rc;

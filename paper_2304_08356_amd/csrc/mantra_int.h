@@ -57,6 +57,9 @@ int fail(int code, const char *fmt, ...);
         }                                                                                 \
     } while (0)
 
+// outputs pass to the host in pieces of this many values
+constexpr int64_t kOutChunk = (int64_t)1 << 22;
+
 template <class T>
 static inline hipError_t dalloc(T **p, size_t count) {
     return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
@@ -140,6 +143,8 @@ struct mantra_graph {
     std::vector<int32_t> iperm; // internal id -> input id
     int32_t *dU = nullptr, *dV = nullptr, *dT = nullptr, *dout_t = nullptr, *din_t = nullptr,
             *dseg_noff = nullptr, *dperm = nullptr;
+    uint32_t *din2k = nullptr;      // [m_in] input edge index -> internal edge id
+    double *dout = nullptr;         // [kOutChunk] outputs in the caller's order, on their way to the host
     int64_t *dout_off = nullptr, *din_off = nullptr, *dseg_eoff = nullptr;
     hipStream_t st = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -311,6 +311,28 @@ def test_repeat_calls_identical(tiny_workload):
     assert ok, worst
 
 
+def test_output_arrays_reused(tiny_workload):
+    """Estimates written into caller-given arrays (every value overwritten,
+    whatever they held) equal those written into fresh ones (to the sums'
+    tolerance: FP64 atomics add the pairs' values in launch order)."""
+    G, gg, og = tiny_workload
+    a_n, a_e, _ = gg.run("sfm", fixed_r=300, seed=3, c=8, edges=True)
+    b_n, b_e, _ = gg.run("pfm", fixed_r=200, seed=5, c=8, edges=True)
+    out = (np.full(gg.n, np.nan), np.full(gg.m_input, np.nan))
+    for want_n, want_e, opt, r, seed in ((a_n, a_e, "sfm", 300, 3), (b_n, b_e, "pfm", 200, 5),
+                                         (a_n, a_e, "sfm", 300, 3)):
+        nb, eb, _ = gg.run(opt, fixed_r=r, seed=seed, c=8, edges=True, out=out)
+        assert nb is out[0] and eb is out[1]
+        assert np.all(np.isfinite(nb)) and np.all(np.isfinite(eb))
+        for got, want in ((nb, want_n), (eb, want_e)):
+            ok, worst = rel_close(got, want, rel=1e-12, abs_floor=1e-300)
+            assert ok, (opt, worst)
+    with pytest.raises(ValueError):
+        gg.run("sh", fixed_r=10, edges=True, out=(np.zeros(gg.n), np.zeros(gg.m_input - 1)))
+    with pytest.raises(ValueError):
+        gg.run("sh", fixed_r=10, out=(np.zeros(gg.n, dtype=np.float32), None))
+
+
 def test_launch_configs_same_results(lib):
     """Pair order, grid size and arc capacity change the schedule only:
     records are bit-identical and sums agree to 1e-12 under every launch
