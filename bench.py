@@ -72,16 +72,23 @@ HEADLINE_LAUNCH = {"n_slabs": 0, "hub_nodes": 2048}
 # DRAM traffic of the sweep kernel (rocprofv3 --pmc FETCH_SIZE, then
 # WRITE_SIZE, summed over the k_sweep dispatches of the profiled run, divided
 # by their count, and scaled by the ratio of bytes to counter bytes that the
-# same counters give for a plain copy of known size), per workload, valid for
-# the kernel source with the given SHA-256 at the given grid, hub count, own
-# arc buffer and pairs per launch only.
+# same counters give for a plain copy of known size), per workload and launch
+# configuration, valid for the kernel source with the given SHA-256 at the
+# given grid, hub count, own arc buffer and pairs per launch only.
 TRAFFIC = {
-    "serve-chunglu-n2m": {"slabs": 1280, "hub_nodes": 2048, "arc_cap": 1040577, "pairs_per_launch": 8192,
-                          "sweep_sha256": "0d36c97e6b258bdd124064d52e060c30ff5d2d5633625e8a1aee9d9f4071ed25",
-                          "fetch_bytes_per_launch": 2.2094e+13, "write_bytes_per_launch": 1.8402e+12},
-    "mid-chunglu-n50k": {"slabs": 2880, "hub_nodes": 0, "arc_cap": 815414, "pairs_per_launch": 20000,
-                         "sweep_sha256": "0d36c97e6b258bdd124064d52e060c30ff5d2d5633625e8a1aee9d9f4071ed25",
-                         "fetch_bytes_per_launch": 4.9429e+11, "write_bytes_per_launch": 7.8774e+10},
+    "serve-chunglu-n2m": [
+        {"slabs": 1280, "hub_nodes": 2048, "arc_cap": 1040577, "pairs_per_launch": 8192,
+         "sweep_sha256": "0d36c97e6b258bdd124064d52e060c30ff5d2d5633625e8a1aee9d9f4071ed25",
+         "fetch_bytes_per_launch": 2.2094e+13, "write_bytes_per_launch": 1.8402e+12},
+    ],
+    "mid-chunglu-n50k": [
+        {"slabs": 2880, "hub_nodes": 0, "arc_cap": 815414, "pairs_per_launch": 20000,
+         "sweep_sha256": "0d36c97e6b258bdd124064d52e060c30ff5d2d5633625e8a1aee9d9f4071ed25",
+         "fetch_bytes_per_launch": 4.9429e+11, "write_bytes_per_launch": 7.8774e+10},
+        {"slabs": 2688, "hub_nodes": 256, "arc_cap": 1048576, "pairs_per_launch": 20000,
+         "sweep_sha256": "0d36c97e6b258bdd124064d52e060c30ff5d2d5633625e8a1aee9d9f4071ed25",
+         "fetch_bytes_per_launch": 4.1898e+11, "write_bytes_per_launch": 7.5541e+10},
+    ],
 }
 
 
@@ -127,12 +134,13 @@ def hbm_frac(t, c):
 
 
 def traffic_of(workload, launch, pairs):
-    tr = TRAFFIC.get(workload)
-    if (not tr or tr["sweep_sha256"] != sha256(SWEEP_SRC) or tr["slabs"] != launch["n_slabs"]
-            or tr["hub_nodes"] != launch["hub_nodes"] or tr["arc_cap"] != launch["arc_cap"]
-            or tr["pairs_per_launch"] != pairs):
-        return None
-    return tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+    """The profiled entry for this workload, kernel source and launch, or None."""
+    sha = sha256(SWEEP_SRC)
+    for tr in TRAFFIC.get(workload, []):
+        if (tr["sweep_sha256"] == sha and tr["slabs"] == launch["n_slabs"] and tr["hub_nodes"] == launch["hub_nodes"]
+                and tr["arc_cap"] == launch["arc_cap"] and tr["pairs_per_launch"] == pairs):
+            return tr
+    return None
 
 
 def timed_steps(gg, torch, opt, r, steps, warmup, seed, c=C):
@@ -163,11 +171,12 @@ def roofline(tot, workload, launch, kernel, pairs):
     kern_ms = tot["sweep_ms"] / max(1, tot["launches"])
     abytes = algorithmic_bytes(tot, C) / max(1, tot["launches"])
     achieved = abytes / (kern_ms / 1e3) / 1e9
-    traffic = traffic_of(workload, launch, pairs)
+    tr = traffic_of(workload, launch, pairs)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
-            "algorithmic_bytes_per_launch": abytes, "sweep_ms_per_launch": kern_ms,
-            "traffic_slabs": TRAFFIC[workload]["slabs"] if traffic is not None else None}
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"] if tr else None,
+            "kernel": kernel, "algorithmic_bytes_per_launch": abytes, "sweep_ms_per_launch": kern_ms,
+            "traffic_slabs": tr["slabs"] if tr else None}
 
 
 class OracleOneThread(threading.Thread):
@@ -460,7 +469,7 @@ def mid_sections(args, pk, torch):
     log("%s resident" % MID)
     if args.mid_slabs > 0:
         # a fixed grid (profiling runs): no autotuner launches in the profile
-        gg.set_launch(n_slabs=args.mid_slabs, hub_nodes=0)
+        gg.set_launch(n_slabs=args.mid_slabs, hub_nodes=args.mid_hub)
         tuned = gg.get_launch()
     else:
         tuned = gg.autotune(OPT, sample_pairs=MID_R, seed=args.seed + 7)
@@ -641,6 +650,7 @@ def main():
                     help="fixed number of persistent workgroups for the headline step (profiling runs)")
     ap.add_argument("--mid-slabs", type=int, default=0,
                     help="fixed grid for the mid-size step instead of the autotuner's (profiling runs)")
+    ap.add_argument("--mid-hub", type=int, default=0, help="hub nodes of the fixed mid-size grid (with --mid-slabs)")
     ap.add_argument("--seed", type=int, default=2005)
     args = ap.parse_args()
     if args.gpus != 1:
