@@ -58,3 +58,19 @@ def test_no_device_gives_an_error_not_a_fallback(lib):
     import numpy as np
     with pytest.raises(MantraError):
         Graph(3, np.array([0, 1]), np.array([1, 2]), np.array([1, 2]))
+
+
+def test_output_array_checks():
+    """Caller-given output arrays must be writeable contiguous float64 of the
+    exact size; None means a fresh zeroed array."""
+    import numpy as np
+    import paper_2304_08356_amd as pk
+    a = np.zeros(5)
+    assert pk.Graph._out_array(a, 5, "x") is a
+    fresh = pk.Graph._out_array(None, 3, "x")
+    assert fresh.dtype == np.float64 and fresh.shape == (3,) and not fresh.any()
+    ro = np.zeros(5)
+    ro.setflags(write=False)
+    for bad in (np.zeros(4), np.zeros(5, dtype=np.float32), np.zeros((5, 1)), np.zeros(10)[::2], ro, [0.0] * 5):
+        with pytest.raises(ValueError):
+            pk.Graph._out_array(bad, 5, "x")
