@@ -395,12 +395,19 @@ static int pool_ensure(mantra_graph *g, SlabPool &p, int nslabs, int64_t cap, in
     p.nmax = nmax; p.cap = cap; p.gmax = gmax;
     size_t ns = (size_t)nslabs;
     const int64_t xm = xmax_of(g, cap), xwords = (nchunks + 31) / 32;
-    if (dalloc(&p.F, ns * nmax * 2) || dalloc(&p.N, ns * nmax) ||
-        dalloc(&p.AG, ns * (size_t)gmax * 2) || dalloc(&p.touched, ns * nmax) ||
-        dalloc(&p.arcs, ns * (size_t)cap * 4) || dalloc(&p.XS, ns * (size_t)gmax * 2) ||
-        dalloc(&p.hdr, ns * 4) || (node_bytes_per_slab(nmax) && dalloc(&p.BM, ns * node_bytes_per_slab(nmax))) ||
-        (nchunks > 0 && (dalloc(&p.xarcs, (size_t)nchunks * 4 * (size_t)kArcChunk) ||
-                         dalloc(&p.xfree, (size_t)xwords) || dalloc(&p.xtab, ns * (size_t)xm)))) {
+    // Allocation order: the shared chunks and the arc buffers first, the
+    // per-node state that the sweep gathers from last.  Measured on the 2M-node
+    // graph (fresh processes, 1,280 slabs): 4,846-4,882 ms per launch of 8,192
+    // sfm pairs this way against 5,272-5,372 ms with the per-node state
+    // allocated first.  The cause is not established: the arrays get other
+    // device addresses, and the state-first pool reallocated after a larger
+    // pool was freed ran 6-8% faster too.
+    if ((nchunks > 0 && (dalloc(&p.xarcs, (size_t)nchunks * 4 * (size_t)kArcChunk) ||
+                         dalloc(&p.xfree, (size_t)xwords) || dalloc(&p.xtab, ns * (size_t)xm))) ||
+        (node_bytes_per_slab(nmax) && dalloc(&p.BM, ns * node_bytes_per_slab(nmax))) || dalloc(&p.hdr, ns * 4) ||
+        dalloc(&p.XS, ns * (size_t)gmax * 2) || dalloc(&p.arcs, ns * (size_t)cap * 4) ||
+        dalloc(&p.touched, ns * nmax) || dalloc(&p.AG, ns * (size_t)gmax * 2) ||
+        dalloc(&p.N, ns * nmax) || dalloc(&p.F, ns * nmax * 2)) {
         p.release();
         (void)hipGetLastError();
         return fail(MANTRA_E_OOM, "slab pool: %d slabs x (%lld nodes, %lld arcs) + %lld arc chunks does not fit",
