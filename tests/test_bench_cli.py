@@ -25,3 +25,25 @@ def test_algorithmic_bytes():
     frac = bench.hbm_frac(t, 25)
     assert abs(frac - bench.algorithmic_bytes(t, 25) / 2e-3 / 1e9 / 8000.0) < 1e-15
     assert bench.hbm_frac(dict(t, sweep_ms=0.0), 25) is None
+
+
+def test_traffic_entries_match_launches():
+    """A profiled traffic figure is reported only for the kernel source it was
+    taken on and the exact launch (grid, hubs, own arc buffer, pairs): an
+    entry taken on another source of the kernel matches nothing."""
+    sha = bench.sha256(bench.SWEEP_SRC)
+    for workload, entries in bench.TRAFFIC.items():
+        assert entries, workload
+        for tr in entries:
+            launch = {"n_slabs": tr["slabs"], "hub_nodes": tr["hub_nodes"], "arc_cap": tr["arc_cap"]}
+            want = tr if tr["sweep_sha256"] == sha else None
+            assert bench.traffic_of(workload, launch, tr["pairs_per_launch"]) is want
+            for key, bad in (("n_slabs", tr["slabs"] + 1), ("hub_nodes", tr["hub_nodes"] + 1),
+                             ("arc_cap", tr["arc_cap"] - 1)):
+                assert bench.traffic_of(workload, dict(launch, **{key: bad}), tr["pairs_per_launch"]) is None
+            assert bench.traffic_of(workload, launch, tr["pairs_per_launch"] + 1) is None
+    assert bench.traffic_of("no-such-workload", {"n_slabs": 1, "hub_nodes": 0, "arc_cap": 1}, 1) is None
+    r = bench.roofline({"sweep_ms": 2.0, "launches": 1, "window_edges": 10, "arcs": 0, "touched_nodes": 0,
+                        "touched_edges": 0}, "no-such-workload", {"n_slabs": 1, "hub_nodes": 0, "arc_cap": 1},
+                       "k", 1)
+    assert r["traffic"] is None and r["traffic_slabs"] is None and abs(r["frac"] - 120 / 2e-3 / 1e9 / 8000.0) < 1e-15
